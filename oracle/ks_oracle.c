@@ -1,0 +1,487 @@
+/*
+ * ks_oracle.c -- plain, slow CPU oracle for CKKS hybrid key switching.
+ *
+ * TEST INFRASTRUCTURE ONLY (see ks_oracle.h).  Every reduction is a plain
+ * uint64 '%'; there is no Montgomery, Shoup or Barrett arithmetic, no lazy
+ * range, no fusion and no reordering beyond what each function's definition
+ * states.  The HIP library must never include or link this file.
+ *
+ * Readings of the paper taken here (the paper is silent on them):
+ *  - moduli: 2^30 - t*2N + 1 for t = 1, 2, ...; first K primes form P,
+ *    the next L+1 form Q (P > Q_j so the ModDown error stays small);
+ *  - psi: the smallest primitive 2N-th root of unity;
+ *  - evaluation domain: NTT(a)[j] = a(psi^(2*brv(j)+1));
+ *  - digits are the raw limbs (Sec. III-A decomposition); the gadget factor
+ *    lives in the key, [P]_m on the digit's own q-limbs and 0 elsewhere;
+ *  - basis conversion is the fast (approximate) one, with no correction,
+ *    in both ModUp P2 and ModDown P2;
+ *  - ModDown P4 computes (acc - w_hat) * [P^-1]_{q_i}; outputs canonical.
+ */
+#include "ks_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int g_fault = 0;
+void oracle_set_fault(int fault) { g_fault = fault; }
+/* Planted mistakes (for tests of the checks, never set otherwise):
+ *  1: ModUp P5 drops the last digit's contribution
+ *  2: ModDown P4 adds w_hat instead of subtracting it
+ *  3: ModUp P2 uses the wrong target constant (index off by one)
+ *  4: ModUp P3 bypass takes the limb from the neighbouring digit */
+
+/* ------------------------------------------------------------------ */
+/* integers                                                             */
+/* ------------------------------------------------------------------ */
+
+static uint32_t mulmod(uint32_t a, uint32_t b, uint32_t q) {
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) % q);
+}
+static uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) {
+  return (uint32_t)(((uint64_t)a + (uint64_t)b) % q);
+}
+static uint32_t submod(uint32_t a, uint32_t b, uint32_t q) {
+  return (uint32_t)(((uint64_t)a + (uint64_t)q - (uint64_t)(b % q)) % q);
+}
+
+uint32_t oracle_powmod(uint32_t b, uint64_t e, uint32_t q) {
+  uint64_t r = 1 % q, x = b % q;
+  while (e) {
+    if (e & 1) r = (r * x) % q;
+    x = (x * x) % q;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+/* q prime: a^(q-2) is the inverse of a (Fermat). */
+uint32_t oracle_invmod(uint32_t a, uint32_t q) { return oracle_powmod(a, (uint64_t)q - 2, q); }
+
+uint32_t oracle_bitrev(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+int oracle_is_prime(uint64_t n) {
+  if (n < 2) return 0;
+  for (uint64_t d = 2; d * d <= n; d++)
+    if (n % d == 0) return 0;
+  return 1;
+}
+
+int oracle_gen_primes(uint32_t log_n, uint32_t count, uint32_t *out) {
+  const uint64_t two_n = 2ull << log_n;
+  uint32_t found = 0;
+  for (uint64_t t = 1; found < count; t++) {
+    if (t * two_n >= (1ull << 29)) return -1; /* stay above 2^29 */
+    uint64_t c = (1ull << 30) - t * two_n + 1;
+    if (oracle_is_prime(c)) out[found++] = (uint32_t)c;
+  }
+  return 0;
+}
+
+int oracle_moduli(const oracle_params *p, uint32_t *out) {
+  uint32_t total = p->num_q + p->num_p;
+  uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * total);
+  if (!pr) return -1;
+  if (oracle_gen_primes(p->log_n, total, pr) != 0) { free(pr); return -1; }
+  for (uint32_t i = 0; i < p->num_q; i++) out[i] = pr[p->num_p + i];
+  for (uint32_t k = 0; k < p->num_p; k++) out[p->num_q + k] = pr[k];
+  free(pr);
+  return 0;
+}
+
+static uint32_t min_psi_search(uint32_t q, uint32_t log_n) {
+  const uint64_t n = 1ull << log_n;
+  for (uint32_t x = 2; x < q; x++)
+    if (oracle_powmod(x, n, q) == q - 1) return x;
+  return 0;
+}
+
+/* The search is slow for small N, so results are remembered per (q, log_n). */
+uint32_t oracle_min_psi(uint32_t q, uint32_t log_n) {
+  static uint32_t cq[512], cl[512], cv[512];
+  static unsigned used = 0;
+  for (unsigned i = 0; i < used; i++)
+    if (cq[i] == q && cl[i] == log_n) return cv[i];
+  uint32_t v = min_psi_search(q, log_n);
+  if (used < 512) { cq[used] = q; cl[used] = log_n; cv[used] = v; used++; }
+  return v;
+}
+
+/* ------------------------------------------------------------------ */
+/* NTT                                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Definition: evaluation of a(X) at psi^(2*brv(j)+1), by Horner's rule. */
+void oracle_ntt_direct(const uint32_t *a, uint32_t *out, uint32_t log_n, uint32_t q, uint32_t psi) {
+  const uint32_t n = 1u << log_n;
+  for (uint32_t j = 0; j < n; j++) {
+    uint32_t x = oracle_powmod(psi, 2ull * oracle_bitrev(j, log_n) + 1, q);
+    uint32_t acc = 0;
+    for (uint32_t i = n; i-- > 0;) acc = addmod(mulmod(acc, x, q), a[i], q);
+    out[j] = acc;
+  }
+}
+
+/* Textbook cyclic DFT over Z_q, radix-2 decimation in time:
+ * A[k] = sum_i a[i] * w^(i*k), natural order in and out. */
+static void cyclic_dft(uint32_t *a, uint32_t log_n, uint32_t q, uint32_t w) {
+  const uint32_t n = 1u << log_n;
+  for (uint32_t i = 0; i < n; i++) {
+    uint32_t r = oracle_bitrev(i, log_n);
+    if (i < r) { uint32_t t = a[i]; a[i] = a[r]; a[r] = t; }
+  }
+  for (uint32_t len = 2; len <= n; len <<= 1) {
+    uint32_t wl = oracle_powmod(w, n / len, q);
+    for (uint32_t s = 0; s < n; s += len) {
+      uint32_t wk = 1;
+      for (uint32_t k = 0; k < len / 2; k++) {
+        uint32_t u = a[s + k];
+        uint32_t v = mulmod(a[s + k + len / 2], wk, q);
+        a[s + k] = addmod(u, v, q);
+        a[s + k + len / 2] = submod(u, v, q);
+        wk = mulmod(wk, wl, q);
+      }
+    }
+  }
+}
+
+/* a(psi^(2b+1)) = sum_i (a_i psi^i) (psi^2)^(b i): twist by psi^i, take the
+ * cyclic DFT with w = psi^2, and list entry brv(j) at position j. */
+void oracle_ntt(uint32_t *a, uint32_t log_n, uint32_t q, uint32_t psi) {
+  const uint32_t n = 1u << log_n;
+  uint32_t *t = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t pw = 1;
+  for (uint32_t i = 0; i < n; i++) { t[i] = mulmod(a[i], pw, q); pw = mulmod(pw, psi, q); }
+  cyclic_dft(t, log_n, q, mulmod(psi, psi, q));
+  for (uint32_t j = 0; j < n; j++) a[j] = t[oracle_bitrev(j, log_n)];
+  free(t);
+}
+
+/* Inverse of oracle_ntt: undo the listing order, inverse cyclic DFT
+ * (w^-1 and a factor N^-1), then untwist by psi^-i. */
+void oracle_intt(uint32_t *a, uint32_t log_n, uint32_t q, uint32_t psi) {
+  const uint32_t n = 1u << log_n;
+  uint32_t *t = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  for (uint32_t k = 0; k < n; k++) t[k] = a[oracle_bitrev(k, log_n)];
+  uint32_t psi_inv = oracle_invmod(psi, q);
+  cyclic_dft(t, log_n, q, mulmod(psi_inv, psi_inv, q));
+  uint32_t n_inv = oracle_invmod(n % q, q), pw = 1;
+  for (uint32_t i = 0; i < n; i++) {
+    a[i] = mulmod(mulmod(t[i], n_inv, q), pw, q);
+    pw = mulmod(pw, psi_inv, q);
+  }
+  free(t);
+}
+
+void oracle_negacyclic_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t log_n, uint32_t q) {
+  const uint32_t n = 1u << log_n;
+  for (uint32_t k = 0; k < n; k++) c[k] = 0;
+  for (uint32_t i = 0; i < n; i++)
+    for (uint32_t j = 0; j < n; j++) {
+      uint32_t prod = mulmod(a[i], b[j], q);
+      if (i + j < n) c[i + j] = addmod(c[i + j], prod, q);
+      else c[i + j - n] = submod(c[i + j - n], prod, q); /* X^N = -1 */
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* basis conversion                                                     */
+/* ------------------------------------------------------------------ */
+
+/* [prod_{i != skip} src_i]_m */
+static uint32_t prod_except(const uint32_t *src, uint32_t ns, uint32_t skip, uint32_t m) {
+  uint32_t r = 1 % m;
+  for (uint32_t i = 0; i < ns; i++)
+    if (i != skip) r = mulmod(r, src[i] % m, m);
+  return r;
+}
+
+void oracle_bconv(const uint32_t *x, const uint32_t *src, uint32_t ns,
+                  uint32_t *y, const uint32_t *dst, uint32_t nt, uint32_t n) {
+  uint32_t *xt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)ns * n);
+  /* [x_i * (S/s_i)^-1]_{s_i} */
+  for (uint32_t i = 0; i < ns; i++) {
+    uint32_t c = oracle_invmod(prod_except(src, ns, i, src[i]), src[i]);
+    for (uint32_t z = 0; z < n; z++) xt[(size_t)i * n + z] = mulmod(x[(size_t)i * n + z], c, src[i]);
+  }
+  for (uint32_t t = 0; t < nt; t++) {
+    const uint32_t m = dst[t];
+    for (uint32_t z = 0; z < n; z++) y[(size_t)t * n + z] = 0;
+    for (uint32_t i = 0; i < ns; i++) {
+      uint32_t ii = (g_fault == 3 && ns > 1) ? (i + 1) % ns : i;
+      uint32_t c = prod_except(src, ns, ii, m);
+      for (uint32_t z = 0; z < n; z++)
+        y[(size_t)t * n + z] = addmod(y[(size_t)t * n + z], mulmod(xt[(size_t)i * n + z], c, m), m);
+    }
+  }
+  free(xt);
+}
+
+/* ------------------------------------------------------------------ */
+/* hybrid key switching                                                 */
+/* ------------------------------------------------------------------ */
+
+uint64_t oracle_evk_words(uint32_t log_n, uint32_t num_q, uint32_t num_p, uint32_t dnum) {
+  return (uint64_t)dnum * 2ull * (uint64_t)(num_q + num_p) << log_n;
+}
+
+typedef struct {
+  uint32_t n, log_n, L1, K, dnum, alpha, level, ntow, ndig;
+  uint32_t q[160];    /* extended basis D_l: q_0..q_l, p_0..p_{K-1} */
+  uint32_t evk_limb[160]; /* limb index of D_l tower t inside the evk */
+  uint32_t psi[160];
+} ks_ctx;
+
+static int ctx_init(ks_ctx *c, const oracle_params *p, const uint32_t *moduli, uint32_t level) {
+  if (p->log_n < 1 || p->log_n > 17 || p->num_q == 0 || p->dnum == 0 || p->dnum > p->num_q ||
+      p->num_p == 0 || level >= p->num_q || p->num_q + p->num_p > 160)
+    return -1;
+  c->log_n = p->log_n;
+  c->n = 1u << p->log_n;
+  c->L1 = p->num_q;
+  c->K = p->num_p;
+  c->dnum = p->dnum;
+  c->alpha = (p->num_q + p->dnum - 1) / p->dnum;  /* Table I: ceil((L+1)/dnum) */
+  c->level = level;
+  c->ntow = level + 1 + p->num_p;
+  c->ndig = (level + 1 + c->alpha - 1) / c->alpha; /* digits holding a live tower */
+  for (uint32_t i = 0; i <= level; i++) { c->q[i] = moduli[i]; c->evk_limb[i] = i; }
+  for (uint32_t k = 0; k < p->num_p; k++) {
+    c->q[level + 1 + k] = moduli[p->num_q + k];
+    c->evk_limb[level + 1 + k] = p->num_q + k;
+  }
+  for (uint32_t t = 0; t < c->ntow; t++) c->psi[t] = oracle_min_psi(c->q[t], c->log_n);
+  return 0;
+}
+
+static void digit_range(const ks_ctx *c, uint32_t j, uint32_t *lo, uint32_t *hi) {
+  *lo = j * c->alpha;
+  *hi = (j + 1) * c->alpha;
+  if (*hi > c->level + 1) *hi = c->level + 1;
+}
+
+#define LIMB(buf, idx, n) ((buf) + (size_t)(idx) * (n))
+
+/* ModDown, Sec. III-C, for one polynomial t: acc holds [ntow][N] (evaluation
+ * domain, towers of D_l), out receives [level+1][N]. */
+static void moddown(const ks_ctx *c, const uint32_t *acc, uint32_t *out) {
+  const uint32_t n = c->n, l1 = c->level + 1, K = c->K;
+  uint32_t *a = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K * n);
+  uint32_t *w = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  /* P1: INTT of the last K towers */
+  for (uint32_t k = 0; k < K; k++) {
+    memcpy(LIMB(a, k, n), LIMB(acc, l1 + k, n), sizeof(uint32_t) * n);
+    oracle_intt(LIMB(a, k, n), c->log_n, c->q[l1 + k], c->psi[l1 + k]);
+  }
+  /* P2: basis conversion P -> Q_l */
+  oracle_bconv(a, &c->q[l1], K, w, c->q, l1, n);
+  /* P3: NTT of the l+1 converted towers; P4: subtract, times P^-1 */
+  for (uint32_t i = 0; i < l1; i++) {
+    const uint32_t qi = c->q[i];
+    oracle_ntt(LIMB(w, i, n), c->log_n, qi, c->psi[i]);
+    uint32_t p_mod = 1;
+    for (uint32_t k = 0; k < K; k++) p_mod = mulmod(p_mod, c->q[l1 + k] % qi, qi);
+    uint32_t p_inv = oracle_invmod(p_mod, qi);
+    for (uint32_t z = 0; z < n; z++) {
+      uint32_t diff = (g_fault == 2) ? addmod(LIMB(acc, i, n)[z], LIMB(w, i, n)[z], qi)
+                                     : submod(LIMB(acc, i, n)[z], LIMB(w, i, n)[z], qi);
+      LIMB(out, i, n)[z] = mulmod(diff, p_inv, qi);
+    }
+  }
+  free(a);
+  free(w);
+}
+
+int oracle_keyswitch(const oracle_params *p, const uint32_t *moduli, uint32_t level,
+                     const uint32_t *evk, const uint32_t *d, uint32_t *out) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, level) != 0) return -1;
+  const uint32_t n = c.n, l1 = level + 1, T = c.ntow, D = c.ndig, EL = c.L1 + c.K;
+  /* ModUp P1: INTT of every input tower */
+  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  /* ModUp P2/P3 output, one [T][N] block per digit: y[j][t] */
+  uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)D * T * n);
+  uint32_t *acc = (uint32_t *)calloc((size_t)2 * T * n, sizeof(uint32_t));
+  uint32_t *tgt = (uint32_t *)malloc(sizeof(uint32_t) * T * n);
+  uint32_t *tq = (uint32_t *)malloc(sizeof(uint32_t) * T);
+  if (!x || !y || !acc || !tgt || !tq) { free(x); free(y); free(acc); free(tgt); free(tq); return -1; }
+
+  memcpy(x, d, sizeof(uint32_t) * (size_t)l1 * n);
+  for (uint32_t i = 0; i < l1; i++) oracle_intt(LIMB(x, i, n), c.log_n, c.q[i], c.psi[i]);
+
+  for (uint32_t j = 0; j < D; j++) {
+    uint32_t lo, hi;
+    digit_range(&c, j, &lo, &hi);
+    /* P2: extend digit j from its towers S_j to every other tower of D_l */
+    uint32_t nt = 0;
+    for (uint32_t t = 0; t < T; t++)
+      if (t < lo || t >= hi) tq[nt++] = c.q[t];
+    oracle_bconv(LIMB(x, lo, n), &c.q[lo], hi - lo, tgt, tq, nt, n);
+    /* P3: NTT of the extended towers, concatenated with the digit itself */
+    uint32_t u = 0;
+    for (uint32_t t = 0; t < T; t++) {
+      uint32_t *dst = LIMB(y, (size_t)j * T + t, n);
+      if (t >= lo && t < hi) {
+        uint32_t src = t;
+        if (g_fault == 4 && D > 1) src = (t + c.alpha) % l1;
+        memcpy(dst, LIMB(d, src, n), sizeof(uint32_t) * n);
+      } else {
+        memcpy(dst, LIMB(tgt, u, n), sizeof(uint32_t) * n);
+        oracle_ntt(dst, c.log_n, c.q[t], c.psi[t]);
+        u++;
+      }
+    }
+  }
+  /* P4: apply the key, P5: sum over digits */
+  for (uint32_t j = 0; j < D; j++) {
+    if (g_fault == 1 && j == D - 1 && D > 1) continue;
+    for (uint32_t s = 0; s < 2; s++)
+      for (uint32_t t = 0; t < T; t++) {
+        const uint32_t *ek = evk + (((size_t)j * 2 + s) * EL + c.evk_limb[t]) * n;
+        const uint32_t *yy = LIMB(y, (size_t)j * T + t, n);
+        uint32_t *aa = LIMB(acc, (size_t)s * T + t, n);
+        for (uint32_t z = 0; z < n; z++) aa[z] = addmod(aa[z], mulmod(yy[z], ek[z], c.q[t]), c.q[t]);
+      }
+  }
+  /* ModDown P1-P4 for both polynomials */
+  for (uint32_t s = 0; s < 2; s++) moddown(&c, LIMB(acc, (size_t)s * T, n), LIMB(out, (size_t)s * l1, n));
+  free(x); free(y); free(acc); free(tgt); free(tq);
+  return 0;
+}
+
+/* Output-Centric order (Sec. IV-C): INTT outputs kept, then one output tower
+ * at a time.  Section 2 (the P towers, every digit extended) comes first so
+ * their INTT (ModDown P1) is available; then each Q tower takes the other
+ * digits through P2/P3, bypasses its own digit, accumulates P4/P5, and goes
+ * through ModDown P2-P4 for that single tower. */
+int oracle_keyswitch_oc(const oracle_params *p, const uint32_t *moduli, uint32_t level,
+                        const uint32_t *evk, const uint32_t *d, uint32_t *out) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, level) != 0) return -1;
+  const uint32_t n = c.n, l1 = level + 1, K = c.K, D = c.ndig, EL = c.L1 + c.K;
+  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  uint32_t *ap = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)2 * K * n); /* ModDown P1 output */
+  uint32_t *one = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t *acc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)2 * n);
+  if (!x || !ap || !one || !acc) { free(x); free(ap); free(one); free(acc); return -1; }
+  memcpy(x, d, sizeof(uint32_t) * (size_t)l1 * n);
+  for (uint32_t i = 0; i < l1; i++) oracle_intt(LIMB(x, i, n), c.log_n, c.q[i], c.psi[i]);
+
+  for (uint32_t pass = 0; pass < 2; pass++) {           /* 0: P towers, 1: Q towers */
+    uint32_t t0 = pass == 0 ? l1 : 0, t1 = pass == 0 ? l1 + K : l1;
+    for (uint32_t t = t0; t < t1; t++) {
+      const uint32_t m = c.q[t];
+      memset(acc, 0, sizeof(uint32_t) * 2 * n);
+      for (uint32_t j = 0; j < D; j++) {
+        uint32_t lo, hi;
+        digit_range(&c, j, &lo, &hi);
+        if (t >= lo && t < hi) memcpy(one, LIMB(d, t, n), sizeof(uint32_t) * n); /* bypass */
+        else {
+          oracle_bconv(LIMB(x, lo, n), &c.q[lo], hi - lo, one, &m, 1, n);
+          oracle_ntt(one, c.log_n, m, c.psi[t]);
+        }
+        for (uint32_t s = 0; s < 2; s++) {
+          const uint32_t *ek = evk + (((size_t)j * 2 + s) * EL + c.evk_limb[t]) * n;
+          for (uint32_t z = 0; z < n; z++) acc[s * n + z] = addmod(acc[s * n + z], mulmod(one[z], ek[z], m), m);
+        }
+      }
+      for (uint32_t s = 0; s < 2; s++) {
+        if (pass == 0) {
+          memcpy(LIMB(ap, (size_t)s * K + (t - l1), n), acc + s * n, sizeof(uint32_t) * n);
+          oracle_intt(LIMB(ap, (size_t)s * K + (t - l1), n), c.log_n, m, c.psi[t]);
+        } else {
+          oracle_bconv(LIMB(ap, (size_t)s * K, n), &c.q[l1], K, one, &m, 1, n);
+          oracle_ntt(one, c.log_n, m, c.psi[t]);
+          uint32_t p_mod = 1;
+          for (uint32_t k = 0; k < K; k++) p_mod = mulmod(p_mod, c.q[l1 + k] % m, m);
+          uint32_t p_inv = oracle_invmod(p_mod, m);
+          uint32_t *o = LIMB(out, (size_t)s * l1 + t, n);
+          for (uint32_t z = 0; z < n; z++) o[z] = mulmod(submod(acc[s * n + z], one[z], m), p_inv, m);
+        }
+      }
+    }
+  }
+  free(x); free(ap); free(one); free(acc);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* key generation                                                       */
+/* ------------------------------------------------------------------ */
+
+/* xoshiro256** (Blackman & Vigna), seeded through splitmix64. */
+typedef struct { uint64_t s[4]; } rng_t;
+static uint64_t splitmix64(uint64_t *x) {
+  uint64_t z = (*x += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+static uint64_t rotl(uint64_t x, int k) { return (x << k) | (x >> (64 - k)); }
+static uint64_t rng_next(rng_t *r) {
+  uint64_t res = rotl(r->s[1] * 5, 7) * 9, t = r->s[1] << 17;
+  r->s[2] ^= r->s[0]; r->s[3] ^= r->s[1]; r->s[1] ^= r->s[2]; r->s[0] ^= r->s[3];
+  r->s[2] ^= t; r->s[3] = rotl(r->s[3], 45);
+  return res;
+}
+static void rng_seed(rng_t *r, uint64_t seed) { for (int i = 0; i < 4; i++) r->s[i] = splitmix64(&seed); }
+/* uniform in [0, m) by rejection */
+static uint32_t rng_below(rng_t *r, uint32_t m) {
+  uint64_t lim = (UINT64_MAX / m) * m;
+  for (;;) { uint64_t v = rng_next(r); if (v < lim) return (uint32_t)(v % m); }
+}
+static double rng_unit(rng_t *r) { return ((rng_next(r) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+static int32_t rng_gauss(rng_t *r) { /* Box-Muller, sigma 3.2, clamp 19 */
+  double u1 = rng_unit(r), u2 = rng_unit(r);
+  double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  long e = lround(3.2 * z);
+  if (e > 19) e = 19;
+  if (e < -19) e = -19;
+  return (int32_t)e;
+}
+static uint32_t signed_mod(int32_t v, uint32_t m) { return v >= 0 ? (uint32_t)v % m : m - ((uint32_t)(-v) % m); }
+
+int oracle_keygen(const oracle_params *p, const uint32_t *moduli, uint64_t seed,
+                  int8_t *s, int8_t *s2, uint32_t *evk) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, p->num_q - 1) != 0) return -1;
+  const uint32_t n = c.n, EL = c.L1 + c.K;
+  rng_t r;
+  rng_seed(&r, seed);
+  int h = 0;
+  for (uint32_t z = 0; z < n; z++) { s[z] = (int8_t)((int)rng_below(&r, 3) - 1); h += s[z] != 0; }
+  for (uint32_t z = 0; z < n; z++) s2[z] = (int8_t)((int)rng_below(&r, 3) - 1);
+  uint32_t *sh = (uint32_t *)malloc(sizeof(uint32_t) * n), *s2h = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t *eh = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  int32_t *e = (int32_t *)malloc(sizeof(int32_t) * n);
+  for (uint32_t j = 0; j < p->dnum; j++) {
+    uint32_t lo = j * c.alpha, hi = (j + 1) * c.alpha;
+    if (hi > c.L1) hi = c.L1;
+    for (uint32_t z = 0; z < n; z++) e[z] = rng_gauss(&r);
+    for (uint32_t g = 0; g < EL; g++) {
+      const uint32_t m = c.q[g]; /* at level L the D_L order equals the evk order */
+      for (uint32_t z = 0; z < n; z++) { sh[z] = signed_mod(s[z], m); s2h[z] = signed_mod(s2[z], m); eh[z] = signed_mod(e[z], m); }
+      oracle_ntt(sh, c.log_n, m, c.psi[g]);
+      oracle_ntt(s2h, c.log_n, m, c.psi[g]);
+      oracle_ntt(eh, c.log_n, m, c.psi[g]);
+      uint32_t gad = 0; /* [P]_m on digit j's own q-limbs */
+      if (g >= lo && g < hi) {
+        gad = 1;
+        for (uint32_t k = 0; k < c.K; k++) gad = mulmod(gad, moduli[c.L1 + k] % m, m);
+      }
+      uint32_t *b = evk + (((size_t)j * 2 + 0) * EL + g) * n;
+      uint32_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
+      for (uint32_t z = 0; z < n; z++) {
+        a[z] = rng_below(&r, m);
+        uint32_t v = submod(eh[z], mulmod(a[z], sh[z], m), m);
+        b[z] = addmod(v, mulmod(gad, s2h[z], m), m);
+      }
+    }
+  }
+  free(sh); free(s2h); free(eh); free(e);
+  return h;
+}
