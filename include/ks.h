@@ -1,0 +1,148 @@
+/*
+ * ks.h -- C ABI of the MI355X (gfx950) hybrid key-switching library.
+ *
+ * The operation (CiFlow, Sec. III): given a polynomial d in R_{Q_l} in the
+ * evaluation domain that decrypts under a key s2, and an evaluation key evk
+ * for s2 -> s, return (c0, c1) in R_{Q_l} with c0 + c1 s ~ d s2 (mod Q_l).
+ * Steps: digit decomposition into dnum digits of alpha towers (Sec. III-A),
+ * ModUp P1 INTT, P2 fast basis conversion to D_l = Q_l u P, P3 NTT, P4
+ * multiply by evk, P5 sum over digits (Sec. III-B), then ModDown P1 INTT of
+ * the K special towers, P2 conversion back to Q_l, P3 NTT, P4 subtract and
+ * multiply by P^-1 mod q_i (Sec. III-C).  Three execution orders of the same
+ * computation are available (Sec. IV): Max-Parallel, Digit-Centric and
+ * Output-Centric; all return identical bits.
+ *
+ * Conventions shared by every entry point:
+ *  - Residues are uint32, canonical in [0, m), moduli are primes with
+ *    2^29 < m < 2^30 and m = 1 mod 2N.  Inputs outside [0, m) give
+ *    unspecified (but memory-safe) outputs.
+ *  - Polynomials are limb-major: [towers][N].  The evaluation domain is
+ *    NTT(a)[j] = a(psi^(2 brv(j) + 1)) with psi the smallest primitive 2N-th
+ *    root of unity mod m and brv the log2(N)-bit reversal.
+ *  - Moduli order: q_0..q_L then p_0..p_{K-1}.  Unless given explicitly, the
+ *    moduli are the primes 2^30 - t*2N + 1, t = 1, 2, ..., the first K
+ *    becoming p_0..p_{K-1} and the next L+1 becoming q_0..q_L.
+ *  - evk layout: [dnum][2][L+1+K][N] (Sec. III-B P4: dnum x 2 x N x (l+K)),
+ *    pair index 0 = b_j, 1 = a_j, with b_j + a_j s = e_j + g_j s2 where g_j is
+ *    [P]_m on digit j's own q-limbs and 0 on every other limb.
+ *  - Device pointers are HIP device addresses on the plan's device; the
+ *    caller owns every buffer (inputs, outputs, evk, workspace).  `stream` is
+ *    a hipStream_t (NULL = default stream).  Calls are asynchronous on the
+ *    stream; argument errors are reported synchronously before anything is
+ *    enqueued; launch failures return KS_ERR_DEVICE.
+ *  - No call aborts or throws across the ABI.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KS_OK = 0,
+  KS_ERR_INVALID_ARG = 1,  /* bad pointer, size, level, alias, modulus */
+  KS_ERR_UNSUPPORTED = 2,  /* valid but outside what this build supports */
+  KS_ERR_NOMEM = 3,        /* device or host allocation failed */
+  KS_ERR_BUDGET = 4,       /* workspace smaller than ks_workspace_size() */
+  KS_ERR_DEVICE = 5        /* a HIP call or kernel launch failed */
+} ks_status_t;
+
+/* Execution orders of Sec. IV. */
+typedef enum {
+  KS_SCHED_AUTO = 0,  /* the plan's tuned choice (OC unless tuned otherwise) */
+  KS_SCHED_MP = 1,    /* Max-Parallel, Sec. IV-A: each stage over all towers */
+  KS_SCHED_DC = 2,    /* Digit-Centric, Sec. IV-B: one digit at a time */
+  KS_SCHED_OC = 3     /* Output-Centric, Sec. IV-C: one output tower tile at a time */
+} ks_schedule_t;
+
+/* Parameter set (Table I).  log_n in [12, 17]; num_q = L+1 >= 1;
+ * 1 <= dnum <= num_q (alpha = ceil(num_q/dnum)); num_p = K (0 => alpha);
+ * num_q + num_p <= 128.  `moduli` is an optional host array of
+ * num_q + num_p values (q_0..q_L, p_0..p_{K-1}); NULL selects the default
+ * primes.  Explicit moduli are validated: prime, 2^29 < m < 2^30,
+ * m = 1 mod 2N, pairwise distinct. */
+typedef struct {
+  uint32_t log_n;
+  uint32_t num_q;
+  uint32_t dnum;
+  uint32_t num_p;
+  const uint32_t *moduli;
+} ks_params_t;
+
+/* Launch configuration (what the autotuner chooses).  Zero fields keep the
+ * plan's current value. */
+typedef struct {
+  ks_schedule_t schedule;
+  uint32_t tile_towers;  /* OC: output towers sharing one column-pass tile (1, 2, 4) */
+  uint32_t col_width;    /* columns per column-pass workgroup (8, 16, 32) */
+  uint32_t row_block;    /* rows per row-pass workgroup (4, 8, 16) */
+} ks_config_t;
+
+typedef struct ks_plan *ks_plan_t;
+
+/* One ciphertext component of a batch: `in` [level+1][N], `out`
+ * [2][level+1][N], `evk` [dnum][2][L+1+K][N] (device pointers). */
+typedef struct {
+  const uint32_t *evk;
+  uint32_t level;
+  const uint32_t *in;
+  uint32_t *out;
+} ks_job_t;
+
+/* Host only, needs no device: the moduli a plan with these parameters uses
+ * (default primes, or the validated explicit list), written to host_out
+ * [num_q + num_p].  Sec. II (RNS towers of word-size moduli). */
+ks_status_t ks_params_moduli(const ks_params_t *p, uint32_t *host_out);
+
+/* Host only: psi for modulus q at ring degree 2^log_n (the smallest
+ * primitive 2N-th root of unity), or 0 if q is not a prime = 1 mod 2N. */
+uint32_t ks_root_of_unity(uint32_t q, uint32_t log_n);
+
+/* Create a plan on the current HIP device: derive moduli and psi, build the
+ * twiddle, basis-conversion and ModDown tables (Sec. III-B/C) and upload
+ * them.  *out owns them until ks_plan_destroy. */
+ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out);
+ks_status_t ks_plan_destroy(ks_plan_t plan);
+/* Moduli of the plan, host_out [num_q + num_p]. */
+ks_status_t ks_plan_moduli(ks_plan_t plan, uint32_t *host_out);
+ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg);
+ks_status_t ks_plan_get_config(ks_plan_t plan, ks_config_t *cfg);
+
+/* Bytes of device workspace ks_keyswitch (count = 1) or ks_keyswitch_batch
+ * needs for jobs at the given levels under the plan's current schedule.
+ * `levels` is a host array of `count` levels (each <= L). */
+ks_status_t ks_workspace_size(ks_plan_t plan, uint32_t count, const uint32_t *levels, size_t *bytes);
+
+/* Hybrid key switch of one polynomial (Sec. III, order per the plan's
+ * schedule, Sec. IV).  in [level+1][N] (device, evaluation domain), out
+ * [2][level+1][N] (device; out must not overlap in, evk or workspace),
+ * evk [dnum][2][L+1+K][N] (device), workspace >= ks_workspace_size bytes,
+ * 256-byte aligned.  Output canonical, evaluation domain. */
+ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
+                         const uint32_t *in, uint32_t *out, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Many key switches at mixed levels in one launch sequence (jobs is a host
+ * array of `count` entries).  Each job's output equals ks_keyswitch of that
+ * job alone.  Outputs must not overlap each other or any input. */
+ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Stage access for tests and tools: in-place forward (inverse = 0) or
+ * inverse (inverse = 1, including the N^-1 factor) negacyclic NTT of
+ * `count` limbs data[count][N] (device), limb c taken modulo the plan's
+ * modulus number g[c] (host array, global index: q_0..q_L, p_0..p_{K-1}).
+ * ModUp P1/P3 and ModDown P1/P3 use the same transform. */
+ks_status_t ks_ntt(ks_plan_t plan, uint32_t count, const uint32_t *g, int inverse,
+                   uint32_t *data, void *stream);
+
+const char *ks_status_string(ks_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

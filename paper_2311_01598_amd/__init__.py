@@ -1,0 +1,247 @@
+"""Python binding of the MI355X hybrid key-switching library (libks.so).
+
+Argument marshalling only: every step of the key switch runs in the HIP
+kernels behind the C ABI declared in ``include/ks.h``.  PyTorch supplies
+device memory and streams; uint32 residues travel in ``torch.int32``
+tensors (same bits).  Importing this module loads ``libks.so`` and raises if
+it is missing -- there is no fallback path.
+
+The functions keep the C names (``ks_plan_create``, ``ks_keyswitch``, ...);
+``Plan`` is a small convenience wrapper around them.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libks.so")
+
+KS_OK, KS_ERR_INVALID_ARG, KS_ERR_UNSUPPORTED, KS_ERR_NOMEM, KS_ERR_BUDGET, KS_ERR_DEVICE = range(6)
+KS_SCHED_AUTO, KS_SCHED_MP, KS_SCHED_DC, KS_SCHED_OC = range(4)
+SCHEDULES = {"auto": KS_SCHED_AUTO, "mp": KS_SCHED_MP, "dc": KS_SCHED_DC, "oc": KS_SCHED_OC}
+
+
+class KsError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {ks_status_string(status)} ({status})")
+
+
+class ks_params_t(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("num_q", ctypes.c_uint32), ("dnum", ctypes.c_uint32),
+                ("num_p", ctypes.c_uint32), ("moduli", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class ks_config_t(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int), ("tile_towers", ctypes.c_uint32), ("col_width", ctypes.c_uint32),
+                ("row_block", ctypes.c_uint32)]
+
+
+class ks_job_t(ctypes.Structure):
+    _fields_ = [("evk", ctypes.c_void_p), ("level", ctypes.c_uint32), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_VP = ctypes.c_void_p
+_SIGS = {
+    "ks_params_moduli": (ctypes.c_int, [ctypes.POINTER(ks_params_t), _U32P]),
+    "ks_root_of_unity": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32]),
+    "ks_plan_create": (ctypes.c_int, [ctypes.POINTER(ks_params_t), ctypes.POINTER(_VP)]),
+    "ks_plan_destroy": (ctypes.c_int, [_VP]),
+    "ks_plan_moduli": (ctypes.c_int, [_VP, _U32P]),
+    "ks_plan_set_config": (ctypes.c_int, [_VP, ctypes.POINTER(ks_config_t)]),
+    "ks_plan_get_config": (ctypes.c_int, [_VP, ctypes.POINTER(ks_config_t)]),
+    "ks_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.POINTER(ctypes.c_size_t)]),
+    "ks_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
+                                          _VP]),
+    "ks_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
+    "ks_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+EXPORTS = tuple(_SIGS)
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(hipcc --offload-arch=gfx950).  There is no CPU fallback.")
+_lib = ctypes.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def lib():
+    return _lib
+
+
+def ks_status_string(status):
+    return _lib.ks_status_string(int(status)).decode()
+
+
+def _check(status, what):
+    if status != KS_OK:
+        raise KsError(status, what)
+
+
+def _u32_array(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_uint32 * len(vals))(*vals)
+
+
+def _params(log_n, num_q, dnum, num_p=0, moduli=None):
+    p = ks_params_t(log_n, num_q, dnum, num_p, None)
+    keep = None
+    if moduli is not None:
+        keep = _u32_array(moduli)
+        p.moduli = ctypes.cast(keep, _U32P)
+    return p, keep
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / int / None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def ks_params_moduli(log_n, num_q, dnum, num_p=0, moduli=None):
+    p, keep = _params(log_n, num_q, dnum, num_p, moduli)
+    alpha = -(-num_q // dnum)
+    k = num_p or alpha
+    out = (ctypes.c_uint32 * (num_q + k))()
+    _check(_lib.ks_params_moduli(ctypes.byref(p), out), "ks_params_moduli")
+    return list(out)
+
+
+def ks_root_of_unity(q, log_n):
+    return int(_lib.ks_root_of_unity(int(q), int(log_n)))
+
+
+def ks_plan_create(log_n, num_q, dnum, num_p=0, moduli=None):
+    p, keep = _params(log_n, num_q, dnum, num_p, moduli)
+    h = _VP()
+    _check(_lib.ks_plan_create(ctypes.byref(p), ctypes.byref(h)), "ks_plan_create")
+    return h.value
+
+
+def ks_plan_destroy(plan):
+    _check(_lib.ks_plan_destroy(plan), "ks_plan_destroy")
+
+
+def ks_plan_moduli(plan, count):
+    out = (ctypes.c_uint32 * count)()
+    _check(_lib.ks_plan_moduli(plan, out), "ks_plan_moduli")
+    return list(out)
+
+
+def ks_plan_set_config(plan, schedule=0, tile_towers=0, col_width=0, row_block=0):
+    if isinstance(schedule, str):
+        schedule = SCHEDULES[schedule]
+    c = ks_config_t(schedule, tile_towers, col_width, row_block)
+    _check(_lib.ks_plan_set_config(plan, ctypes.byref(c)), "ks_plan_set_config")
+
+
+def ks_plan_get_config(plan):
+    c = ks_config_t()
+    _check(_lib.ks_plan_get_config(plan, ctypes.byref(c)), "ks_plan_get_config")
+    return {"schedule": c.schedule, "tile_towers": c.tile_towers, "col_width": c.col_width,
+            "row_block": c.row_block}
+
+
+def ks_workspace_size(plan, levels):
+    n = ctypes.c_size_t()
+    arr = _u32_array(levels)
+    _check(_lib.ks_workspace_size(plan, len(levels), arr, ctypes.byref(n)), "ks_workspace_size")
+    return n.value
+
+
+def ks_keyswitch(plan, evk, level, inp, out, workspace, workspace_bytes=None, stream=None):
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    st = _lib.ks_keyswitch(plan, _ptr(evk), int(level), _ptr(inp), _ptr(out), _ptr(workspace),
+                           int(workspace_bytes), _stream(stream))
+    _check(st, "ks_keyswitch")
+
+
+def ks_keyswitch_batch(plan, jobs, workspace, workspace_bytes=None, stream=None):
+    """jobs: list of (evk, level, in, out) tensors/addresses."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_job_t * len(jobs))()
+    for i, (evk, level, inp, out) in enumerate(jobs):
+        arr[i] = ks_job_t(_ptr(evk), int(level), _ptr(inp), _ptr(out))
+    st = _lib.ks_keyswitch_batch(plan, len(jobs), arr, _ptr(workspace), int(workspace_bytes), _stream(stream))
+    _check(st, "ks_keyswitch_batch")
+
+
+def ks_ntt(plan, g, inverse, data, stream=None):
+    arr = _u32_array(g)
+    _check(_lib.ks_ntt(plan, len(g), arr, int(bool(inverse)), _ptr(data), _stream(stream)), "ks_ntt")
+
+
+class Plan:
+    """A key-switching plan on the current device (owns the C handle)."""
+
+    def __init__(self, log_n, num_q, dnum, num_p=0, moduli=None, schedule=None, **cfg):
+        self.log_n, self.num_q, self.dnum = log_n, num_q, dnum
+        self.alpha = -(-num_q // dnum)
+        self.num_p = num_p or self.alpha
+        self.n = 1 << log_n
+        self.handle = ks_plan_create(log_n, num_q, dnum, num_p, moduli)
+        self.moduli = ks_plan_moduli(self.handle, num_q + self.num_p)
+        if schedule is not None or cfg:
+            self.configure(schedule or 0, **cfg)
+
+    def configure(self, schedule=0, tile_towers=0, col_width=0, row_block=0):
+        ks_plan_set_config(self.handle, schedule, tile_towers, col_width, row_block)
+
+    @property
+    def config(self):
+        return ks_plan_get_config(self.handle)
+
+    def workspace_bytes(self, levels):
+        return ks_workspace_size(self.handle, list(levels))
+
+    def workspace(self, levels, device="cuda"):
+        import torch
+        nbytes = max(self.workspace_bytes(levels), 256)
+        return torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=device)
+
+    def keyswitch(self, evk, level, d, out=None, workspace=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int32, device=d.device)
+        if workspace is None:
+            workspace = self.workspace([level], d.device)
+        ks_keyswitch(self.handle, evk, level, d, out, workspace, stream=stream)
+        return out
+
+    def keyswitch_batch(self, jobs, workspace=None, stream=None):
+        if workspace is None:
+            workspace = self.workspace([j[1] for j in jobs])
+        ks_keyswitch_batch(self.handle, jobs, workspace, stream=stream)
+
+    def ntt(self, data, g, inverse=False, stream=None):
+        ks_ntt(self.handle, list(g), inverse, data, stream=stream)
+
+    def close(self):
+        if self.handle:
+            ks_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,359 @@
+// api.cpp -- the C ABI (include/ks.h): validation, workspace layout and the
+// three execution orders of Sec. IV as launch sequences.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+
+using namespace ks;
+
+struct ks_plan {
+  Plan p;
+};
+
+namespace {
+
+inline size_t limb_bytes(const Plan &pl) { return (size_t)pl.n * sizeof(uint32_t); }
+
+ks_schedule_t effective(const Plan &pl) {
+  return pl.cfg.schedule == KS_SCHED_AUTO ? KS_SCHED_OC : pl.cfg.schedule;
+}
+
+// Workspace of one key switch at `level`, in limbs, per schedule.
+size_t ws_limbs(const Plan &pl, ks_schedule_t sch, uint32_t level) {
+  const size_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level);
+  switch (sch) {
+    case KS_SCHED_MP: return L1 + D * T + D * 2 * T + 2 * T + 2 * K + 2 * L1;
+    case KS_SCHED_DC: return pl.alpha + T + 2 * T + 2 * K + 2 * L1;
+    default: return L1 + D * T + 2 * K + 2 * L1;
+  }
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+ks_status_t dev_err(hipError_t e) { return e == hipSuccess ? KS_OK : KS_ERR_DEVICE; }
+
+#define TRY(expr)                                  \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return KS_ERR_DEVICE;    \
+  } while (0)
+
+// ---------------------------------------------------------------- MP
+// Sec. IV-A: every stage over all towers, every stage output in HBM.
+ks_status_t run_mp(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
+                   uint32_t *ws, hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
+  uint32_t *X = ws, *Y = X + (size_t)L1 * N, *Z = Y + (size_t)D * T * N, *ACC = Z + (size_t)D * 2 * T * N;
+  uint32_t *XP = ACC + (size_t)2 * T * N, *W = XP + (size_t)2 * K * N;
+  std::vector<uint32_t> so, dof, g;
+  // ModUp P1: INTT of all towers
+  for (uint32_t i = 0; i < L1; i++) { so.push_back(i); dof.push_back(i); g.push_back(i); }
+  TRY(launch_ntt(pl, true, d, X, so, dof, g, st));
+  // P2: basis conversion of every digit
+  TRY(launch_bconv_up(pl, level, 0, D, false, X, Y, st));
+  // P3: NTT of every extended tower
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t j = 0; j < D; j++) {
+    uint32_t lo, hi;
+    digit_range(pl, level, j, &lo, &hi);
+    for (uint32_t t = 0; t < T; t++) {
+      if (t >= lo && t < hi) continue;
+      so.push_back(j * T + t); dof.push_back(j * T + t); g.push_back(tower_g(pl, level, t));
+    }
+  }
+  TRY(launch_ntt(pl, false, Y, Y, so, dof, g, st));
+  // P4: apply key, P5: sum over digits
+  TRY(launch_keymul(pl, level, d, Y, evk, Z, st));
+  TRY(launch_reduce_digits(pl, level, Z, ACC, st));
+  // ModDown P1: INTT of the K special towers of both polynomials
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl.num_q + k); }
+  TRY(launch_ntt(pl, true, ACC, XP, so, dof, g, st));
+  // P2: basis conversion P -> Q_l; P3: NTT; P4: subtract, times P^-1
+  TRY(launch_bconv_down(pl, level, XP, W, st));
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t i = 0; i < L1; i++) { so.push_back(s * L1 + i); dof.push_back(s * L1 + i); g.push_back(i); }
+  TRY(launch_ntt(pl, false, W, W, so, dof, g, st));
+  TRY(launch_moddown_final(pl, level, ACC, W, out, st));
+  return KS_OK;
+}
+
+// ---------------------------------------------------------------- DC
+// Sec. IV-B: one digit at a time through P1-P5, partial sums accumulated.
+ks_status_t run_dc(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
+                   uint32_t *ws, hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
+  uint32_t *X = ws, *Yj = X + (size_t)pl.alpha * N, *ACC = Yj + (size_t)T * N;
+  uint32_t *XP = ACC + (size_t)2 * T * N, *W = XP + (size_t)2 * K * N;
+  std::vector<uint32_t> so, dof, g;
+  for (uint32_t j = 0; j < D; j++) {
+    uint32_t lo, hi;
+    digit_range(pl, level, j, &lo, &hi);
+    so.clear(); dof.clear(); g.clear();
+    for (uint32_t i = lo; i < hi; i++) { so.push_back(i); dof.push_back(i - lo); g.push_back(i); }
+    TRY(launch_ntt(pl, true, d, X, so, dof, g, st));
+    TRY(launch_bconv_up(pl, level, j, 1, true, X, Yj, st));
+    so.clear(); dof.clear(); g.clear();
+    for (uint32_t t = 0; t < T; t++) {
+      if (t >= lo && t < hi) continue;
+      so.push_back(t); dof.push_back(t); g.push_back(tower_g(pl, level, t));
+    }
+    TRY(launch_ntt(pl, false, Yj, Yj, so, dof, g, st));
+    TRY(launch_keymac_digit(pl, level, j, d, Yj, evk, ACC, st));
+  }
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl.num_q + k); }
+  TRY(launch_ntt(pl, true, ACC, XP, so, dof, g, st));
+  TRY(launch_bconv_down(pl, level, XP, W, st));
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t i = 0; i < L1; i++) { so.push_back(s * L1 + i); dof.push_back(s * L1 + i); g.push_back(i); }
+  TRY(launch_ntt(pl, false, W, W, so, dof, g, st));
+  TRY(launch_moddown_final(pl, level, ACC, W, out, st));
+  return KS_OK;
+}
+
+// ---------------------------------------------------------------- OC
+ks_status_t run_oc(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
+                   uint32_t *ws, hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
+  OcArgs a{};
+  a.d = d;
+  a.evk = evk;
+  a.out = out;
+  a.level = level;
+  a.xt = ws;
+  a.ycol = a.xt + (size_t)L1 * N;
+  a.zp = a.ycol + (size_t)D * T * N;
+  a.wcol = a.zp + (size_t)2 * K * N;
+  return dev_err(launch_oc(pl, a, st));
+}
+
+ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint32_t level, const uint32_t *d,
+                    uint32_t *out, uint32_t *ws, hipStream_t st) {
+  switch (sch) {
+    case KS_SCHED_MP: return run_mp(pl, evk, level, d, out, ws, st);
+    case KS_SCHED_DC: return run_dc(pl, evk, level, d, out, ws, st);
+    default: return run_oc(pl, evk, level, d, out, ws, st);
+  }
+}
+
+ks_status_t check_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *in, const uint32_t *out,
+                      const void *ws, size_t ws_bytes, size_t need) {
+  if (!evk || !in || !out || !ws) return KS_ERR_INVALID_ARG;
+  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  if (((uintptr_t)evk | (uintptr_t)in | (uintptr_t)out) & 15) return KS_ERR_INVALID_ARG;
+  if ((uintptr_t)ws & 255) return KS_ERR_INVALID_ARG;
+  if (ws_bytes < need) return KS_ERR_BUDGET;
+  const size_t lb = limb_bytes(pl);
+  const size_t out_b = 2 * (size_t)(level + 1) * lb, in_b = (size_t)(level + 1) * lb;
+  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb;
+  if (overlaps(out, out_b, in, in_b) || overlaps(out, out_b, evk, evk_b) || overlaps(out, out_b, ws, ws_bytes))
+    return KS_ERR_INVALID_ARG;
+  if (overlaps(ws, ws_bytes, in, in_b) || overlaps(ws, ws_bytes, evk, evk_b)) return KS_ERR_INVALID_ARG;
+  return KS_OK;
+}
+
+ks_status_t validate_params(const ks_params_t *p) {
+  if (!p) return KS_ERR_INVALID_ARG;
+  if (p->log_n < 12 || p->log_n > 17) return KS_ERR_UNSUPPORTED;
+  if (p->num_q == 0 || p->dnum == 0 || p->dnum > p->num_q) return KS_ERR_INVALID_ARG;
+  const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum;
+  const uint32_t K = p->num_p ? p->num_p : alpha;
+  if (p->num_q + K > kMaxTowers) return KS_ERR_UNSUPPORTED;
+  if (alpha > 32 || K > 32) return KS_ERR_UNSUPPORTED;
+  if (p->moduli) {
+    const uint64_t two_n = 2ull << p->log_n;
+    for (uint32_t i = 0; i < p->num_q + K; i++) {
+      const uint32_t m = p->moduli[i];
+      if (m <= (1u << 29) || m >= (1u << 30) || m % two_n != 1 || !is_prime_u64(m)) return KS_ERR_INVALID_ARG;
+      for (uint32_t j = 0; j < i; j++)
+        if (p->moduli[j] == m) return KS_ERR_INVALID_ARG;
+    }
+  }
+  return KS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ks_status_string(ks_status_t s) {
+  switch (s) {
+    case KS_OK: return "ok";
+    case KS_ERR_INVALID_ARG: return "invalid argument";
+    case KS_ERR_UNSUPPORTED: return "unsupported parameters";
+    case KS_ERR_NOMEM: return "out of memory";
+    case KS_ERR_BUDGET: return "workspace too small";
+    case KS_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+ks_status_t ks_params_moduli(const ks_params_t *p, uint32_t *host_out) {
+  ks_status_t st = validate_params(p);
+  if (st != KS_OK) return st;
+  if (!host_out) return KS_ERR_INVALID_ARG;
+  const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum;
+  const uint32_t K = p->num_p ? p->num_p : alpha, tot = p->num_q + K;
+  if (p->moduli) {
+    std::copy(p->moduli, p->moduli + tot, host_out);
+    return KS_OK;
+  }
+  std::vector<uint32_t> pr(tot);
+  if (ntt_primes(p->log_n, tot, pr.data()) != 0) return KS_ERR_UNSUPPORTED;
+  for (uint32_t i = 0; i < p->num_q; i++) host_out[i] = pr[K + i];
+  for (uint32_t k = 0; k < K; k++) host_out[p->num_q + k] = pr[k];
+  return KS_OK;
+}
+
+uint32_t ks_root_of_unity(uint32_t q, uint32_t log_n) {
+  if (log_n < 1 || log_n > 20) return 0;
+  return min_root_2n(q, log_n);
+}
+
+ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
+  if (!out) return KS_ERR_INVALID_ARG;
+  *out = nullptr;
+  ks_status_t st = validate_params(p);
+  if (st != KS_OK) return st;
+  ks_plan *pl = new (std::nothrow) ks_plan();
+  if (!pl) return KS_ERR_NOMEM;
+  pl->p.cfg = ks_config_t{KS_SCHED_OC, 1, 16, 8};
+  st = plan_build(p, &pl->p);
+  if (st != KS_OK) {
+    plan_free(&pl->p);
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return KS_OK;
+}
+
+ks_status_t ks_plan_destroy(ks_plan_t plan) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  plan_free(&plan->p);
+  delete plan;
+  return KS_OK;
+}
+
+ks_status_t ks_plan_moduli(ks_plan_t plan, uint32_t *host_out) {
+  if (!plan || !host_out) return KS_ERR_INVALID_ARG;
+  std::copy(plan->p.mod.begin(), plan->p.mod.end(), host_out);
+  return KS_OK;
+}
+
+ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
+  if (!plan || !cfg) return KS_ERR_INVALID_ARG;
+  if ((int)cfg->schedule < 0 || (int)cfg->schedule > 3) return KS_ERR_INVALID_ARG;
+  auto ok = [](uint32_t v, std::initializer_list<uint32_t> allowed) {
+    if (!v) return true;
+    for (uint32_t a : allowed) if (a == v) return true;
+    return false;
+  };
+  if (!ok(cfg->tile_towers, {1, 2, 4}) || !ok(cfg->col_width, {8, 16, 32}) || !ok(cfg->row_block, {4, 8, 16}))
+    return KS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(plan->p.lock);
+  ks_config_t &c = plan->p.cfg;
+  c.schedule = cfg->schedule;
+  if (cfg->tile_towers) c.tile_towers = cfg->tile_towers;
+  if (cfg->col_width) c.col_width = cfg->col_width;
+  if (cfg->row_block) c.row_block = cfg->row_block;
+  return KS_OK;
+}
+
+ks_status_t ks_plan_get_config(ks_plan_t plan, ks_config_t *cfg) {
+  if (!plan || !cfg) return KS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(plan->p.lock);
+  *cfg = plan->p.cfg;
+  return KS_OK;
+}
+
+ks_status_t ks_workspace_size(ks_plan_t plan, uint32_t count, const uint32_t *levels, size_t *bytes) {
+  if (!plan || !bytes || (count && !levels)) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  size_t mx = 0;
+  for (uint32_t i = 0; i < count; i++) {
+    if (levels[i] >= pl.num_q) return KS_ERR_INVALID_ARG;
+    mx = std::max(mx, ws_limbs(pl, effective(pl), levels[i]));
+  }
+  *bytes = mx * limb_bytes(pl);
+  return KS_OK;
+}
+
+ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in, uint32_t *out,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  const ks_schedule_t sch = effective(pl);
+  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  const size_t need = ws_limbs(pl, sch, level) * limb_bytes(pl);
+  ks_status_t st = check_job(pl, evk, level, in, out, workspace, workspace_bytes, need);
+  if (st != KS_OK) return st;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  return run_one(pl, sch, evk, level, in, out, (uint32_t *)workspace, (hipStream_t)stream);
+}
+
+ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+  if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  const ks_schedule_t sch = effective(pl);
+  size_t need = 0;
+  for (uint32_t i = 0; i < count; i++) {
+    if (jobs[i].level >= pl.num_q) return KS_ERR_INVALID_ARG;
+    need = std::max(need, ws_limbs(pl, sch, jobs[i].level) * limb_bytes(pl));
+  }
+  for (uint32_t i = 0; i < count; i++) {
+    ks_status_t st = check_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, workspace,
+                               workspace_bytes, need);
+    if (st != KS_OK) return st;
+    const size_t ob = 2 * (size_t)(jobs[i].level + 1) * limb_bytes(pl);
+    for (uint32_t k = 0; k < i; k++) {
+      const size_t okb = 2 * (size_t)(jobs[k].level + 1) * limb_bytes(pl);
+      const size_t ikb = (size_t)(jobs[k].level + 1) * limb_bytes(pl);
+      if (overlaps(jobs[i].out, ob, jobs[k].out, okb) || overlaps(jobs[i].out, ob, jobs[k].in, ikb))
+        return KS_ERR_INVALID_ARG;
+    }
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  for (uint32_t i = 0; i < count; i++) {
+    ks_status_t st = run_one(pl, sch, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)workspace,
+                             (hipStream_t)stream);
+    if (st != KS_OK) return st;
+  }
+  return KS_OK;
+}
+
+ks_status_t ks_ntt(ks_plan_t plan, uint32_t count, const uint32_t *g, int inverse, uint32_t *data, void *stream) {
+  if (!plan || (count && (!g || !data))) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  std::vector<uint32_t> off(count), gv(count);
+  for (uint32_t c = 0; c < count; c++) {
+    if (g[c] >= pl.ntot) return KS_ERR_INVALID_ARG;
+    off[c] = c;
+    gv[c] = g[c];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  TRY(launch_ntt(pl, inverse != 0, data, data, off, off, gv, st));
+  for (uint32_t b = 0; b < count; b += kMaxList) {
+    LimbList L{};
+    L.count = std::min(count - b, kMaxList);
+    for (uint32_t c = 0; c < L.count; c++) { L.dst_off[c] = b + c; L.g[c] = (uint16_t)g[b + c]; }
+    TRY(launch_finish_ntt(pl, inverse != 0, data, L, st));
+  }
+  return KS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// modarith.h -- exact uint32 modular arithmetic for 30-bit NTT primes on gfx950.
+//
+// All moduli satisfy 2^29 < q < 2^30, so 4q < 2^32: lazy values in [0, 4q)
+// fit a 32-bit lane.  Three reductions are used:
+//   * Shoup multiplication by a precomputed constant w (companion
+//     w' = floor(w * 2^32 / q)): a*w mod q in [0, 2q) for any a < 2^32,
+//     one mul_hi and two mul_lo;
+//   * REDC of a 64-bit accumulator T (sum of at most 16 products of values
+//     below 2^30): returns T * 2^-32 mod q, canonical.  The high word is first
+//     brought below 2q with a one-word Barrett step (mu = floor(2^32/q)), so
+//     T' = hi*2^32 + lo < 2q*2^32 and (T' + u q)/2^32 < 3q;
+//   * conditional subtraction csub(a, m) = min(a, a - m) (unsigned).
+// Constants that meet a REDC carry the factor 2^32 (Montgomery form), so a
+// dot product followed by one REDC yields the plain residue.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ks {
+
+struct ModQ {
+  uint32_t q;        // modulus
+  uint32_t qinv;     // -q^-1 mod 2^32
+  uint32_t mu;       // floor(2^32 / q)
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) {
+  uint32_t d = a - m;
+  return d < a ? d : a;  // a >= m ? a - m : a
+}
+
+// a * w mod q in [0, 2q), any a < 2^32.
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
+  uint32_t h = __umulhi(a, wp);
+  return a * w - h * q;
+}
+
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
+  return (uint64_t)a * (uint64_t)b + c;
+}
+
+// T * 2^-32 mod q, canonical, for any T < 2^64.
+__device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
+  uint32_t hi = (uint32_t)(T >> 32), lo = (uint32_t)T;
+  hi -= __umulhi(hi, m.mu) * m.q;        // [0, 2q)
+  uint32_t u = lo * m.qinv;
+  uint64_t s = (uint64_t)u * m.q + (((uint64_t)hi << 32) | lo);
+  uint32_t r = (uint32_t)(s >> 32);      // [0, 3q)
+  r = csub(r, m.q);
+  return csub(r, m.q);
+}
+
+// Harvey forward (Cooley-Tukey) butterfly, inputs and outputs in [0, 4q).
+__device__ __forceinline__ void bfly_ct(uint32_t &x, uint32_t &y, uint32_t w, uint32_t wp, uint32_t q) {
+  uint32_t two_q = q << 1;
+  uint32_t a = csub(x, two_q);
+  uint32_t t = mul_shoup(y, w, wp, q);
+  x = a + t;
+  y = a + two_q - t;
+}
+
+// Harvey inverse (Gentleman-Sande) butterfly, inputs and outputs in [0, 2q).
+__device__ __forceinline__ void bfly_gs(uint32_t &x, uint32_t &y, uint32_t w, uint32_t wp, uint32_t q) {
+  uint32_t two_q = q << 1;
+  uint32_t a = x, b = y;
+  x = csub(a + b, two_q);
+  y = mul_shoup(a + two_q - b, w, wp, q);
+}
+
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ uint32_t canon4(uint32_t a, uint32_t q) { return csub(csub(a, q << 1), q); }
+
+}  // namespace ks

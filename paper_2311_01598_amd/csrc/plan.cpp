@@ -1,0 +1,247 @@
+// plan.cpp -- moduli, roots of unity and precomputed tables of a plan.
+//
+// Derivations used here (all exact integer arithmetic on the host):
+//  * primality: deterministic Miller-Rabin, bases {2, 7, 61} (exact for
+//    n < 4,759,123,141);
+//  * psi: from a generator c of Z_q^* (smallest c with c^((q-1)/f) != 1 for
+//    every prime f | q-1), psi_0 = c^((q-1)/2N) is a primitive 2N-th root;
+//    the primitive 2N-th roots are psi_0^k for odd k, the smallest is kept;
+//  * twiddles: psi^brv(i) and psi^-brv(i) for i < N with Shoup companions;
+//  * basis-conversion constants of ModUp P2 and ModDown P2 (Sec. III-B/C),
+//    with N^-1 of the preceding inverse NTT folded into the per-source
+//    constant and the factors of 2^32 that REDC removes folded in where the
+//    reduction happens (see DevPlan in plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace ks {
+
+static inline uint64_t mulm(uint64_t a, uint64_t b, uint64_t m) {
+  return (uint64_t)((unsigned __int128)a * b % m);
+}
+
+uint32_t pow_mod(uint64_t b, uint64_t e, uint32_t q) {
+  uint64_t r = 1 % q;
+  b %= q;
+  while (e) {
+    if (e & 1) r = mulm(r, b, q);
+    b = mulm(b, b, q);
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+static uint32_t inv_mod(uint32_t a, uint32_t q) {  // extended Euclid
+  int64_t t = 0, nt = 1, r = q, nr = a % q;
+  while (nr) {
+    int64_t k = r / nr;
+    int64_t tmp = t - k * nt; t = nt; nt = tmp;
+    tmp = r - k * nr; r = nr; nr = tmp;
+  }
+  if (t < 0) t += q;
+  return (uint32_t)t;
+}
+
+bool is_prime_u64(uint64_t n) {
+  if (n < 2) return false;
+  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 61ull})
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = 0;
+  while (!(d & 1)) { d >>= 1; s++; }
+  for (uint64_t a : {2ull, 7ull, 61ull}) {
+    uint64_t x = 1, b = a % n, e = d;
+    while (e) { if (e & 1) x = mulm(x, b, n); b = mulm(b, b, n); e >>= 1; }
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < s; i++) {
+      x = mulm(x, x, n);
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+int ntt_primes(uint32_t log_n, uint32_t count, uint32_t *out) {
+  const uint64_t step = 2ull << log_n;
+  uint32_t k = 0;
+  for (uint64_t c = (1ull << 30) + 1 - step; k < count; c -= step) {
+    if (c <= (1ull << 29)) return -1;
+    if (is_prime_u64(c)) out[k++] = (uint32_t)c;
+  }
+  return 0;
+}
+
+uint32_t min_root_2n(uint32_t q, uint32_t log_n) {
+  const uint64_t two_n = 2ull << log_n;
+  if (!is_prime_u64(q) || (q - 1) % two_n) return 0;
+  std::vector<uint32_t> f;
+  uint32_t m = q - 1;
+  for (uint32_t p = 2; (uint64_t)p * p <= m; p++)
+    if (m % p == 0) { f.push_back(p); while (m % p == 0) m /= p; }
+  if (m > 1) f.push_back(m);
+  uint32_t gen = 0;
+  for (uint32_t c = 2; c < q && !gen; c++) {
+    bool ok = true;
+    for (uint32_t p : f) if (pow_mod(c, (q - 1) / p, q) == 1) { ok = false; break; }
+    if (ok) gen = c;
+  }
+  const uint32_t psi0 = pow_mod(gen, (q - 1) / two_n, q);
+  const uint32_t psi0_sq = (uint32_t)mulm(psi0, psi0, q);
+  uint32_t best = psi0, cur = psi0;
+  for (uint64_t k = 1; k < two_n / 2; k++) {  // psi0^(2k+1)
+    cur = (uint32_t)mulm(cur, psi0_sq, q);
+    best = std::min(best, cur);
+  }
+  return best;
+}
+
+static inline uint32_t shoup_of(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+static inline uint2 shoup_pair(uint32_t w, uint32_t q) { return make_uint2(w, shoup_of(w, q)); }
+static inline uint32_t mont_of(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) % q); }
+static inline uint32_t bitrev(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+template <class T>
+static ks_status_t upload(Plan *pl, const std::vector<T> &h, const T **dst) {
+  void *p = nullptr;
+  size_t bytes = std::max<size_t>(h.size() * sizeof(T), 256);
+  if (hipMalloc(&p, bytes) != hipSuccess) return KS_ERR_NOMEM;
+  pl->allocs.push_back(p);
+  if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return KS_ERR_DEVICE;
+  *dst = (const T *)p;
+  return KS_OK;
+}
+
+ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
+  pl->log_n = p->log_n;
+  pl->n = 1u << p->log_n;
+  pl->num_q = p->num_q;
+  pl->dnum = p->dnum;
+  pl->alpha = (p->num_q + p->dnum - 1) / p->dnum;
+  pl->num_p = p->num_p ? p->num_p : pl->alpha;
+  pl->ntot = pl->num_q + pl->num_p;
+  const uint32_t n = pl->n, ntot = pl->ntot, L1 = pl->num_q, K = pl->num_p, A = pl->alpha;
+
+  pl->mod.resize(ntot);
+  if (p->moduli) {
+    std::copy(p->moduli, p->moduli + ntot, pl->mod.begin());
+  } else {
+    std::vector<uint32_t> pr(ntot);
+    if (ntt_primes(p->log_n, ntot, pr.data()) != 0) return KS_ERR_UNSUPPORTED;
+    for (uint32_t i = 0; i < L1; i++) pl->mod[i] = pr[K + i];
+    for (uint32_t k = 0; k < K; k++) pl->mod[L1 + k] = pr[k];
+  }
+  pl->psi.resize(ntot);
+  for (uint32_t g = 0; g < ntot; g++) {
+    pl->psi[g] = min_root_2n(pl->mod[g], p->log_n);
+    if (!pl->psi[g]) return KS_ERR_INVALID_ARG;
+  }
+  if (hipGetDevice(&pl->device) != hipSuccess) return KS_ERR_DEVICE;
+
+  // --- twiddles
+  std::vector<uint2> twf((size_t)ntot * n), twi((size_t)ntot * n);
+  std::vector<uint32_t> pw(n), pwi(n);
+  for (uint32_t g = 0; g < ntot; g++) {
+    const uint32_t q = pl->mod[g], s = pl->psi[g], si = inv_mod(s, q);
+    pw[0] = pwi[0] = 1;
+    for (uint32_t i = 1; i < n; i++) {
+      pw[i] = (uint32_t)mulm(pw[i - 1], s, q);
+      pwi[i] = (uint32_t)mulm(pwi[i - 1], si, q);
+    }
+    for (uint32_t i = 0; i < n; i++) {
+      uint32_t r = bitrev(i, p->log_n);
+      twf[(size_t)g * n + i] = shoup_pair(pw[r], q);
+      twi[(size_t)g * n + i] = shoup_pair(pwi[r], q);
+    }
+  }
+  std::vector<ModQ> mq(ntot);
+  for (uint32_t g = 0; g < ntot; g++) {
+    const uint32_t q = pl->mod[g];
+    uint32_t inv = 1;  // q^-1 mod 2^32 by Newton iteration
+    for (int i = 0; i < 5; i++) inv *= 2u - q * inv;
+    mq[g] = ModQ{q, (uint32_t)(0u - inv), (uint32_t)((1ull << 32) / q), 0};
+  }
+
+  // --- ModUp basis conversion (per digit j and digit size s)
+  std::vector<uint2> up_pre((size_t)pl->dnum * A * A, make_uint2(0, 0));
+  std::vector<uint32_t> up_conv((size_t)pl->dnum * A * A * ntot, 0);
+  for (uint32_t j = 0; j < pl->dnum; j++) {
+    const uint32_t lo = j * A;
+    if (lo >= L1) break;
+    const uint32_t smax = std::min(A, L1 - lo);
+    for (uint32_t s = 1; s <= smax; s++) {
+      for (uint32_t i = 0; i < s; i++) {
+        const uint32_t qi = pl->mod[lo + i];
+        uint64_t hat = 1;  // qhat_i mod q_i
+        for (uint32_t i2 = 0; i2 < s; i2++)
+          if (i2 != i) hat = mulm(hat, pl->mod[lo + i2] % qi, qi);
+        uint32_t c = (uint32_t)mulm(inv_mod((uint32_t)hat, qi), inv_mod(n % qi, qi), qi);
+        const size_t row = ((size_t)j * A + (s - 1)) * A + i;
+        up_pre[row] = shoup_pair(c, qi);
+        for (uint32_t g = 0; g < ntot; g++) {
+          const uint32_t m = pl->mod[g];
+          uint64_t h = 1;
+          for (uint32_t i2 = 0; i2 < s; i2++)
+            if (i2 != i) h = mulm(h, pl->mod[lo + i2] % m, m);
+          up_conv[row * ntot + g] = mont_of((uint32_t)h, m);
+        }
+      }
+    }
+  }
+  // --- ModDown
+  std::vector<uint2> dn_pre(K), dn_fin(L1);
+  std::vector<uint32_t> dn_conv((size_t)K * L1);
+  for (uint32_t k = 0; k < K; k++) {
+    const uint32_t pk = pl->mod[L1 + k];
+    uint64_t hat = 1;
+    for (uint32_t k2 = 0; k2 < K; k2++)
+      if (k2 != k) hat = mulm(hat, pl->mod[L1 + k2] % pk, pk);
+    uint32_t c = (uint32_t)mulm(inv_mod((uint32_t)hat, pk), inv_mod(n % pk, pk), pk);
+    dn_pre[k] = shoup_pair(mont_of(c, pk), pk);
+    for (uint32_t i = 0; i < L1; i++) {
+      const uint32_t qi = pl->mod[i];
+      uint64_t h = 1;
+      for (uint32_t k2 = 0; k2 < K; k2++)
+        if (k2 != k) h = mulm(h, pl->mod[L1 + k2] % qi, qi);
+      dn_conv[(size_t)k * L1 + i] = (uint32_t)h;
+    }
+  }
+  for (uint32_t i = 0; i < L1; i++) {
+    const uint32_t qi = pl->mod[i];
+    uint64_t P = 1;
+    for (uint32_t k = 0; k < K; k++) P = mulm(P, pl->mod[L1 + k] % qi, qi);
+    dn_fin[i] = shoup_pair(mont_of(inv_mod((uint32_t)P, qi), qi), qi);
+  }
+
+  DevPlan &d = pl->dev;
+  ks_status_t st;
+  if ((st = upload(pl, twf, &d.tw_fwd)) || (st = upload(pl, twi, &d.tw_inv)) || (st = upload(pl, mq, &d.mods)) ||
+      (st = upload(pl, up_pre, &d.up_pre)) || (st = upload(pl, up_conv, &d.up_conv)) ||
+      (st = upload(pl, dn_pre, &d.dn_pre)) || (st = upload(pl, dn_conv, &d.dn_conv)) ||
+      (st = upload(pl, dn_fin, &d.dn_fin)))
+    return st;
+  d.log_n = p->log_n;
+  d.logb = kRowLog;
+  d.loga = p->log_n - kRowLog;
+  d.num_q = L1;
+  d.num_p = K;
+  d.dnum = pl->dnum;
+  d.alpha = A;
+  d.ntot = ntot;
+  return KS_OK;
+}
+
+void plan_free(Plan *pl) {
+  for (void *p : pl->allocs) (void)hipFree(p);
+  pl->allocs.clear();
+}
+
+}  // namespace ks

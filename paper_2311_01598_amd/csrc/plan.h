@@ -1,0 +1,76 @@
+// plan.h -- host-side plan of a key-switching parameter set and the device
+// view of its precomputed tables.
+//
+// Tower numbering.  Global index g in [0, num_q + num_p): g <= L is q_g,
+// g = L+1+k is p_k -- the limb order of the evaluation key.  At level l the
+// extended basis D_l has T = l+1+K towers; tower t < l+1 is q_t (g = t) and
+// tower t >= l+1 is p_{t-l-1} (g = L+1+t-l-1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "modarith.h"
+
+namespace ks {
+
+constexpr uint32_t kMaxTowers = 128;  // num_q + num_p
+constexpr uint32_t kRowLog = 8;       // NTT row length 2^8 (second pass)
+
+// Device view of a plan: plain pointers and scalars, passed by value.
+struct DevPlan {
+  const uint2 *tw_fwd;   // [ntot][N] (psi^brv(i), Shoup companion)
+  const uint2 *tw_inv;   // [ntot][N] (psi^-brv(i), Shoup companion)
+  const ModQ *mods;      // [ntot]
+  // ModUp basis conversion, digit j holding s towers (the last digit of a
+  // lower level may be partial):
+  //   up_pre [(j*alpha + s-1)*alpha + i]          Shoup pair of N^-1 [qhat_i^-1]_{q_i}
+  //   up_conv[((j*alpha + s-1)*alpha + i)*ntot + g] [qhat_i]_{m_g} * 2^32 mod m_g
+  const uint2 *up_pre;
+  const uint32_t *up_conv;
+  // ModDown: dn_pre[k]  Shoup pair of N^-1 2^32 [phat_k^-1]_{p_k}
+  //          dn_conv[k*num_q + i]  [phat_k]_{q_i}
+  //          dn_fin[i]  Shoup pair of 2^32 [P^-1]_{q_i}
+  const uint2 *dn_pre;
+  const uint32_t *dn_conv;
+  const uint2 *dn_fin;
+  uint32_t log_n, loga, logb;  // N = 2^log_n = 2^loga columns-length x 2^logb row-length
+  uint32_t num_q, num_p, dnum, alpha, ntot;
+};
+
+struct Plan {
+  uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
+  int device = -1;
+  std::vector<uint32_t> mod;  // global order
+  std::vector<uint32_t> psi;
+  DevPlan dev{};
+  std::vector<void *> allocs;
+  ks_config_t cfg{};
+  std::mutex lock;  // guards the graph cache and config
+  void *graph_cache = nullptr;
+};
+
+// Number theory used by the plan (independent of any test oracle).
+bool is_prime_u64(uint64_t n);
+int ntt_primes(uint32_t log_n, uint32_t count, uint32_t *out);
+uint32_t min_root_2n(uint32_t q, uint32_t log_n);
+uint32_t pow_mod(uint64_t b, uint64_t e, uint32_t q);
+
+ks_status_t plan_build(const ks_params_t *p, Plan *pl);
+void plan_free(Plan *pl);
+
+// Tower helpers.
+inline uint32_t tower_g(const Plan &pl, uint32_t level, uint32_t t) {
+  return t <= level ? t : pl.num_q + (t - level - 1);
+}
+inline uint32_t num_digits(const Plan &pl, uint32_t level) { return (level + pl.alpha) / pl.alpha; }
+inline void digit_range(const Plan &pl, uint32_t level, uint32_t j, uint32_t *lo, uint32_t *hi) {
+  *lo = j * pl.alpha;
+  uint32_t h = (j + 1) * pl.alpha;
+  *hi = h > level + 1 ? level + 1 : h;
+}
+
+}  // namespace ks

@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library loads, exports every entry point declared in include/ks.h, and
+its own derivation of moduli and roots of unity agrees with the oracle's
+independent one (trial division / brute-force root search).  Argument errors
+that are decided before any device work return the documented status.
+"""
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ks = pytest.importorskip("paper_2311_01598_amd")
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ks.h")).read()
+    declared = set(re.findall(r"\b(ks_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    assert declared == set(ks.EXPORTS)
+    for name in declared:
+        assert hasattr(ks.lib(), name), name
+
+
+@pytest.mark.parametrize("shape", [(12, 4, 2, 2), (16, 24, 3, 8), (14, 10, 3, 0), (17, 48, 3, 16), (15, 26, 3, 7)])
+def test_moduli_match_oracle(shape):
+    log_n, num_q, dnum, num_p = shape
+    got = ks.ks_params_moduli(log_n, num_q, dnum, num_p)
+    want = [int(x) for x in oracle.moduli(oracle.Params(log_n, num_q, dnum, num_p))]
+    assert got == want
+
+
+@pytest.mark.parametrize("log_n", [12, 14, 16, 17])
+def test_roots_match_oracle(log_n):
+    for q in oracle.gen_primes(log_n, 4):
+        assert ks.ks_root_of_unity(int(q), log_n) == oracle.min_psi(int(q), log_n)
+
+
+def test_root_rejects_bad_modulus():
+    assert ks.ks_root_of_unity(1 << 30, 12) == 0            # not prime
+    q = int(oracle.gen_primes(12, 1)[0])
+    assert ks.ks_root_of_unity(q, 17) == 0 or (q - 1) % (2 << 17) == 0
+
+
+def test_explicit_moduli_validation():
+    good = ks.ks_params_moduli(12, 4, 2, 2)
+    assert ks.ks_params_moduli(12, 4, 2, 2, moduli=good) == good
+    bad_dup = list(good)
+    bad_dup[1] = bad_dup[0]
+    bad_comp = list(good)
+    bad_comp[0] = good[0] + 2 * 4096   # same residue class, composite or not 2N-friendly prime
+    for bad in (bad_dup, [m + 1 for m in good], [3] + good[1:]):
+        with pytest.raises(ks.KsError) as e:
+            ks.ks_params_moduli(12, 4, 2, 2, moduli=bad)
+        assert e.value.status == ks.KS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("shape,status", [((11, 4, 2, 2), "KS_ERR_UNSUPPORTED"), ((18, 4, 2, 2), "KS_ERR_UNSUPPORTED"),
+                                          ((12, 0, 1, 1), "KS_ERR_INVALID_ARG"), ((12, 4, 5, 1), "KS_ERR_INVALID_ARG"),
+                                          ((12, 4, 0, 1), "KS_ERR_INVALID_ARG"), ((16, 100, 1, 0), "KS_ERR_UNSUPPORTED")])
+def test_plan_rejects_bad_params_before_device_work(shape, status):
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_plan_create(*shape)
+    assert e.value.status == getattr(ks, status)
+
+
+def test_status_strings():
+    for s in range(6):
+        assert ks.ks_status_string(s)

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP key switch against the CPU oracle, bit for bit.
+
+All arithmetic is exact modular integer arithmetic, so the bar is equality
+of every output word (tolerance 0).  Cases cover the plain single-ciphertext
+workload at every level, the N=2^16 / 24-tower / dnum 3 workload at full size
+(every element compared), partial last digits, dnum = 1, K != alpha, a zero
+input, a decryption check of the GPU output, and the NTT stage alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_01598_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+SCHEDS = ["mp", "dc", "oc"]
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16, 17])
+def test_ntt_matches_oracle(ks, log_n):
+    say(f"[ntt] log_n={log_n}")
+    plan = ks.Plan(log_n, 3, 1, 2)
+    n = 1 << log_n
+    mods = plan.moduli
+    a = synth.uniform_limbs(mods, n, seed=log_n)
+    d = dev(a)
+    plan.ntt(d, range(len(mods)), inverse=False)
+    torch.cuda.synchronize()
+    got = host(d)
+    for r, q in enumerate(mods):
+        assert np.array_equal(got[r], oracle.ntt(a[r], q)), (log_n, r)
+    plan.ntt(d, range(len(mods)), inverse=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(d), a)
+    plan.close()
+
+
+def _run(ks, plan, sched, evk_d, level, d, **cfg):
+    plan.configure(sched, **cfg)
+    out = plan.keyswitch(evk_d, level, dev(d))
+    torch.cuda.synchronize()
+    return host(out)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_plain_workload_all_levels_and_decrypts(ks, level):
+    """N=2^12, l+1 = 4, dnum 2, K 2, real RLWE keys."""
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    s, s2, evk, h = oracle.keygen(p, mods, seed=1234)
+    plan = ks.Plan(12, 4, 2, 2)
+    assert plan.moduli == [int(x) for x in mods]
+    evk_d = dev(evk)
+    d = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(1, level))
+    want = oracle.keyswitch(p, mods, level, evk, d)
+    for sched in SCHEDS:
+        say(f"[plain] level={level} sched={sched}")
+        got = _run(ks, plan, sched, evk_d, level, d)
+        assert np.array_equal(got, want), (sched, level, np.argwhere(got != want)[:5])
+    r = oracle.decrypt_residual(p, mods, level, d, got, s, s2)
+    assert max(abs(v) for v in r) <= oracle.noise_bound(p, mods, level, h)
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def big_case():
+    p = oracle.Params(16, 24, 3, 8)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 3, p.n, synth.seed_for(2, 0))
+    d = synth.uniform_limbs(mods[:24], p.n, synth.seed_for(2, 1))
+    want = oracle.keyswitch(p, mods, 23, evk, d)
+    return p, mods, evk, d, want
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_full_size_n16_l24_dnum3(ks, big_case, sched):
+    """The N=2^16, l+1=24, dnum 3, K 8 workload at full size, every element."""
+    p, mods, evk, d, want = big_case
+    plan = ks.Plan(16, 24, 3, 8)
+    say(f"[n16] sched={sched}")
+    got = _run(ks, plan, sched, dev(evk), 23, d)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (sched, bad[:5], len(bad))
+    plan.close()
+
+
+@pytest.mark.parametrize("tile", [2, 4])
+def test_oc_tiles_n16(ks, big_case, tile):
+    p, mods, evk, d, want = big_case
+    plan = ks.Plan(16, 24, 3, 8)
+    say(f"[n16] oc tile={tile}")
+    got = _run(ks, plan, "oc", dev(evk), 23, d, tile_towers=tile)
+    assert np.array_equal(got, want)
+    plan.close()
+
+
+SHAPES = [
+    # (log_n, num_q, dnum, num_p, levels)
+    (13, 5, 2, 0, [4, 2]),        # partial last digit
+    (12, 4, 1, 0, [3, 1]),        # dnum = 1
+    (14, 9, 3, 2, [8, 5]),        # K != alpha
+    (15, 7, 7, 1, [6, 3]),        # alpha = 1
+    (17, 6, 2, 3, [5]),           # N = 2^17, two-pass 512 x 256
+    (12, 20, 2, 0, [19, 10]),     # alpha = 10 sources
+]
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,levels", SHAPES)
+def test_shapes(ks, log_n, num_q, dnum, num_p, levels):
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, dnum, p.n, seed=log_n * 7 + num_q)
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    evk_d = dev(evk)
+    for level in levels:
+        d = synth.uniform_limbs(mods[:level + 1], p.n, seed=level + 100)
+        want = oracle.keyswitch(p, mods, level, evk, d)
+        for sched in SCHEDS:
+            say(f"[shape] {p} level={level} sched={sched}")
+            got = _run(ks, plan, sched, evk_d, level, d)
+            assert np.array_equal(got, want), (sched, level)
+    plan.close()
+
+
+def test_zero_input_gives_zero(ks):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 2, p.n, seed=3)
+    plan = ks.Plan(12, 4, 2, 2)
+    for sched in SCHEDS:
+        say(f"[zero] sched={sched}")
+        got = _run(ks, plan, sched, dev(evk), 3, np.zeros((4, p.n), np.uint32))
+        assert not got.any()
+    plan.close()
+
+
+def test_batch_equals_single(ks):
+    p = oracle.Params(13, 6, 3, 2)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 3, p.n, seed=5)
+    plan = ks.Plan(13, 6, 3, 2)
+    evk_d = dev(evk)
+    levels = [5, 2, 0, 4, 3, 5]
+    ins = [dev(synth.uniform_limbs(mods[:l + 1], p.n, seed=50 + i)) for i, l in enumerate(levels)]
+    for sched in SCHEDS:
+        say(f"[batch] sched={sched}")
+        plan.configure(sched)
+        outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in levels]
+        plan.keyswitch_batch([(evk_d, l, i, o) for l, i, o in zip(levels, ins, outs)])
+        torch.cuda.synchronize()
+        for l, i, o in zip(levels, ins, outs):
+            want = oracle.keyswitch(p, mods, l, evk, host(i))
+            assert np.array_equal(host(o), want), (sched, l)
+    plan.close()
+
+
+def test_error_paths(ks):
+    plan = ks.Plan(12, 4, 2, 2)
+    n = plan.n
+    evk = torch.zeros((2, 2, 6, n), dtype=torch.int32, device="cuda")
+    d = torch.zeros((4, n), dtype=torch.int32, device="cuda")
+    out = torch.empty((2, 4, n), dtype=torch.int32, device="cuda")
+    ws = plan.workspace([3])
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_keyswitch(plan.handle, evk, 4, d, out, ws)      # level > L
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_keyswitch(plan.handle, evk, 3, d, out, ws, workspace_bytes=64)
+    assert e.value.status == ks.KS_ERR_BUDGET
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_keyswitch(plan.handle, evk, 3, d, d, ws)        # out aliases in
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_keyswitch(plan.handle, None, 3, d, out, ws)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_plan_set_config(plan.handle, 9)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    plan.close()
