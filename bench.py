@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark: hybrid key switching on one MI355X.
+
+Workload: N = 2^16, l+1 = 24 towers of 30-bit primes, dnum = 3 (alpha 8),
+K = 8 special primes, uint32 residues; seeded uniform inputs and keys (key
+switching is data-oblivious, so values do not change the timing).  A step is
+one key switch of one polynomial through every stage (ModUp P1-P5, ModDown
+P1-P4) with the plan's primary schedule (Output-Centric).  To make the key
+stream from HBM instead of the 256 MB last-level cache, consecutive steps
+rotate over `--evk-copies` distinct keys (48 MiB each).
+
+Prints one JSON line (see the contract in the project documentation).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LOG_N, NUM_Q, DNUM, NUM_P, LEVEL = 16, 24, 3, 8, 23
+HBM_PEAK_GBS = 8000.0
+# 32-bit integer multiplies (v_mul_lo_u32, v_mul_hi_u32, v_mad_u64_u32) issue
+# at the FP64 vector rate, 64 lanes per clock per CU: 256 CUs x 64 x 2.4 GHz.
+MUL_PEAK_PER_S = 256 * 64 * 2.4e9
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_oc_n16_l24_dnum3.json")
+
+
+def alg_bytes(n, l1, k, ndig):
+    """Algorithmic HBM bytes of one key switch: input, key limbs read, output."""
+    return 4 * n * (l1 + 2 * ndig * (l1 + k) + 2 * l1)
+
+
+def stage_muls(log_n, l1, k, alpha):
+    """Algorithmic 32-bit multiplies per launch of each Output-Centric stage.
+
+    Counted per the method's arithmetic: a Shoup product (twiddle, constant)
+    is 3 multiplies, a 32x32+64 multiply-accumulate 1, a REDC reduction of a
+    64-bit sum 4; a length-2^s transform pass has s * N/2 butterflies."""
+    n, a, b = 1 << log_n, log_n - 8, 8
+    t = l1 + k
+    sizes = [min(alpha, l1 - lo) for lo in range(0, l1, alpha)]
+    ndig = len(sizes)
+    col_ntt, row_ntt = 3 * a * n // 2, 3 * b * n // 2
+    return {
+        "ntt.row.inv": l1 * row_ntt,
+        "oc.intt_col.up": l1 * (col_ntt + 3 * n),
+        "oc.bconv_col.up": sum((t - s) * (n * (s + 4) + col_ntt) for s in sizes),
+        "oc.row.p": k * (ndig * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt),
+        "oc.intt_col.down": 2 * k * (col_ntt + 3 * n),
+        "oc.bconv_col.down": 2 * l1 * (n * (k + 4) + col_ntt),
+        "oc.row.q": l1 * ((ndig - 1) * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt + 2 * 3 * n),
+    }
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2311_01598_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--evk-copies", type=int, default=8)
+    ap.add_argument("--schedule", default="oc", choices=["oc", "mp", "dc"])
+    ap.add_argument("--compare", action="store_true", help="also time the other schedules")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle key switches in the CPU sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy 3 times (counter calibration) and exit")
+    ap.add_argument("--rates", action="store_true", help="also run the ALU / copy rate probes")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); "
+              "multi-GPU key switching is a design note, not part of this build.", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_2311_01598_amd as ks
+    import synth
+
+    torch.cuda.init()
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch_read": a.numel() * 4, "written": b.numel() * 4}))
+        return 0
+    plan = ks.Plan(LOG_N, NUM_Q, DNUM, NUM_P)
+    n, l1 = plan.n, LEVEL + 1
+    ndig = -(-l1 // plan.alpha)
+    mods = plan.moduli
+    evks = [torch.from_numpy(synth.uniform_evk(mods, DNUM, n, synth.seed_for(2, 100 + c)).view(np.int32)).cuda()
+            for c in range(args.evk_copies)]
+    d = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 1)).view(np.int32)).cuda()
+    out = torch.empty((2, l1, n), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(schedule, steps, warmup, lat=None):
+        plan.configure(schedule)
+        ws = plan.workspace([LEVEL])
+        for i in range(warmup):
+            plan.keyswitch(evks[i % len(evks)], LEVEL, d, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if lat is not None else None
+        t0 = time.perf_counter()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for i in range(steps):
+            if ev:
+                ev[i].record(stream)
+            plan.keyswitch(evks[i % len(evks)], LEVEL, d, out=out, workspace=ws)
+        if ev:
+            ev[steps].record(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop)
+        if ev is not None:
+            lat.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+        return ms, wall
+
+    lat = []
+    ms, wall = run(args.schedule, args.steps, args.warmup, lat)
+    # Per-kernel durations: the same K steps again with start/stop events
+    # attached to every kernel dispatch (kept out of the timed region above,
+    # because the traced launch path costs host time between kernels).
+    ks.ks_trace_enable(plan.handle, True)
+    run(args.schedule, args.steps, 0)
+    ks.ks_trace_enable(plan.handle, False)
+    trace = ks.ks_trace_read(plan.handle)
+    ks_per_s = args.steps / (ms / 1e3)
+    nbytes = alg_bytes(n, l1, NUM_P, ndig)
+    lat.sort()
+    res = {
+        "metric": "key-switches/sec (N=2^16, l+1=24, dnum=3)",
+        "value": round(ks_per_s, 1),
+        "unit": "key-switches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded uniform residues and keys)",
+        "config": {"workload": "hybrid key switch, N=2^16, l+1=24, dnum=3, alpha=8, K=8, 1 ciphertext per call",
+                   "schedule": args.schedule, "evk_copies": args.evk_copies},
+        "hbm_gbs_algorithmic": round(nbytes * ks_per_s / 1e9, 1),
+        "latency_ms": {"p50": round(lat[len(lat) // 2], 4), "p99": round(lat[min(len(lat) - 1, int(len(lat) * 0.99))], 4)},
+    }
+    muls = stage_muls(LOG_N, l1, NUM_P, plan.alpha)
+    stages = {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(v[0], 1), 3)} for k, v in trace.items()}
+    dom = max((k for k in trace if k in muls), key=lambda k: trace[k][1] / max(trace[k][0], 1))
+    dom_s = 1e-3 * trace[dom][1] / trace[dom][0]
+    achieved = muls[dom] / dom_s
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        prof = json.load(open(PROFILE_TRAFFIC))
+        if prof.get("source_digest") == kernel_source_digest() and dom in prof.get("kernels", {}):
+            traffic = prof["kernels"][dom]["bytes_per_launch"]
+    res["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 4),
+                       "peak": round(MUL_PEAK_PER_S / 1e12, 4), "unit": "Tmul/s (32-bit integer multiplies)",
+                       "frac": round(achieved / MUL_PEAK_PER_S, 4), "traffic": traffic,
+                       "avg_us": round(dom_s * 1e6, 3), "muls_per_launch": muls[dom]}
+    tot_muls = sum(muls.values())
+    res["whole_keyswitch"] = {"muls": tot_muls, "mul_frac": round(tot_muls * ks_per_s / MUL_PEAK_PER_S, 4),
+                              "hbm_frac": round(nbytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
+    res["stages"] = stages
+    if args.rates:
+        res["device_rates"] = {k: round(v / 1e12, 4) for k, v in ks.ks_device_rates().items()}
+    if args.compare:
+        res["schedules"] = {}
+        for sch in ("mp", "dc", "oc"):
+            ms2, _ = run(sch, max(20, args.steps // 4), 5)
+            res["schedules"][sch] = round(max(20, args.steps // 4) / (ms2 / 1e3), 1)
+    if not args.no_cpu:
+        import oracle
+        op = oracle.Params(LOG_N, NUM_Q, DNUM, NUM_P)
+        om = oracle.moduli(op)
+        evk_h = synth.uniform_evk(om, DNUM, n, synth.seed_for(2, 100))
+        d_h = synth.uniform_limbs(om[:l1], n, synth.seed_for(2, 1))
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_sample):
+            oracle.keyswitch(op, om, LEVEL, evk_h, d_h)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(args.cpu_sample / dt, 4), "unit": "key-switches/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{args.cpu_sample} key switches of the same workload, single thread"}
+    print(json.dumps(res), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -140,6 +140,25 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
 ks_status_t ks_ntt(ks_plan_t plan, uint32_t count, const uint32_t *g, int inverse,
                    uint32_t *data, void *stream);
 
+/* Tracing for tools (not part of the method): while enabled, the plan
+ * records a HIP event on the launch stream before every kernel it enqueues
+ * and one after each key switch, so event-to-event intervals time each
+ * kernel on the stream it runs on.  Enabling clears nothing; reading
+ * synchronises on the last event, returns per stage name the number of
+ * launches and total milliseconds (up to `max` entries, `*count` = number of
+ * distinct names) and clears the record.  names[i] are static strings. */
+ks_status_t ks_trace_enable(ks_plan_t plan, int on);
+ks_status_t ks_trace_read(ks_plan_t plan, uint32_t max, const char **names, uint32_t *launches,
+                          double *total_ms, uint32_t *count);
+
+/* Roofline probes for tools: on the current device, lane-operations per
+ * second of long independent chains of single instructions v_add_u32,
+ * v_mul_lo_u32, v_mul_hi_u32, v_mad_u64_u32, v_fma_f64 (out[0..4]), the
+ * bytes per second of a 1 GiB device-to-device copy kernel (out[5], read +
+ * write), and lazy modular butterflies per second (out[6]).  out must hold 7
+ * doubles.  Allocates and frees 2 GiB of device memory; synchronous. */
+ks_status_t ks_device_rates(double *out, void *stream);
+
 const char *ks_status_string(ks_status_t s);
 
 #ifdef __cplusplus

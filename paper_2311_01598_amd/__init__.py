@@ -56,9 +56,19 @@ _SIGS = {
     "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
                                           _VP]),
     "ks_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
+    "ks_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "ks_trace_read": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_char_p), _U32P,
+                                     ctypes.POINTER(ctypes.c_double), _U32P]),
+    "ks_device_rates": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _VP]),
     "ks_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
+
+# PyTorch ships its own HIP runtime under the same soname as the system one
+# libks.so links against.  Loading torch first makes libks.so bind to that
+# already-loaded runtime, so the process has exactly one HIP runtime and
+# torch's tensors and streams are valid handles for the library.
+import torch  # noqa: E402,F401
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
@@ -188,6 +198,29 @@ def ks_keyswitch_batch(plan, jobs, workspace, workspace_bytes=None, stream=None)
 def ks_ntt(plan, g, inverse, data, stream=None):
     arr = _u32_array(g)
     _check(_lib.ks_ntt(plan, len(g), arr, int(bool(inverse)), _ptr(data), _stream(stream)), "ks_ntt")
+
+
+def ks_trace_enable(plan, on=True):
+    _check(_lib.ks_trace_enable(plan, int(bool(on))), "ks_trace_enable")
+
+
+def ks_trace_read(plan, max_names=64):
+    """{stage name: (launches, total ms)} recorded since the last read."""
+    names = (ctypes.c_char_p * max_names)()
+    launches = (ctypes.c_uint32 * max_names)()
+    ms = (ctypes.c_double * max_names)()
+    count = ctypes.c_uint32()
+    _check(_lib.ks_trace_read(plan, max_names, names, launches, ms, ctypes.byref(count)), "ks_trace_read")
+    return {names[i].decode(): (launches[i], ms[i]) for i in range(min(count.value, max_names))}
+
+
+RATE_NAMES = ("add_u32", "mul_lo_u32", "mul_hi_u32", "mad_u64_u32", "fma_f64", "copy_bytes", "butterfly")
+
+
+def ks_device_rates(stream=None):
+    out = (ctypes.c_double * 7)()
+    _check(_lib.ks_device_rates(out, _stream(stream)), "ks_device_rates")
+    return dict(zip(RATE_NAMES, list(out)))
 
 
 class Plan:

@@ -139,11 +139,13 @@ ks_status_t run_oc(const Plan &pl, const uint32_t *evk, uint32_t level, const ui
 
 ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint32_t level, const uint32_t *d,
                     uint32_t *out, uint32_t *ws, hipStream_t st) {
+  ks_status_t r;
   switch (sch) {
-    case KS_SCHED_MP: return run_mp(pl, evk, level, d, out, ws, st);
-    case KS_SCHED_DC: return run_dc(pl, evk, level, d, out, ws, st);
-    default: return run_oc(pl, evk, level, d, out, ws, st);
+    case KS_SCHED_MP: r = run_mp(pl, evk, level, d, out, ws, st); break;
+    case KS_SCHED_DC: r = run_dc(pl, evk, level, d, out, ws, st); break;
+    default: r = run_oc(pl, evk, level, d, out, ws, st); break;
   }
+  return r;
 }
 
 ks_status_t check_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *in, const uint32_t *out,
@@ -354,6 +356,45 @@ ks_status_t ks_ntt(ks_plan_t plan, uint32_t count, const uint32_t *g, int invers
     TRY(launch_finish_ntt(pl, inverse != 0, data, L, st));
   }
   return KS_OK;
+}
+
+ks_status_t ks_trace_enable(ks_plan_t plan, int on) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  Trace &t = plan->p.trace;
+  std::lock_guard<std::mutex> g(t.mu);
+  t.on = on != 0;
+  return KS_OK;
+}
+
+ks_status_t ks_trace_read(ks_plan_t plan, uint32_t max, const char **names, uint32_t *launches, double *total_ms,
+                          uint32_t *count) {
+  if (!plan || !count || (max && (!names || !launches || !total_ms))) return KS_ERR_INVALID_ARG;
+  Trace &t = plan->p.trace;
+  std::lock_guard<std::mutex> g(t.mu);
+  std::vector<const char *> nm;
+  std::vector<uint32_t> ln;
+  std::vector<double> ms;
+  ks_status_t st = KS_OK;
+  if (!t.marks.empty() && hipEventSynchronize(t.marks.back().stop) != hipSuccess) st = KS_ERR_DEVICE;
+  for (size_t i = 0; st == KS_OK && i < t.marks.size(); i++) {
+    const char *name = t.marks[i].stage;
+    float e = 0;
+    if (hipEventElapsedTime(&e, t.marks[i].start, t.marks[i].stop) != hipSuccess) { st = KS_ERR_DEVICE; break; }
+    size_t k = 0;
+    while (k < nm.size() && std::strcmp(nm[k], name) != 0) k++;
+    if (k == nm.size()) { nm.push_back(name); ln.push_back(0); ms.push_back(0); }
+    ln[k]++;
+    ms[k] += e;
+  }
+  for (auto &m : t.marks) { t.pool.push_back(m.start); t.pool.push_back(m.stop); }
+  t.marks.clear();
+  *count = (uint32_t)nm.size();
+  for (uint32_t k = 0; k < nm.size() && k < max; k++) {
+    names[k] = nm[k];
+    launches[k] = ln[k];
+    total_ms[k] = ms[k];
+  }
+  return st;
 }
 
 }  // extern "C"

@@ -94,15 +94,15 @@ static hipError_t col_dispatch(const Plan &pl, const uint32_t *src, uint32_t *ds
   if (W == 32 || (A <= 5 && W > 8)) {
     constexpr int Wc = 32;
     dim3 grid(cols / Wc, L.count);
-    hipLaunchKernelGGL((k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.col.inv" : "ntt.col.fwd", (k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
   } else if (W == 16) {
     constexpr int Wc = 16;
     dim3 grid(cols / Wc, L.count);
-    hipLaunchKernelGGL((k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.col.inv" : "ntt.col.fwd", (k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
   } else {
     constexpr int Wc = 8;
     dim3 grid(cols / Wc, L.count);
-    hipLaunchKernelGGL((k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.col.inv" : "ntt.col.fwd", (k_col<INV, A, Wc>), grid, dim3(Wc * SubNtt<A>::TPS), 0, st, pl.dev, src, dst, L);
   }
   return hipGetLastError();
 }
@@ -133,11 +133,11 @@ static hipError_t row_launch(const Plan &pl, const uint32_t *src, uint32_t *dst,
   uint32_t RB = pl.cfg.row_block ? pl.cfg.row_block : 8;
   if (RB > rows) RB = rows;
   if (RB >= 16) {
-    hipLaunchKernelGGL((k_row<INV, 16>), dim3(rows / 16, L.count), dim3(256), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.row.inv" : "ntt.row.fwd", (k_row<INV, 16>), dim3(rows / 16, L.count), dim3(256), 0, st, pl.dev, src, dst, L);
   } else if (RB >= 8) {
-    hipLaunchKernelGGL((k_row<INV, 8>), dim3(rows / 8, L.count), dim3(128), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.row.inv" : "ntt.row.fwd", (k_row<INV, 8>), dim3(rows / 8, L.count), dim3(128), 0, st, pl.dev, src, dst, L);
   } else {
-    hipLaunchKernelGGL((k_row<INV, 4>), dim3(rows / 4, L.count), dim3(64), 0, st, pl.dev, src, dst, L);
+    KS_LAUNCH(pl, INV ? "ntt.row.inv" : "ntt.row.fwd", (k_row<INV, 4>), dim3(rows / 4, L.count), dim3(64), 0, st, pl.dev, src, dst, L);
   }
   return hipGetLastError();
 }
@@ -150,7 +150,7 @@ hipError_t launch_row(const Plan &pl, bool inverse, const uint32_t *src, uint32_
 
 hipError_t launch_finish_ntt(const Plan &pl, bool inverse, uint32_t *data, const LimbList &L, hipStream_t st) {
   if (!L.count) return hipSuccess;
-  hipLaunchKernelGGL(k_finish, dim3((pl.n + 255) / 256, L.count), dim3(256), 0, st, pl.dev, inverse, data, L);
+  KS_LAUNCH(pl, "ntt.finish", k_finish, dim3((pl.n + 255) / 256, L.count), dim3(256), 0, st, pl.dev, inverse, data, L);
   return hipGetLastError();
 }
 
@@ -225,13 +225,13 @@ hipError_t launch_bconv_up(const Plan &pl, uint32_t level, uint32_t j0, uint32_t
                                 const uint32_t *x, uint32_t *y, hipStream_t st) {
   dim3 grid((pl.n + 255) / 256, nd);
   if (pl.alpha <= 4)
-    hipLaunchKernelGGL((k_bconv_up<4>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
+    KS_LAUNCH(pl, "bconv.up", (k_bconv_up<4>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
   else if (pl.alpha <= 8)
-    hipLaunchKernelGGL((k_bconv_up<8>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
+    KS_LAUNCH(pl, "bconv.up", (k_bconv_up<8>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
   else if (pl.alpha <= 16)
-    hipLaunchKernelGGL((k_bconv_up<16>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
+    KS_LAUNCH(pl, "bconv.up", (k_bconv_up<16>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
   else if (pl.alpha <= 32)
-    hipLaunchKernelGGL((k_bconv_up<32>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
+    KS_LAUNCH(pl, "bconv.up", (k_bconv_up<32>), grid, dim3(256), 0, st, pl.dev, level, j0, digit_rel, x, y);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_keymul(DevPlan P, uint32_t level, const
 hipError_t launch_keymul(const Plan &pl, uint32_t level, const uint32_t *d, const uint32_t *y, const uint32_t *evk,
                          uint32_t *z, hipStream_t st) {
   const uint32_t T = level + 1 + pl.num_p, D = num_digits(pl, level);
-  hipLaunchKernelGGL(k_keymul, dim3((pl.n + 255) / 256, T, D * 2), dim3(256), 0, st, pl.dev, level, d, y, evk, z);
+  KS_LAUNCH(pl, "keymul", k_keymul, dim3((pl.n + 255) / 256, T, D * 2), dim3(256), 0, st, pl.dev, level, d, y, evk, z);
   return hipGetLastError();
 }
 
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_reduce_digits(DevPlan P, uint32_t level
 
 hipError_t launch_reduce_digits(const Plan &pl, uint32_t level, const uint32_t *z, uint32_t *acc, hipStream_t st) {
   const uint32_t T = level + 1 + pl.num_p, D = num_digits(pl, level);
-  hipLaunchKernelGGL(k_reduce_digits, dim3((pl.n + 255) / 256, T, 2), dim3(256), 0, st, pl.dev, level, D, z, acc);
+  KS_LAUNCH(pl, "reduce_digits", k_reduce_digits, dim3((pl.n + 255) / 256, T, 2), dim3(256), 0, st, pl.dev, level, D, z, acc);
   return hipGetLastError();
 }
 
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_keymac_digit(DevPlan P, uint32_t level,
 hipError_t launch_keymac_digit(const Plan &pl, uint32_t level, uint32_t j, const uint32_t *d, const uint32_t *yj,
                                const uint32_t *evk, uint32_t *acc, hipStream_t st) {
   const uint32_t T = level + 1 + pl.num_p;
-  hipLaunchKernelGGL(k_keymac_digit, dim3((pl.n + 255) / 256, T, 2), dim3(256), 0, st, pl.dev, level, j, d, yj, evk,
+  KS_LAUNCH(pl, "keymac_digit", k_keymac_digit, dim3((pl.n + 255) / 256, T, 2), dim3(256), 0, st, pl.dev, level, j, d, yj, evk,
                      acc);
   return hipGetLastError();
 }
@@ -344,13 +344,13 @@ __global__ __launch_bounds__(256) void k_bconv_down(DevPlan P, uint32_t level, c
 hipError_t launch_bconv_down(const Plan &pl, uint32_t level, const uint32_t *xp, uint32_t *w, hipStream_t st) {
   dim3 grid((pl.n + 255) / 256, 2);
   if (pl.num_p <= 4)
-    hipLaunchKernelGGL((k_bconv_down<4>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
+    KS_LAUNCH(pl, "bconv.down", (k_bconv_down<4>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
   else if (pl.num_p <= 8)
-    hipLaunchKernelGGL((k_bconv_down<8>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
+    KS_LAUNCH(pl, "bconv.down", (k_bconv_down<8>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
   else if (pl.num_p <= 16)
-    hipLaunchKernelGGL((k_bconv_down<16>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
+    KS_LAUNCH(pl, "bconv.down", (k_bconv_down<16>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
   else if (pl.num_p <= 32)
-    hipLaunchKernelGGL((k_bconv_down<32>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
+    KS_LAUNCH(pl, "bconv.down", (k_bconv_down<32>), grid, dim3(256), 0, st, pl.dev, level, xp, w);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void k_moddown_final(DevPlan P, uint32_t level
 
 hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *acc, const uint32_t *what,
                                 uint32_t *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_moddown_final, dim3((pl.n + 255) / 256, level + 1, 2), dim3(256), 0, st, pl.dev, level, acc,
+  KS_LAUNCH(pl, "moddown_final", k_moddown_final, dim3((pl.n + 255) / 256, level + 1, 2), dim3(256), 0, st, pl.dev, level, acc,
                      what, out);
   return hipGetLastError();
 }

@@ -367,7 +367,7 @@ template <int A, int TT, int MS>
 static void launch_bc(const Plan &pl, const OcArgs &a, int mode, uint32_t tiles, hipStream_t st) {
   constexpr int NT = 16 * SubNtt<A>::TPS;
   const uint32_t cols = 1u << pl.dev.logb;
-  hipLaunchKernelGGL((k_oc_bconv_col<A, 16, TT, MS>), dim3(cols / 16, tiles), dim3(NT), 0, st, pl.dev, a, mode);
+  KS_LAUNCH(pl, mode == 0 ? "oc.bconv_col.up" : "oc.bconv_col.down", (k_oc_bconv_col<A, 16, TT, MS>), dim3(cols / 16, tiles), dim3(NT), 0, st, pl.dev, a, mode);
 }
 
 // Largest allowed tile <= want for `nsrc` sources.
@@ -403,7 +403,7 @@ hipError_t oc_cols(const Plan &pl, const OcArgs &a, hipStream_t st) {
   constexpr int NT = 16 * SubNtt<A>::TPS;
   const uint32_t want = pl.cfg.tile_towers ? pl.cfg.tile_towers : 1;
   // step 2: inverse column pass of the inputs
-  hipLaunchKernelGGL((k_oc_intt_col<A, 16>), dim3(cols / 16, L1), dim3(NT), 0, st, pl.dev, a.xt, a.level, 0);
+  KS_LAUNCH(pl, "oc.intt_col.up", (k_oc_intt_col<A, 16>), dim3(cols / 16, L1), dim3(NT), 0, st, pl.dev, a.xt, a.level, 0);
   // step 3: ModUp conversion + forward column pass
   const uint32_t tt_up = bc_tile<A>(want, pl.alpha);
   uint32_t tiles = 0;
@@ -419,16 +419,16 @@ hipError_t oc_cols(const Plan &pl, const OcArgs &a, hipStream_t st) {
   // step 4: special towers, row pass
   const uint32_t rows = 1u << pl.dev.loga;
   const uint32_t RB = rows >= 8 ? 8 : rows;
-  if (RB == 8) hipLaunchKernelGGL((k_oc_row<8, true>), dim3(rows / 8, K), dim3(128), 0, st, pl.dev, a);
-  else hipLaunchKernelGGL((k_oc_row<4, true>), dim3(rows / 4, K), dim3(64), 0, st, pl.dev, a);
+  if (RB == 8) KS_LAUNCH(pl, "oc.row.p", (k_oc_row<8, true>), dim3(rows / 8, K), dim3(128), 0, st, pl.dev, a);
+  else KS_LAUNCH(pl, "oc.row.p", (k_oc_row<4, true>), dim3(rows / 4, K), dim3(64), 0, st, pl.dev, a);
   // step 5: inverse column pass of the special towers
-  hipLaunchKernelGGL((k_oc_intt_col<A, 16>), dim3(cols / 16, 2 * K), dim3(NT), 0, st, pl.dev, a.zp, a.level, 1);
+  KS_LAUNCH(pl, "oc.intt_col.down", (k_oc_intt_col<A, 16>), dim3(cols / 16, 2 * K), dim3(NT), 0, st, pl.dev, a.zp, a.level, 1);
   // step 6: ModDown conversion + forward column pass
   const uint32_t tt_dn = bc_tile<A>(want, K);
   if (!dispatch_bc<A>(pl, a, 1, tt_dn, K, 2 * ((L1 + tt_dn - 1) / tt_dn), st)) return hipErrorInvalidValue;
   // step 7: Q towers, row pass with ModDown
-  if (RB == 8) hipLaunchKernelGGL((k_oc_row<8, false>), dim3(rows / 8, L1), dim3(128), 0, st, pl.dev, a);
-  else hipLaunchKernelGGL((k_oc_row<4, false>), dim3(rows / 4, L1), dim3(64), 0, st, pl.dev, a);
+  if (RB == 8) KS_LAUNCH(pl, "oc.row.q", (k_oc_row<8, false>), dim3(rows / 8, L1), dim3(128), 0, st, pl.dev, a);
+  else KS_LAUNCH(pl, "oc.row.q", (k_oc_row<4, false>), dim3(rows / 4, L1), dim3(64), 0, st, pl.dev, a);
   return hipGetLastError();
 }
 

@@ -242,6 +242,35 @@ ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
 void plan_free(Plan *pl) {
   for (void *p : pl->allocs) (void)hipFree(p);
   pl->allocs.clear();
+  std::lock_guard<std::mutex> g(pl->trace.mu);
+  for (auto &m : pl->trace.marks) {
+    (void)hipEventDestroy(m.start);
+    (void)hipEventDestroy(m.stop);
+  }
+  for (hipEvent_t e : pl->trace.pool) (void)hipEventDestroy(e);
+  pl->trace.marks.clear();
+  pl->trace.pool.clear();
+}
+
+bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t *stop) {
+  Trace &t = pl.trace;
+  if (!t.on) return false;
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on) return false;
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; i++) {
+    if (!t.pool.empty()) {
+      ev[i] = t.pool.back();
+      t.pool.pop_back();
+    } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+      if (i) t.pool.push_back(ev[0]);
+      return false;
+    }
+  }
+  t.marks.push_back(TraceMark{stage, ev[0], ev[1]});
+  *start = ev[0];
+  *stop = ev[1];
+  return true;
 }
 
 }  // namespace ks

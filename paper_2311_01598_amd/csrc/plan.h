@@ -6,6 +6,7 @@
 // extended basis D_l has T = l+1+K towers; tower t < l+1 is q_t (g = t) and
 // tower t >= l+1 is p_{t-l-1} (g = L+1+t-l-1).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,6 +42,21 @@ struct DevPlan {
   uint32_t num_q, num_p, dnum, alpha, ntot;
 };
 
+// Optional per-kernel event trace (tools and the benchmark): while `on`,
+// every kernel the plan enqueues is launched with hipExtLaunchKernelGGL and
+// a start/stop event pair attached to its own dispatch (no extra packets on
+// the stream), tagged with the kernel's stage name.
+struct TraceMark {
+  const char *stage;
+  hipEvent_t start, stop;
+};
+struct Trace {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<TraceMark> marks;
+};
+
 struct Plan {
   uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
   int device = -1;
@@ -51,7 +67,20 @@ struct Plan {
   ks_config_t cfg{};
   std::mutex lock;  // guards the graph cache and config
   void *graph_cache = nullptr;
+  mutable Trace trace;
 };
+
+// True (with two events to attach to the launch) while tracing is on.
+bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t *stop);
+
+#define KS_LAUNCH(pl, stage, kernel, grid, block, shmem, st, ...)                            \
+  do {                                                                                    \
+    hipEvent_t ks_e0_, ks_e1_;                                                            \
+    if (::ks::trace_pair((pl), (stage), &ks_e0_, &ks_e1_))                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, ks_e0_, ks_e1_, 0, __VA_ARGS__); \
+    else                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                    \
+  } while (0)
 
 // Number theory used by the plan (independent of any test oracle).
 bool is_prime_u64(uint64_t n);
