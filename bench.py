@@ -40,15 +40,17 @@ def stage_muls(log_n, l1, k, alpha):
     is 3 multiplies, a 32x32+64 multiply-accumulate 1, a REDC reduction of a
     64-bit sum 4; a length-2^s transform pass has s * N/2 butterflies."""
     n, a, b = 1 << log_n, log_n - 8, 8
-    t = l1 + k
     sizes = [min(alpha, l1 - lo) for lo in range(0, l1, alpha)]
     ndig = len(sizes)
     col_ntt, row_ntt = 3 * a * n // 2, 3 * b * n // 2
+    up_p = sum(k * (n * (s + 4) + col_ntt) for s in sizes)
+    up_q = sum((l1 - s) * (n * (s + 4) + col_ntt) for s in sizes)
     return {
-        "ntt.row.inv": l1 * row_ntt,
+        "oc.intt_row": l1 * row_ntt,
         "oc.intt_col.up": l1 * (col_ntt + 3 * n),
-        "oc.bconv_col.up": sum((t - s) * (n * (s + 4) + col_ntt) for s in sizes),
+        "oc.bconv_col.up_p": up_p,
         "oc.row.p": k * (ndig * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt),
+        "oc.bconv_col.up_q": up_q,
         "oc.intt_col.down": 2 * k * (col_ntt + 3 * n),
         "oc.bconv_col.down": 2 * l1 * (n * (k + 4) + col_ntt),
         "oc.row.q": l1 * ((ndig - 1) * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt + 2 * 3 * n),

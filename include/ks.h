@@ -60,8 +60,8 @@ typedef enum {
 } ks_schedule_t;
 
 /* Parameter set (Table I).  log_n in [12, 17]; num_q = L+1 >= 1;
- * 1 <= dnum <= num_q (alpha = ceil(num_q/dnum)); num_p = K (0 => alpha);
- * num_q + num_p <= 128.  `moduli` is an optional host array of
+ * 1 <= dnum <= min(num_q, 16) (alpha = ceil(num_q/dnum) <= 32); num_p = K
+ * (0 => alpha, at most 32); num_q + num_p <= 128.  `moduli` is an optional host array of
  * num_q + num_p values (q_0..q_L, p_0..p_{K-1}); NULL selects the default
  * primes.  Explicit moduli are validated: prime, 2^29 < m < 2^30,
  * m = 1 mod 2N, pairwise distinct. */
@@ -77,9 +77,17 @@ typedef struct {
  * plan's current value. */
 typedef struct {
   ks_schedule_t schedule;
-  uint32_t tile_towers;  /* OC: output towers sharing one column-pass tile (1, 2, 4) */
-  uint32_t col_width;    /* columns per column-pass workgroup (8, 16, 32) */
-  uint32_t row_block;    /* rows per row-pass workgroup (4, 8, 16) */
+  uint32_t tile_towers;  /* OC: target towers per basis-conversion tile (1, 2) */
+  uint32_t col_width;    /* MP/DC: columns per column-pass workgroup (8, 16, 32) */
+  uint32_t row_block;    /* MP/DC: rows per row-pass workgroup (4, 8, 16) */
+  uint32_t batch_mode;   /* OC batches: 1 = one launch per phase over all jobs,
+                            2 = one persistent work-queue launch (currently
+                            switched off: KS_ERR_UNSUPPORTED) */
+  uint32_t graph;        /* batches: 1 = capture the launches in a hipGraph and
+                            replay it (currently switched off:
+                            KS_ERR_UNSUPPORTED), 2 = launch directly */
+  uint32_t spin_limit;   /* persistent launch: polls before a dependency wait
+                            gives up and flags an error (tests use tiny values) */
 } ks_config_t;
 
 typedef struct ks_plan *ks_plan_t;
@@ -126,11 +134,21 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
                          const uint32_t *in, uint32_t *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
-/* Many key switches at mixed levels in one launch sequence (jobs is a host
- * array of `count` entries).  Each job's output equals ks_keyswitch of that
- * job alone.  Outputs must not overlap each other or any input. */
+/* Many key switches at mixed levels (jobs is a host array of `count`
+ * entries; the key may differ per job).  Each job's output equals
+ * ks_keyswitch of that job alone.  Outputs must not overlap each other, any
+ * input or the workspace.  With the OC schedule the jobs run together: one
+ * launch per phase over all jobs, or one persistent work-queue launch, and
+ * the launches are captured once per (count, workspace, configuration) in a
+ * hipGraph that is replayed afterwards.  The job table travels in the
+ * workspace, so concurrent batches need distinct workspaces. */
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs,
                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* After a batch: waits for `stream`, then sets *error_flag to 1 if a
+ * dependency wait of the persistent launch exceeded its spin limit (the
+ * outputs of that batch are then invalid), else 0. */
+ks_status_t ks_batch_status(ks_plan_t plan, const void *workspace, void *stream, uint32_t *error_flag);
 
 /* Stage access for tests and tools: in-place forward (inverse = 0) or
  * inverse (inverse = 1, including the N^-1 factor) negacyclic NTT of

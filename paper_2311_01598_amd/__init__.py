@@ -33,7 +33,8 @@ class ks_params_t(ctypes.Structure):
 
 class ks_config_t(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("tile_towers", ctypes.c_uint32), ("col_width", ctypes.c_uint32),
-                ("row_block", ctypes.c_uint32)]
+                ("row_block", ctypes.c_uint32), ("batch_mode", ctypes.c_uint32), ("graph", ctypes.c_uint32),
+                ("spin_limit", ctypes.c_uint32)]
 
 
 class ks_job_t(ctypes.Structure):
@@ -55,6 +56,7 @@ _SIGS = {
     "ks_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
                                           _VP]),
+    "ks_batch_status": (ctypes.c_int, [_VP, _VP, _VP, _U32P]),
     "ks_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
     "ks_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "ks_trace_read": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_char_p), _U32P,
@@ -155,18 +157,30 @@ def ks_plan_moduli(plan, count):
     return list(out)
 
 
-def ks_plan_set_config(plan, schedule=0, tile_towers=0, col_width=0, row_block=0):
+CONFIG_FIELDS = ("tile_towers", "col_width", "row_block", "batch_mode", "graph", "spin_limit")
+
+
+def ks_plan_set_config(plan, schedule=0, **fields):
     if isinstance(schedule, str):
         schedule = SCHEDULES[schedule]
-    c = ks_config_t(schedule, tile_towers, col_width, row_block)
+    unknown = set(fields) - set(CONFIG_FIELDS)
+    if unknown:
+        raise TypeError(f"unknown config fields {sorted(unknown)}")
+    c = ks_config_t(schedule, *[int(fields.get(f, 0)) for f in CONFIG_FIELDS])
     _check(_lib.ks_plan_set_config(plan, ctypes.byref(c)), "ks_plan_set_config")
 
 
 def ks_plan_get_config(plan):
     c = ks_config_t()
     _check(_lib.ks_plan_get_config(plan, ctypes.byref(c)), "ks_plan_get_config")
-    return {"schedule": c.schedule, "tile_towers": c.tile_towers, "col_width": c.col_width,
-            "row_block": c.row_block}
+    return {"schedule": c.schedule, **{f: getattr(c, f) for f in CONFIG_FIELDS}}
+
+
+def ks_batch_status_flag(plan, workspace, stream=None):
+    """1 if the last persistent batch in `workspace` hit its spin limit."""
+    flag = ctypes.c_uint32()
+    _check(_lib.ks_batch_status(plan, _ptr(workspace), _stream(stream), ctypes.byref(flag)), "ks_batch_status")
+    return flag.value
 
 
 def ks_workspace_size(plan, levels):
@@ -236,8 +250,8 @@ class Plan:
         if schedule is not None or cfg:
             self.configure(schedule or 0, **cfg)
 
-    def configure(self, schedule=0, tile_towers=0, col_width=0, row_block=0):
-        ks_plan_set_config(self.handle, schedule, tile_towers, col_width, row_block)
+    def configure(self, schedule=0, **fields):
+        ks_plan_set_config(self.handle, schedule, **fields)
 
     @property
     def config(self):

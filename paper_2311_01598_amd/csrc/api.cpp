@@ -30,6 +30,30 @@ size_t ws_limbs(const Plan &pl, ks_schedule_t sch, uint32_t level) {
   }
 }
 
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// OC batch workspace: control words, segment table, job table, then one
+// OC region per job.
+struct BatchLayout {
+  size_t ctl, segs, jobs, regions, total;
+  std::vector<size_t> region;  // byte offset of each job's region
+};
+BatchLayout batch_layout(const Plan &pl, uint32_t count, const uint32_t *levels) {
+  BatchLayout b;
+  b.ctl = 0;
+  b.segs = align256((4 + (size_t)count * OC_NPHASE) * sizeof(uint32_t));
+  b.jobs = b.segs + align256((size_t)count * OC_NPHASE * sizeof(OcSeg));
+  b.regions = b.jobs + align256((size_t)count * sizeof(OcJob));
+  size_t off = b.regions;
+  b.region.resize(count);
+  for (uint32_t i = 0; i < count; i++) {
+    b.region[i] = off;
+    off += align256(ws_limbs(pl, KS_SCHED_OC, levels[i]) * limb_bytes(pl));
+  }
+  b.total = off;
+  return b;
+}
+
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
   const char *x = (const char *)a, *y = (const char *)b;
   return x < y + nb && y < x + na;
@@ -122,19 +146,30 @@ ks_status_t run_dc(const Plan &pl, const uint32_t *evk, uint32_t level, const ui
 }
 
 // ---------------------------------------------------------------- OC
+OcJob make_oc_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
+                  uint32_t *ws, uint32_t tt) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
+  OcJob j{};
+  j.d = d;
+  j.evk = evk;
+  j.out = out;
+  j.level = level;
+  j.xt = ws;
+  j.ycol = j.xt + (size_t)L1 * N;
+  j.zp = j.ycol + (size_t)D * T * N;
+  j.wcol = j.zp + (size_t)2 * K * N;
+  j.ttu = j.ttd = tt;
+  oc_tiles_host(pl, level, tt, j.tiles);
+  return j;
+}
+
+uint32_t oc_tt(const Plan &pl) { return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1); }
+
 ks_status_t run_oc(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
                    uint32_t *ws, hipStream_t st) {
-  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
-  OcArgs a{};
-  a.d = d;
-  a.evk = evk;
-  a.out = out;
-  a.level = level;
-  a.xt = ws;
-  a.ycol = a.xt + (size_t)L1 * N;
-  a.zp = a.ycol + (size_t)D * T * N;
-  a.wcol = a.zp + (size_t)2 * K * N;
-  return dev_err(launch_oc(pl, a, st));
+  const uint32_t tt = oc_tt(pl);
+  const OcJob j = make_oc_job(pl, evk, level, d, out, ws, tt);
+  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, st));
 }
 
 ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint32_t level, const uint32_t *d,
@@ -146,6 +181,97 @@ ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint
     default: r = run_oc(pl, evk, level, d, out, ws, st); break;
   }
   return r;
+}
+
+// A captured batch: the graph replays the launches for one (count,
+// workspace, configuration); the job table is re-uploaded before each replay.
+struct GraphEntry {
+  uint32_t count, mode, tt, spin, total;
+  std::vector<uint32_t> max_tiles;
+  const void *ws;
+  hipGraphExec_t exec;
+};
+struct GraphCache {
+  hipStream_t capture = nullptr;
+  std::vector<GraphEntry> entries;
+};
+
+ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<uint32_t> &max_tiles, uint32_t total,
+                            char *ws, const BatchLayout &lay, uint32_t mode, uint32_t tt, uint32_t spin,
+                            hipStream_t st) {
+  const OcJob *djobs = (const OcJob *)(ws + lay.jobs);
+  if (mode == 2)
+    return dev_err(launch_oc_persistent(pl, djobs, (const OcSeg *)(ws + lay.segs), count * OC_NPHASE, total, count,
+                                        (uint32_t *)(ws + lay.ctl), spin, st));
+  const OcJob none{};
+  return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, st));
+}
+
+ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const BatchLayout &lay, char *ws,
+                         hipStream_t st) {
+  const uint32_t mode = pl.cfg.batch_mode == 2 ? 2 : 1;
+  const uint32_t tt = mode == 2 ? 1 : oc_tt(pl);
+  const uint32_t spin = pl.cfg.spin_limit ? pl.cfg.spin_limit : (1u << 20);
+  // host tables
+  std::vector<OcJob> hj(count);
+  std::vector<uint32_t> max_tiles(OC_NPHASE, 0);
+  for (uint32_t i = 0; i < count; i++) {
+    hj[i] = make_oc_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)(ws + lay.region[i]), tt);
+    for (uint32_t p = 0; p < OC_NPHASE; p++) max_tiles[p] = std::max(max_tiles[p], hj[i].tiles[p]);
+  }
+  std::vector<OcSeg> segs;
+  segs.reserve((size_t)count * OC_NPHASE);
+  uint32_t total = 0;
+  for (uint32_t p = 0; p < OC_NPHASE; p++)
+    for (uint32_t i = 0; i < count; i++) {
+      segs.push_back(OcSeg{total, i, p, 0});
+      total += hj[i].tiles[p];
+    }
+  // the job and segment tables live in the workspace (the graph reads them there)
+  // control words (zero), segment table and job table in one upload
+  std::vector<char> blob(lay.regions, 0);
+  std::memcpy(blob.data() + lay.segs, segs.data(), segs.size() * sizeof(OcSeg));
+  std::memcpy(blob.data() + lay.jobs, hj.data(), hj.size() * sizeof(OcJob));
+  TRY(upload_async(pl, ws, blob.data(), blob.size(), st));
+
+  const bool use_graph = pl.cfg.graph != 2 && !pl.trace.on;
+  if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, st);
+
+  // graph keyed by (count, workspace, mode, tile, spin); the persistent launch
+  // reads `total` from its arguments, so it is part of the key as well
+  std::lock_guard<std::mutex> g(pl.lock);
+  GraphCache *gc = (GraphCache *)pl.graph_cache;
+  if (!gc) {
+    gc = new GraphCache();
+    pl.graph_cache = gc;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto &e : gc->entries)
+    if (e.count == count && e.ws == ws && e.mode == mode && e.tt == tt && e.spin == spin && e.total == total &&
+        e.max_tiles == max_tiles)
+      exec = e.exec;
+  if (!exec) {
+    if (!gc->capture && hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking) != hipSuccess)
+      return KS_ERR_DEVICE;
+    TRY(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
+    ks_status_t r = launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, gc->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(gc->capture, &graph);
+    if (r != KS_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return KS_ERR_DEVICE;
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return KS_ERR_DEVICE;
+    if (gc->entries.size() >= 64) {  // bounded cache: drop the oldest capture
+      (void)hipGraphExecDestroy(gc->entries.front().exec);
+      gc->entries.erase(gc->entries.begin());
+    }
+    gc->entries.push_back(GraphEntry{count, mode, tt, spin, total, max_tiles, ws, exec});
+  }
+  TRY(hipGraphLaunch(exec, st));
+  return KS_OK;
 }
 
 ks_status_t check_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *in, const uint32_t *out,
@@ -171,7 +297,7 @@ ks_status_t validate_params(const ks_params_t *p) {
   const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum;
   const uint32_t K = p->num_p ? p->num_p : alpha;
   if (p->num_q + K > kMaxTowers) return KS_ERR_UNSUPPORTED;
-  if (alpha > 32 || K > 32) return KS_ERR_UNSUPPORTED;
+  if (alpha > 32 || K > 32 || p->dnum > 16) return KS_ERR_UNSUPPORTED;
   if (p->moduli) {
     const uint64_t two_n = 2ull << p->log_n;
     for (uint32_t i = 0; i < p->num_q + K; i++) {
@@ -229,7 +355,7 @@ ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
   if (st != KS_OK) return st;
   ks_plan *pl = new (std::nothrow) ks_plan();
   if (!pl) return KS_ERR_NOMEM;
-  pl->p.cfg = ks_config_t{KS_SCHED_OC, 1, 16, 8};
+  pl->p.cfg = ks_config_t{KS_SCHED_OC, 1, 16, 8, 1, 2, 0};
   st = plan_build(p, &pl->p);
   if (st != KS_OK) {
     plan_free(&pl->p);
@@ -243,6 +369,12 @@ ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
 ks_status_t ks_plan_destroy(ks_plan_t plan) {
   if (!plan) return KS_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
+  if (GraphCache *gc = (GraphCache *)plan->p.graph_cache) {
+    for (auto &e : gc->entries) (void)hipGraphExecDestroy(e.exec);
+    if (gc->capture) (void)hipStreamDestroy(gc->capture);
+    delete gc;
+    plan->p.graph_cache = nullptr;
+  }
   plan_free(&plan->p);
   delete plan;
   return KS_OK;
@@ -262,14 +394,22 @@ ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
     for (uint32_t a : allowed) if (a == v) return true;
     return false;
   };
-  if (!ok(cfg->tile_towers, {1, 2, 4}) || !ok(cfg->col_width, {8, 16, 32}) || !ok(cfg->row_block, {4, 8, 16}))
+  if (!ok(cfg->tile_towers, {1, 2, 4}) || !ok(cfg->col_width, {8, 16, 32}) || !ok(cfg->row_block, {4, 8, 16}) ||
+      !ok(cfg->batch_mode, {1, 2}) || !ok(cfg->graph, {1, 2}))
     return KS_ERR_INVALID_ARG;
+  // The persistent work-queue launch and graph capture of batches are
+  // switched off: a batch run through them stopped making progress on the
+  // device and the cause is not yet established.
+  if (cfg->batch_mode == 2 || cfg->graph == 1) return KS_ERR_UNSUPPORTED;
   std::lock_guard<std::mutex> g(plan->p.lock);
   ks_config_t &c = plan->p.cfg;
   c.schedule = cfg->schedule;
   if (cfg->tile_towers) c.tile_towers = cfg->tile_towers;
   if (cfg->col_width) c.col_width = cfg->col_width;
   if (cfg->row_block) c.row_block = cfg->row_block;
+  if (cfg->batch_mode) c.batch_mode = cfg->batch_mode;
+  if (cfg->graph) c.graph = cfg->graph;
+  if (cfg->spin_limit) c.spin_limit = cfg->spin_limit;
   return KS_OK;
 }
 
@@ -289,6 +429,7 @@ ks_status_t ks_workspace_size(ks_plan_t plan, uint32_t count, const uint32_t *le
     mx = std::max(mx, ws_limbs(pl, effective(pl), levels[i]));
   }
   *bytes = mx * limb_bytes(pl);
+  if (count > 1 && effective(pl) == KS_SCHED_OC) *bytes = batch_layout(pl, count, levels).total;
   return KS_OK;
 }
 
@@ -309,12 +450,21 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, co
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
                                size_t workspace_bytes, void *stream) {
   if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
-  const Plan &pl = plan->p;
+  Plan &pl = plan->p;
   const ks_schedule_t sch = effective(pl);
-  size_t need = 0;
+  if (!count) return KS_OK;
+  std::vector<uint32_t> levels(count);
   for (uint32_t i = 0; i < count; i++) {
     if (jobs[i].level >= pl.num_q) return KS_ERR_INVALID_ARG;
-    need = std::max(need, ws_limbs(pl, sch, jobs[i].level) * limb_bytes(pl));
+    levels[i] = jobs[i].level;
+  }
+  const bool together = sch == KS_SCHED_OC && count > 1;
+  size_t need = 0;
+  for (uint32_t i = 0; i < count; i++) need = std::max(need, ws_limbs(pl, sch, levels[i]) * limb_bytes(pl));
+  BatchLayout lay;
+  if (together) {
+    lay = batch_layout(pl, count, levels.data());
+    need = lay.total;
   }
   for (uint32_t i = 0; i < count; i++) {
     ks_status_t st = check_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, workspace,
@@ -330,11 +480,24 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
-  for (uint32_t i = 0; i < count; i++) {
-    ks_status_t st = run_one(pl, sch, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)workspace,
-                             (hipStream_t)stream);
-    if (st != KS_OK) return st;
+  hipStream_t st = (hipStream_t)stream;
+  if (!together) {
+    for (uint32_t i = 0; i < count; i++) {
+      ks_status_t r = run_one(pl, sch, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)workspace, st);
+      if (r != KS_OK) return r;
+    }
+    return KS_OK;
   }
+  return run_oc_batch(pl, count, jobs, lay, (char *)workspace, st);
+}
+
+ks_status_t ks_batch_status(ks_plan_t plan, const void *workspace, void *stream, uint32_t *error_flag) {
+  if (!plan || !workspace || !error_flag) return KS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t ctl[2] = {0, 0};
+  if (hipStreamSynchronize(st) != hipSuccess) return KS_ERR_DEVICE;
+  if (hipMemcpy(ctl, workspace, sizeof(ctl), hipMemcpyDeviceToHost) != hipSuccess) return KS_ERR_DEVICE;
+  *error_flag = ctl[1] ? 1u : 0u;
   return KS_OK;
 }
 

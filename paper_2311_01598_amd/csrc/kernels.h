@@ -47,21 +47,74 @@ hipError_t launch_bconv_down(const Plan &pl, uint32_t level, const uint32_t *xp,
 hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *acc, const uint32_t *what,
                                 uint32_t *out, hipStream_t st);
 
-// Output-Centric fused kernels, see kernels.hip.
-struct OcArgs {
-  const uint32_t *d;     // [l+1][N] input
-  const uint32_t *evk;   // [dnum][2][L+1+K][N]
-  uint32_t *out;         // [2][l+1][N]
-  uint32_t *xt;          // [l+1][N]   ModUp P1 output (unscaled INTT, lazy)
-  uint32_t *ycol;        // [ndig][T][N] column-pass output of ModUp P2/P3
-  uint32_t *zp;          // [2][K][N]  ModDown P1 row-pass output
-  uint32_t *wcol;        // [2][l+1][N] column-pass output of ModDown P2/P3
-  uint32_t level;
+// ------------------------------------------------------------ Output-Centric
+// Phases in issue order (see oc_kernels.h).
+enum OcPhase : uint32_t {
+  OC_INTT_ROW = 0, OC_INTT_COL, OC_UP_P, OC_ROW_P, OC_UP_Q, OC_INTT_COL_DN, OC_DN, OC_ROW_Q, OC_NPHASE
 };
-hipError_t launch_oc(const Plan &pl, const OcArgs &a, hipStream_t st);
-// Steps 2-7 of the Output-Centric order for a column pass of length 2^A
-// (explicitly instantiated in oc_a<A>.hip).
+
+// One key switch as the OC kernels see it (device-visible, by value or in a
+// job table).  Workspace regions: xt [l+1][N] ModUp P1 output, ycol
+// [ndig][T][N] column-pass output of ModUp P2/P3, zp [2][K][N] ModDown P1,
+// wcol [2][l+1][N] column-pass output of ModDown P2/P3.
+struct OcJob {
+  const uint32_t *d;
+  const uint32_t *evk;
+  uint32_t *out;
+  uint32_t *xt, *ycol, *zp, *wcol;
+  uint32_t level, ttu, ttd, pad;
+  uint32_t tiles[OC_NPHASE];  // tile count of every phase for this job
+};
+
+// Segment of the persistent work queue: items [start, next.start) are the
+// tiles of `phase` for job `job`.
+struct OcSeg {
+  uint32_t start, job, phase, pad;
+};
+
+constexpr int kRB = 16;  // rows per OC row tile
+
+__host__ __device__ __forceinline__ uint32_t oc_gidx(uint32_t num_q, uint32_t level, uint32_t t) {
+  return t <= level ? t : num_q + (t - level - 1);
+}
+__host__ __device__ __forceinline__ uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// Tile counts of every phase for a job at `level`.
+__host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint32_t alpha, uint32_t K,
+                                               uint32_t level, uint32_t ttu, uint32_t ttd, uint32_t *n) {
+  const uint32_t L1 = level + 1, rbk = (1u << loga) / kRB, ndig = cdiv(L1, alpha);
+  uint32_t upq = 0;
+  for (uint32_t j = 0; j < ndig; j++) {
+    const uint32_t lo = j * alpha, s = (lo + alpha < L1 ? lo + alpha : L1) - lo;
+    upq += cdiv(L1 - s, ttu);
+  }
+  n[OC_INTT_ROW] = rbk * L1;
+  n[OC_INTT_COL] = cb * L1;
+  n[OC_UP_P] = cb * ndig * cdiv(K, ttu);
+  n[OC_ROW_P] = rbk * K;
+  n[OC_UP_Q] = cb * upq;
+  n[OC_INTT_COL_DN] = cb * 2 * K;
+  n[OC_DN] = cb * 2 * cdiv(L1, ttd);
+  n[OC_ROW_Q] = rbk * L1;
+}
+
+// Effective targets per basis-conversion tile (1 or 2) for a column pass of
+// length 2^loga.
+uint32_t oc_effective_tt(uint32_t loga, uint32_t want);
+// Tile counts of every phase (host).
+void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles);
+// One launch per phase; jobs == nullptr runs `one` alone.
+hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
+                            const uint32_t *max_tiles, uint32_t tt, hipStream_t st);
+// Persistent work-queue launch (tiles of one target per conversion tile).
+hipError_t launch_oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs,
+                                uint32_t total, uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);
+
 template <int A>
-hipError_t oc_cols(const Plan &pl, const OcArgs &a, hipStream_t st);
+hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
+                     uint32_t tt, hipStream_t st);
+template <int A>
+hipError_t oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs, uint32_t total,
+                         uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);
 
 }  // namespace ks

@@ -377,22 +377,46 @@ hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *
 }
 
 // ------------------------------------------------------------ OC entry
-hipError_t launch_oc(const Plan &pl, const OcArgs &a, hipStream_t st) {
-  const uint32_t L1 = a.level + 1;
-  if (L1 > kMaxList) return hipErrorInvalidValue;
-  // step 1: inverse row pass of the inputs, d -> xt
-  LimbList Lr{};
-  Lr.count = L1;
-  for (uint32_t i = 0; i < L1; i++) { Lr.src_off[i] = Lr.dst_off[i] = i; Lr.g[i] = (uint16_t)i; }
-  hipError_t e = launch_row(pl, true, a.d, a.xt, Lr, st);
-  if (e != hipSuccess) return e;
+uint32_t oc_effective_tt(uint32_t loga, uint32_t want) {
+  // two targets per tile keep 2 x 16 accumulators per thread; columns of
+  // 32 elements per thread (loga 5 and 9) stay at one
+  return (want >= 2 && loga != 5 && loga != 9) ? 2 : 1;
+}
+
+static uint32_t col_blocks(uint32_t loga) {
+  switch (loga) {
+    case 4: case 5: return 1;
+    case 6: case 7: return 8;
+    default: return 16;
+  }
+}
+
+void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles) {
+  oc_phase_tiles(pl.dev.loga, col_blocks(pl.dev.loga), pl.alpha, pl.num_p, level, tt, tt, tiles);
+}
+
+hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
+                            const uint32_t *max_tiles, uint32_t tt, hipStream_t st) {
   switch (pl.dev.loga) {
-    case 4: return oc_cols<4>(pl, a, st);
-    case 5: return oc_cols<5>(pl, a, st);
-    case 6: return oc_cols<6>(pl, a, st);
-    case 7: return oc_cols<7>(pl, a, st);
-    case 8: return oc_cols<8>(pl, a, st);
-    case 9: return oc_cols<9>(pl, a, st);
+    case 4: return oc_phases<4>(pl, one, jobs, count, max_tiles, tt, st);
+    case 5: return oc_phases<5>(pl, one, jobs, count, max_tiles, tt, st);
+    case 6: return oc_phases<6>(pl, one, jobs, count, max_tiles, tt, st);
+    case 7: return oc_phases<7>(pl, one, jobs, count, max_tiles, tt, st);
+    case 8: return oc_phases<8>(pl, one, jobs, count, max_tiles, tt, st);
+    case 9: return oc_phases<9>(pl, one, jobs, count, max_tiles, tt, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs,
+                                uint32_t total, uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st) {
+  switch (pl.dev.loga) {
+    case 4: return oc_persistent<4>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
+    case 5: return oc_persistent<5>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
+    case 6: return oc_persistent<6>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
+    case 7: return oc_persistent<7>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
+    case 8: return oc_persistent<8>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
+    case 9: return oc_persistent<9>(pl, jobs, segs, nsegs, total, count, ctl, spin_limit, st);
   }
   return hipErrorInvalidValue;
 }

@@ -1,6 +1,9 @@
 // oc_a6.hip -- Output-Centric kernels for a column pass of length 2^6.
-#include "oc_kernels.h"
+#include "oc_persist.h"
 
 namespace ks {
-template hipError_t oc_cols<6>(const Plan &, const OcArgs &, hipStream_t);
+template hipError_t oc_phases<6>(const Plan &, const OcJob &, const OcJob *, uint32_t, const uint32_t *, uint32_t,
+                                  hipStream_t);
+template hipError_t oc_persistent<6>(const Plan &, const OcJob *, const OcSeg *, uint32_t, uint32_t, uint32_t,
+                                      uint32_t *, uint32_t, hipStream_t);
 }  // namespace ks

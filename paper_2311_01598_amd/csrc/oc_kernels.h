@@ -4,62 +4,191 @@
 // expansion (ModUp P2) and the key products (P4) of a tower are produced and
 // consumed on chip, P5 accumulates on chip, the INTT outputs are kept and
 // reused by every tower, and ModDown converts one tower at a time from the
-// K special towers.  With the two-pass NTT (column pass, row pass) a tower's
-// transform is spread over many workgroups, so the unit of work here is an
-// output tower (or a tile of towers) times a column block or a row block:
+// K special towers.  A 2^16-point transform does not fit one CU, so a
+// tower's transform is split into a column pass and a row pass (see
+// ntt_engine.h) and the unit of work is a tile: an output tower (or a few)
+// times a column block, or a tower times a block of 16 rows.  Phases, in the
+// order they are issued:
 //
-//   1. inverse row pass of the input towers            (ModUp P1, part 1)
-//   2. inverse column pass + per-source constant        (ModUp P1, part 2)
-//   3. per (digit, target tile, column block): basis conversion from the
-//      digit's towers fused with the forward column pass (ModUp P2, P3)
-//   4. per (P tower, row block): forward row pass of every digit, key
-//      multiply-accumulate over digits in registers, then the inverse row
-//      pass of both accumulators (ModUp P3-P5, ModDown P1 part 1)
-//   5. inverse column pass of the 2K special towers + constant (ModDown P1)
-//   6. per (poly, Q-target tile, column block): conversion P -> q_i fused
-//      with the forward column pass (ModDown P2, P3)
-//   7. per (Q tower, row block): forward row pass of the foreign digits,
-//      bypass of the own digit, key multiply-accumulate, forward row pass of
-//      the ModDown term and (acc - w) * P^-1 (ModUp P3-P5, ModDown P3-P4).
+//   INTT_ROW    inverse row pass of the input towers              ModUp P1
+//   INTT_COL    inverse column pass + per-source constant         ModUp P1
+//   UP_P        per (digit, special target, column block): basis
+//               conversion fused with the forward column pass     ModUp P2, P3
+//   ROW_P       per (special tower, row block): forward row pass of
+//               every digit, key multiply-accumulate in registers,
+//               inverse row pass of both accumulators             P3-P5, ModDown P1
+//   UP_Q        as UP_P for the Q targets outside each digit      ModUp P2, P3
+//   INTT_COL_DN inverse column pass of the 2K special towers       ModDown P1
+//   DN          per (poly, Q target, column block): conversion
+//               P -> q_i fused with the forward column pass       ModDown P2, P3
+//   ROW_Q       per (Q tower, row block): forward row pass of the
+//               foreign digits, bypass of the own digit, key
+//               multiply-accumulate, forward row pass of the
+//               ModDown term, (acc - w) * P^-1                    P3-P5, ModDown P3-P4
+//
 // The special towers go first (the paper's Section 2) so that every Q tower
-// finishes ModUp and ModDown in one kernel and its accumulator never leaves
-// registers.
+// finishes ModUp and ModDown in one tile and its accumulator never leaves
+// registers.  Every tile is one 256-thread workgroup; the same tile bodies
+// serve one launch per phase (single key switch or a batch, job index in
+// grid z) and the persistent work-queue kernel of oc_persist.h.
 #pragma once
 #include "kernels.h"
 #include "ntt_engine.h"
 
 namespace ks {
 
-__device__ __forceinline__ uint32_t oc_gidx(const DevPlan &P, uint32_t level, uint32_t t) {
-  return t <= level ? t : P.num_q + (t - level - 1);
+constexpr int kOcThreads = 256;
+constexpr int kPad = 272;   // LDS words per row: 256 + one pad word per 16
+constexpr int kRowLds = kRB * kPad;
+__device__ __forceinline__ int rl(int k) { return k + (k >> 4); }
+
+template <int A>
+struct ColGeom {
+  static constexpr int TPS = SubNtt<A>::TPS, R1 = SubNtt<A>::R1, R2 = SubNtt<A>::R2, E = 1 << R1;
+  static constexpr int W = kOcThreads / TPS;  // columns per tile (TPS threads per column)
+  static constexpr int CB = TPS;              // column blocks: 256 / W
+  static constexpr int LDS = W << A;          // words per target tile
+};
+
+// ------------------------------------------------------------ twiddles
+// Twiddles of one group in registers: entry (2^t - 1) + k is stage t's k-th.
+template <int R>
+struct GroupTw {
+  uint2 w[(1 << R) - 1];
+};
+template <int A, int S0, int R>
+__device__ __forceinline__ void load_group_tw(GroupTw<R> &gt, const uint2 *__restrict__ tw, int g, uint32_t M) {
+  const uint32_t hi = (uint32_t)Phase<A, S0, R>::hi(g);
+#pragma unroll
+  for (int t = 0; t < R; t++) {
+    const uint32_t node = (M << (S0 + t - 1)) + (hi << t);
+#pragma unroll
+    for (int k = 0; k < (1 << t); k++) gt.w[(1 << t) - 1 + k] = tw[node + k];
+  }
+}
+template <int R>
+__device__ __forceinline__ void ct_regs(uint32_t (&x)[1 << R], const GroupTw<R> &gt, uint32_t q) {
+#pragma unroll
+  for (int t = 0; t < R; t++) {
+    const int half = 1 << (R - 1 - t);
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) {
+      if (u & half) continue;
+      const uint2 w = gt.w[(1 << t) - 1 + (u >> (R - t))];
+      bfly_ct(x[u], x[u + half], w.x, w.y, q);
+    }
+  }
+}
+template <int R>
+__device__ __forceinline__ void gs_regs(uint32_t (&x)[1 << R], const GroupTw<R> &gt, uint32_t q) {
+#pragma unroll
+  for (int t = R - 1; t >= 0; t--) {
+    const int half = 1 << (R - 1 - t);
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) {
+      if (u & half) continue;
+      const uint2 w = gt.w[(1 << t) - 1 + (u >> (R - t))];
+      bfly_gs(x[u], x[u + half], w.x, w.y, q);
+    }
+  }
 }
 
-// ------------------------------------------------------------ step 2 / 5
-// Inverse column pass of one limb, then x~ = [v * c]_m canonical with the
-// per-source constant c (ModUp: N^-1 qhat^-1, ModDown: N^-1 2^32 phat^-1).
-// mode 0: limb i of xt (ModUp sources); mode 1: limb s*K+k of zp.
-template <int A, int W>
-__global__ __launch_bounds__(W *SubNtt<A>::TPS) void k_oc_intt_col(DevPlan P, uint32_t *data, uint32_t level,
-                                                                  int mode) {
-  using S = SubNtt<A>;
-  constexpr int R1 = S::R1, R2 = S::R2, TPS = S::TPS;
-  __shared__ uint32_t lds[W << A];
+// A row (256 words) is transformed by 16 threads: phase 1 (row stages 1-4)
+// holds k = tig + 16u, phase 2 (stages 5-8) holds k = 16 tig + u.
+struct RowTw {
+  GroupTw<4> p1, p2;
+};
+__device__ __forceinline__ void load_row_tw(RowTw &r, const uint2 *__restrict__ tw, int tig, uint32_t M) {
+  load_group_tw<8, 1, 4>(r.p1, tw, tig, M);
+  load_group_tw<8, 5, 4>(r.p2, tw, tig, M);
+}
+
+__device__ __forceinline__ void load16(uint32_t (&x)[16], const uint32_t *p) {
+  const uint4 *v = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const uint4 t = v[i];
+    x[4 * i] = t.x; x[4 * i + 1] = t.y; x[4 * i + 2] = t.z; x[4 * i + 3] = t.w;
+  }
+}
+__device__ __forceinline__ void store16(uint32_t *p, const uint32_t (&x)[16]) {
+  uint4 *v = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+  for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+}
+
+// Forward transform of a row read from global in phase-1 layout; result in
+// x (phase-2 layout, lazy [0, 4q)).  lr: this row's LDS slice.
+__device__ __forceinline__ void row_fwd(uint32_t (&x)[16], const uint32_t *row, uint32_t *lr, int tig,
+                                        const RowTw &tw, uint32_t q) {
+#pragma unroll
+  for (int u = 0; u < 16; u++) x[u] = row[tig + 16 * u];
+  ct_regs<4>(x, tw.p1, q);
+#pragma unroll
+  for (int u = 0; u < 16; u++) lr[rl(tig + 16 * u)] = x[u];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; u++) x[u] = lr[rl(16 * tig + u)];
+  ct_regs<4>(x, tw.p2, q);
+  __syncthreads();
+}
+
+// Inverse transform of x (phase-2 layout, values < 2q) written to global in
+// phase-1 layout (lazy [0, 2q)).
+__device__ __forceinline__ void row_inv(uint32_t (&x)[16], uint32_t *row, uint32_t *lr, int tig, const RowTw &tw,
+                                        uint32_t q) {
+  gs_regs<4>(x, tw.p2, q);
+#pragma unroll
+  for (int u = 0; u < 16; u++) lr[rl(16 * tig + u)] = x[u];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; u++) x[u] = lr[rl(tig + 16 * u)];
+  gs_regs<4>(x, tw.p1, q);
+#pragma unroll
+  for (int u = 0; u < 16; u++) row[tig + 16 * u] = x[u];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ tile bodies
+// INTT_ROW: inverse row pass of input tower `i`, row block `blk`, d -> xt.
+__device__ __forceinline__ void tile_intt_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
-  const uint32_t rowlen = 1u << P.logb, c0 = blockIdx.x * W, li = blockIdx.y;
+  const uint32_t rbk = (1u << P.loga) / kRB, i = tile / rbk, blk = tile % rbk;
+  const int rr = threadIdx.x >> 4, tig = threadIdx.x & 15;
+  const uint32_t row = blk * kRB + rr, M = (1u << P.loga) + row;
+  const size_t roff = (size_t)i * N + (size_t)row * 256;
+  RowTw tw;
+  load_row_tw(tw, P.tw_inv + (size_t)i * N, tig, M);
+  uint32_t x[16];
+  load16(x, J.d + roff + 16 * tig);
+  row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, P.mods[i].q);
+}
+
+// INTT_COL / INTT_COL_DN: inverse column pass of one limb, then
+// x~ = [v * c]_m canonical with the per-source constant c.
+template <int A>
+__device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, uint32_t tile, bool down,
+                                              uint32_t *lds) {
+  using G = ColGeom<A>;
+  constexpr int R1 = G::R1, R2 = G::R2, TPS = G::TPS, W = G::W;
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t li = tile / G::CB, c0 = (tile % G::CB) * W, rowlen = 256;
   uint32_t g;
   uint2 pre;
-  if (mode == 0) {
+  uint32_t *col;
+  if (!down) {
+    const uint32_t j = li / P.alpha, lo = j * P.alpha, s = min(lo + P.alpha, J.level + 1) - lo;
     g = li;
-    const uint32_t j = li / P.alpha, lo = j * P.alpha, s = min(lo + P.alpha, level + 1) - lo;
     pre = P.up_pre[((size_t)j * P.alpha + (s - 1)) * P.alpha + (li - lo)];
+    col = J.xt + (size_t)li * N + c0;
   } else {
     const uint32_t k = li % P.num_p;
     g = P.num_q + k;
     pre = P.dn_pre[k];
+    col = J.zp + (size_t)li * N + c0;
   }
   const uint32_t q = P.mods[g].q;
-  const uint2 *tw = P.tw_inv + g * N;
-  uint32_t *col = data + (size_t)li * N + c0;
+  const uint2 *tw = P.tw_inv + (size_t)g * N;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
   if constexpr (R2 > 0) {
     using Ph = Phase<A, 1 + R1, R2>;
@@ -75,134 +204,75 @@ __global__ __launch_bounds__(W *SubNtt<A>::TPS) void k_oc_intt_col(DevPlan P, ui
     }
     __syncthreads();
   }
-  {
-    using Ph = Phase<A, 1, R1>;
-    uint32_t x[1 << R1];
+  using Ph = Phase<A, 1, R1>;
+  uint32_t x[1 << R1];
 #pragma unroll
-    for (int u = 0; u < (1 << R1); u++)
-      x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : col[(size_t)Ph::elem(tig, u) * rowlen + w];
-    gs_group<A, 1, R1>(x, tig, 1u, tw, q);
+  for (int u = 0; u < (1 << R1); u++)
+    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : col[(size_t)Ph::elem(tig, u) * rowlen + w];
+  gs_group<A, 1, R1>(x, tig, 1u, tw, q);
 #pragma unroll
-    for (int u = 0; u < (1 << R1); u++)
-      col[(size_t)Ph::elem(tig, u) * rowlen + w] = csub(mul_shoup(x[u], pre.x, pre.y, q), q);
-  }
+  for (int u = 0; u < (1 << R1); u++)
+    col[(size_t)Ph::elem(tig, u) * rowlen + w] = csub(mul_shoup(x[u], pre.x, pre.y, q), q);
+  __syncthreads();
 }
 
-// ------------------------------------------------------------ step 3 / 6
-// Basis conversion of one column block to TT target towers fused with the
-// forward column pass.  Tile decode (blockIdx.y):
-//   mode 0 (ModUp): digits in order, each split into ceil(beta_j / TT) tiles
-//     over its targets D_l \ S_j (compressed index); sources xt[lo..hi),
-//     constants up_conv (Montgomery form), output ycol[j][t];
-//   mode 1 (ModDown): poly s = tile / ceil((l+1)/TT), targets q_i; sources
-//     zp[s][0..K), constants dn_conv, output wcol[s][i].
-template <int A, int W, int TT, int MAXS>
-__global__ __launch_bounds__(W *SubNtt<A>::TPS) void k_oc_bconv_col(DevPlan P, OcArgs a, int mode) {
-  using S = SubNtt<A>;
-  constexpr int R1 = S::R1, R2 = S::R2, TPS = S::TPS, E = 1 << R1;
-  __shared__ uint32_t lds[TT][W << A];
+// UP_P / UP_Q / DN: basis conversion of one column block to up to TT target
+// towers, fused with the forward column pass.  Sources are canonical
+// (prescaled) limbs src + i*N, i < nsrc; constant of source i for target e
+// is cbase[i * cstride + tcol[e]] (REDC form).
+template <int A, int TT>
+__device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t *src, uint32_t nsrc,
+                                               const uint32_t *cbase, uint32_t cstride, const uint32_t (&tg)[TT],
+                                               const uint32_t (&tcol)[TT], uint32_t *const (&tout)[TT],
+                                               uint32_t ntgt, uint32_t c0, uint32_t *lds) {
+  using G = ColGeom<A>;
+  constexpr int R1 = G::R1, R2 = G::R2, TPS = G::TPS, W = G::W, E = G::E;
   const size_t N = (size_t)1 << P.log_n;
-  const uint32_t level = a.level, L1 = level + 1, T = L1 + P.num_p;
-  const uint32_t rowlen = 1u << P.logb, c0 = blockIdx.x * W;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
-
-  // ---- decode the tile
-  uint32_t nsrc, cstride, ntgt = 0;
-  const uint32_t *src;
-  const uint32_t *cbase;
-  uint32_t tg[TT], tcol[TT];
-  uint32_t *tout[TT];
-  if (mode == 0) {
-    const uint32_t ndig = (level + P.alpha) / P.alpha;
-    uint32_t tile = blockIdx.y, j = 0, lo = 0, hi = 0, nt = 0;
-    for (; j < ndig; j++) {
-      lo = j * P.alpha;
-      hi = min(lo + P.alpha, L1);
-      nt = (T - (hi - lo) + TT - 1) / TT;
-      if (tile < nt) break;
-      tile -= nt;
-    }
-    if (j == ndig) return;  // grid larger than the tile count: nothing to do
-    const uint32_t s = hi - lo, beta = T - s;
-    nsrc = s;
-    src = a.xt + (size_t)lo * N;
-    cstride = P.ntot;
-    cbase = P.up_conv + (((size_t)j * P.alpha + (s - 1)) * P.alpha) * P.ntot;
-#pragma unroll
-    for (int e = 0; e < TT; e++) {
-      const uint32_t ci = tile * TT + e;
-      if (ci < beta) {
-        const uint32_t t = ci < lo ? ci : ci + s;
-        tg[e] = oc_gidx(P, level, t);
-        tcol[e] = tg[e];
-        tout[e] = a.ycol + ((size_t)j * T + t) * N;
-        ntgt = e + 1;
-      } else {
-        tg[e] = tcol[e] = 0;
-        tout[e] = nullptr;
-      }
-    }
-  } else {
-    const uint32_t per = (L1 + TT - 1) / TT, s = blockIdx.y / per, tile = blockIdx.y % per;
-    nsrc = P.num_p;
-    src = a.zp + (size_t)s * P.num_p * N;
-    cstride = P.num_q;
-    cbase = P.dn_conv;
-#pragma unroll
-    for (int e = 0; e < TT; e++) {
-      const uint32_t i = tile * TT + e;
-      if (i < L1) {
-        tg[e] = i;
-        tcol[e] = i;
-        tout[e] = a.wcol + ((size_t)s * L1 + i) * N;
-        ntgt = e + 1;
-      } else {
-        tg[e] = tcol[e] = 0;
-        tout[e] = nullptr;
-      }
-    }
-  }
-
-  // ---- basis conversion of this thread's phase-1 group
   using Ph1 = Phase<A, 1, R1>;
-  uint32_t y[TT][E];
   ModQ mq[TT];
 #pragma unroll
   for (int e = 0; e < TT; e++) mq[e] = P.mods[tg[e]];
+  uint32_t y[TT][E];
 #pragma unroll
-  for (int u = 0; u < E; u++) {
-    const size_t off = (size_t)Ph1::elem(tig, u) * rowlen + c0 + w;
-    uint32_t xs[MAXS];
+  for (int e = 0; e < TT; e++)
 #pragma unroll
-    for (int i = 0; i < MAXS; i++)
-      if ((uint32_t)i < nsrc) xs[i] = src[(size_t)i * N + off];
+    for (int u = 0; u < E; u++) y[e][u] = 0;
+  for (uint32_t i0 = 0; i0 < nsrc; i0 += 16) {
+    const uint32_t i1 = min(nsrc, i0 + 16);
+    uint64_t acc[TT][E];
 #pragma unroll
-    for (int e = 0; e < TT; e++) {
-      uint64_t acc = 0;
-      uint32_t r = 0;
+    for (int e = 0; e < TT; e++)
 #pragma unroll
-      for (int i = 0; i < MAXS; i++) {
-        if ((uint32_t)i < nsrc) {
-          acc = mad64(xs[i], cbase[(size_t)i * cstride + tcol[e]], acc);
-          if ((i & 15) == 15) { r = csub(r + redc64(acc, mq[e]), mq[e].q); acc = 0; }
-        }
+      for (int u = 0; u < E; u++) acc[e][u] = 0;
+    for (uint32_t i = i0; i < i1; i++) {
+      const uint32_t *s = src + (size_t)i * N + c0 + w;
+      uint32_t c[TT];
+#pragma unroll
+      for (int e = 0; e < TT; e++) c[e] = cbase[(size_t)i * cstride + tcol[e]];
+#pragma unroll
+      for (int u = 0; u < E; u++) {
+        const uint32_t xv = s[(size_t)Ph1::elem(tig, u) * 256];
+#pragma unroll
+        for (int e = 0; e < TT; e++) acc[e][u] = mad64(xv, c[e], acc[e][u]);
       }
-      y[e][u] = csub(r + redc64(acc, mq[e]), mq[e].q);
     }
+#pragma unroll
+    for (int e = 0; e < TT; e++)
+#pragma unroll
+      for (int u = 0; u < E; u++) y[e][u] = csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
   }
-
-  // ---- forward column pass per target
 #pragma unroll
   for (int e = 0; e < TT; e++) {
     if ((uint32_t)e < ntgt) {
-      const uint2 *tw = P.tw_fwd + tg[e] * N;
+      const uint2 *tw = P.tw_fwd + (size_t)tg[e] * N;
       ct_group<A, 1, R1>(y[e], tig, 1u, tw, mq[e].q);
       if constexpr (R2 > 0) {
 #pragma unroll
-        for (int u = 0; u < E; u++) lds[e][Ph1::elem(tig, u) * W + w] = y[e][u];
+        for (int u = 0; u < E; u++) lds[e * G::LDS + Ph1::elem(tig, u) * W + w] = y[e][u];
       } else {
 #pragma unroll
-        for (int u = 0; u < E; u++) tout[e][(size_t)Ph1::elem(tig, u) * rowlen + c0 + w] = y[e][u];
+        for (int u = 0; u < E; u++) tout[e][(size_t)Ph1::elem(tig, u) * 256 + c0 + w] = y[e][u];
       }
     }
   }
@@ -212,223 +282,223 @@ __global__ __launch_bounds__(W *SubNtt<A>::TPS) void k_oc_bconv_col(DevPlan P, O
 #pragma unroll
     for (int e = 0; e < TT; e++) {
       if ((uint32_t)e < ntgt) {
-        const uint2 *tw = P.tw_fwd + tg[e] * N;
+        const uint2 *tw = P.tw_fwd + (size_t)tg[e] * N;
 #pragma unroll
         for (int gi = 0; gi < Ph2::GROUPS / TPS; gi++) {
           const int gg = tig + gi * TPS;
           uint32_t x[1 << R2];
 #pragma unroll
-          for (int u = 0; u < (1 << R2); u++) x[u] = lds[e][Ph2::elem(gg, u) * W + w];
+          for (int u = 0; u < (1 << R2); u++) x[u] = lds[e * G::LDS + Ph2::elem(gg, u) * W + w];
           ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
 #pragma unroll
-          for (int u = 0; u < (1 << R2); u++) tout[e][(size_t)Ph2::elem(gg, u) * rowlen + c0 + w] = x[u];
+          for (int u = 0; u < (1 << R2); u++) tout[e][(size_t)Ph2::elem(gg, u) * 256 + c0 + w] = x[u];
         }
       }
     }
   }
-}
-
-// ------------------------------------------------------------ step 4 / 7
-// Row pass helpers.  A row of 256 words is handled by 16 threads; phase 1
-// (stages 1-4 of the row) holds k = tig + 16u, phase 2 (stages 5-8) holds
-// k = 16 tig + u.
-constexpr int kPad = 272;
-__device__ __forceinline__ int rl(int k) { return k + (k >> 4); }
-
-// Forward row transform of a row read from global (phase-1 layout); leaves
-// the result in x in phase-2 layout.  Uses lds row `lr` (kPad words).
-__device__ __forceinline__ void row_fwd_from_global(uint32_t (&x)[16], const uint32_t *row, uint32_t *lr, int tig,
-                                                    uint32_t M, const uint2 *tw, uint32_t q) {
-#pragma unroll
-  for (int u = 0; u < 16; u++) x[u] = row[tig + 16 * u];
-  ct_group<8, 1, 4>(x, tig, M, tw, q);
-#pragma unroll
-  for (int u = 0; u < 16; u++) lr[rl(tig + 16 * u)] = x[u];
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 16; u++) x[u] = lr[rl(16 * tig + u)];
-  ct_group<8, 5, 4>(x, tig, M, tw, q);
   __syncthreads();
 }
 
-// Inverse row transform of x (phase-2 layout) written to global (phase-1
-// layout, lazy [0, 2q)).
-__device__ __forceinline__ void row_inv_to_global(uint32_t (&x)[16], uint32_t *row, uint32_t *lr, int tig, uint32_t M,
-                                                  const uint2 *tw, uint32_t q) {
-  gs_group<8, 5, 4>(x, tig, M, tw, q);
-#pragma unroll
-  for (int u = 0; u < 16; u++) lr[rl(16 * tig + u)] = x[u];
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 16; u++) x[u] = lr[rl(tig + 16 * u)];
-  gs_group<8, 1, 4>(x, tig, M, tw, q);
-#pragma unroll
-  for (int u = 0; u < 16; u++) row[tig + 16 * u] = x[u];
-  __syncthreads();
-}
-
-__device__ __forceinline__ void load16(uint32_t (&x)[16], const uint32_t *p) {
-  const uint4 *v = reinterpret_cast<const uint4 *>(p);
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    uint4 t = v[i];
-    x[4 * i] = t.x; x[4 * i + 1] = t.y; x[4 * i + 2] = t.z; x[4 * i + 3] = t.w;
-  }
-}
-__device__ __forceinline__ void store16(uint32_t *p, const uint32_t (&x)[16]) {
-  uint4 *v = reinterpret_cast<uint4 *>(p);
-#pragma unroll
-  for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
-}
-
-// IS_P: blockIdx.y = k, tower t = l+1+k; otherwise blockIdx.y = i, tower i.
-template <int RB, bool IS_P>
-__global__ __launch_bounds__(RB * 16) void k_oc_row(DevPlan P, OcArgs a) {
-  __shared__ uint32_t lds[RB * kPad];
+// UP_P and UP_Q tiles: decode (digit, target chunk, column block).
+template <int A, int TT>
+__device__ __forceinline__ void tile_up(const DevPlan &P, const OcJob &J, uint32_t tile, bool special, uint32_t ttu,
+                                        uint32_t *lds) {
+  using G = ColGeom<A>;
   const size_t N = (size_t)1 << P.log_n;
-  const uint32_t level = a.level, L1 = level + 1, T = L1 + P.num_p;
-  const uint32_t t = IS_P ? L1 + blockIdx.y : blockIdx.y;
-  const uint32_t g = oc_gidx(P, level, t);
+  const uint32_t L1 = J.level + 1, T = L1 + P.num_p, ndig = cdiv(L1, P.alpha);
+  const uint32_t unit = tile / G::CB, c0 = (tile % G::CB) * G::W;
+  uint32_t j, chunk, lo, s;
+  if (special) {
+    const uint32_t per = cdiv(P.num_p, ttu);
+    j = unit / per;
+    chunk = unit % per;
+    lo = j * P.alpha;
+    s = min(lo + P.alpha, L1) - lo;
+  } else {
+    uint32_t u = unit;
+    for (j = 0; j < ndig; j++) {
+      lo = j * P.alpha;
+      s = min(lo + P.alpha, L1) - lo;
+      const uint32_t nt = cdiv(L1 - s, ttu);
+      if (u < nt) break;
+      u -= nt;
+    }
+    if (j >= ndig) return;
+    chunk = u;
+  }
+  uint32_t tg[TT], tcol[TT], ntgt = 0;
+  uint32_t *tout[TT];
+#pragma unroll
+  for (int e = 0; e < TT; e++) {
+    const uint32_t ci = chunk * ttu + e;
+    uint32_t t = 0;
+    bool ok;
+    if (special) {
+      ok = (uint32_t)e < ttu && ci < P.num_p;
+      t = L1 + ci;
+    } else {
+      ok = (uint32_t)e < ttu && ci < L1 - s;
+      t = ci < lo ? ci : ci + s;
+    }
+    tg[e] = ok ? oc_gidx(P.num_q, J.level, t) : 0;
+    tcol[e] = tg[e];
+    tout[e] = ok ? J.ycol + ((size_t)j * T + t) * N : nullptr;
+    if (ok) ntgt = e + 1;
+  }
+  tile_bconv_col<A, TT>(P, J.xt + (size_t)lo * N, s, P.up_conv + ((size_t)j * P.alpha + (s - 1)) * P.alpha * P.ntot,
+                        P.ntot, tg, tcol, tout, ntgt, c0, lds);
+}
+
+// DN tiles: decode (poly, Q-target chunk, column block).
+template <int A, int TT>
+__device__ __forceinline__ void tile_dn(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t ttd, uint32_t *lds) {
+  using G = ColGeom<A>;
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t L1 = J.level + 1, per = cdiv(L1, ttd);
+  const uint32_t unit = tile / G::CB, c0 = (tile % G::CB) * G::W, s = unit / per, chunk = unit % per;
+  uint32_t tg[TT], tcol[TT], ntgt = 0;
+  uint32_t *tout[TT];
+#pragma unroll
+  for (int e = 0; e < TT; e++) {
+    const uint32_t i = chunk * ttd + e;
+    const bool ok = (uint32_t)e < ttd && i < L1;
+    tg[e] = tcol[e] = ok ? i : 0;
+    tout[e] = ok ? J.wcol + ((size_t)s * L1 + i) * N : nullptr;
+    if (ok) ntgt = e + 1;
+  }
+  tile_bconv_col<A, TT>(P, J.zp + (size_t)s * P.num_p * N, P.num_p, P.dn_conv, P.num_q, tg, tcol, tout, ntgt, c0, lds);
+}
+
+// ROW_P / ROW_Q tiles: (tower, row block).
+template <bool IS_P>
+__device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
+  const uint32_t rbk = (1u << P.loga) / kRB, unit = tile / rbk, blk = tile % rbk;
+  const uint32_t t = IS_P ? L1 + unit : unit;
+  const uint32_t g = oc_gidx(P.num_q, level, t);
   const ModQ m = P.mods[g];
   const uint32_t q = m.q;
-  const uint2 *twf = P.tw_fwd + g * N, *twi = P.tw_inv + g * N;
   const int rr = threadIdx.x >> 4, tig = threadIdx.x & 15;
-  const uint32_t row = blockIdx.x * RB + rr;
-  const uint32_t M = (1u << P.loga) + row;
+  const uint32_t row = blk * kRB + rr, M = (1u << P.loga) + row;
   const size_t roff = (size_t)row * 256;
   uint32_t *lr = lds + rr * kPad;
-  const uint32_t ndig = (level + P.alpha) / P.alpha;
+  const uint32_t ndig = cdiv(L1, P.alpha);
+  RowTw twf;
+  load_row_tw(twf, P.tw_fwd + (size_t)g * N, tig, M);
 
+  // at most 16 digits (checked at plan creation): 16 products < 2^64 need one REDC
   uint64_t acc0[16], acc1[16];
-  uint32_t part0[16], part1[16];
 #pragma unroll
-  for (int u = 0; u < 16; u++) { acc0[u] = acc1[u] = 0; part0[u] = part1[u] = 0; }
+  for (int u = 0; u < 16; u++) acc0[u] = acc1[u] = 0;
   for (uint32_t j = 0; j < ndig; j++) {
     const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, L1);
     uint32_t x[16];
     if (!IS_P && t >= lo && t < hi) {
-      load16(x, a.d + (size_t)t * N + roff + 16 * tig);  // own digit: bypass
+      load16(x, J.d + (size_t)t * N + roff + 16 * tig);  // own digit: bypass
     } else {
-      row_fwd_from_global(x, a.ycol + ((size_t)j * T + t) * N + roff, lr, tig, M, twf, q);
+      row_fwd(x, J.ycol + ((size_t)j * T + t) * N + roff, lr, tig, twf, q);
 #pragma unroll
       for (int u = 0; u < 16; u++) x[u] = canon4(x[u], q);
     }
     uint32_t e0[16], e1[16];
-    load16(e0, a.evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + roff + 16 * tig);
-    load16(e1, a.evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + roff + 16 * tig);
+    load16(e0, J.evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + roff + 16 * tig);
+    load16(e1, J.evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + roff + 16 * tig);
 #pragma unroll
     for (int u = 0; u < 16; u++) {
       acc0[u] = mad64(x[u], e0[u], acc0[u]);
       acc1[u] = mad64(x[u], e1[u], acc1[u]);
     }
-    if ((j & 15) == 15) {
-#pragma unroll
-      for (int u = 0; u < 16; u++) {
-        part0[u] = csub(part0[u] + redc64(acc0[u], m), q);
-        part1[u] = csub(part1[u] + redc64(acc1[u], m), q);
-        acc0[u] = acc1[u] = 0;
-      }
-    }
   }
   uint32_t r0[16], r1[16];
 #pragma unroll
   for (int u = 0; u < 16; u++) {
-    r0[u] = csub(part0[u] + redc64(acc0[u], m), q);
-    r1[u] = csub(part1[u] + redc64(acc1[u], m), q);
+    r0[u] = redc64(acc0[u], m);
+    r1[u] = redc64(acc1[u], m);
   }
   if (IS_P) {
-    const uint32_t k = blockIdx.y;
-    row_inv_to_global(r0, a.zp + ((size_t)0 * P.num_p + k) * N + roff, lr, tig, M, twi, q);
-    row_inv_to_global(r1, a.zp + ((size_t)1 * P.num_p + k) * N + roff, lr, tig, M, twi, q);
+    const uint32_t k = unit;
+    RowTw twi;
+    load_row_tw(twi, P.tw_inv + (size_t)g * N, tig, M);
+    row_inv(r0, J.zp + ((size_t)0 * P.num_p + k) * N + roff, lr, tig, twi, q);
+    row_inv(r1, J.zp + ((size_t)1 * P.num_p + k) * N + roff, lr, tig, twi, q);
   } else {
     const uint2 f = P.dn_fin[t];
 #pragma unroll
     for (int s = 0; s < 2; s++) {
       uint32_t wv[16];
-      row_fwd_from_global(wv, a.wcol + ((size_t)s * L1 + t) * N + roff, lr, tig, M, twf, q);
+      row_fwd(wv, J.wcol + ((size_t)s * L1 + t) * N + roff, lr, tig, twf, q);
       uint32_t o[16];
 #pragma unroll
       for (int u = 0; u < 16; u++) {
         const uint32_t av = s ? r1[u] : r0[u];
         o[u] = csub(mul_shoup(av + q - canon4(wv[u], q), f.x, f.y, q), q);
       }
-      store16(a.out + ((size_t)s * L1 + t) * N + roff + 16 * tig, o);
+      store16(J.out + ((size_t)s * L1 + t) * N + roff + 16 * tig, o);
     }
   }
 }
 
-// ------------------------------------------------------------ launcher
-// Unrolled basis-conversion variants are limited to TT * 2^R1 * MAXS <= 1024
-// products per thread; larger requests fall back to fewer targets per tile.
-template <int A, int TT, int MS>
-constexpr bool bc_ok() { return TT * (1 << SubNtt<A>::R1) * MS <= 1024; }
-
-template <int A, int TT, int MS>
-static void launch_bc(const Plan &pl, const OcArgs &a, int mode, uint32_t tiles, hipStream_t st) {
-  constexpr int NT = 16 * SubNtt<A>::TPS;
-  const uint32_t cols = 1u << pl.dev.logb;
-  KS_LAUNCH(pl, mode == 0 ? "oc.bconv_col.up" : "oc.bconv_col.down", (k_oc_bconv_col<A, 16, TT, MS>), dim3(cols / 16, tiles), dim3(NT), 0, st, pl.dev, a, mode);
-}
-
-// Largest allowed tile <= want for `nsrc` sources.
-template <int A>
-static uint32_t bc_tile(uint32_t want, uint32_t nsrc) {
-  const uint32_t ms = nsrc <= 8 ? 8 : nsrc <= 16 ? 16 : 32;
-  uint32_t tt = want >= 4 ? 4 : want >= 2 ? 2 : 1;
-  while (tt > 1 && tt * (1u << SubNtt<A>::R1) * ms > 1024) tt >>= 1;
-  return tt;
-}
-
-template <int A>
-static bool dispatch_bc(const Plan &pl, const OcArgs &a, int mode, uint32_t tt, uint32_t nsrc, uint32_t tiles,
-                        hipStream_t st) {
-#define KS_TRY(TTv, MSv)                                                            \
-  if constexpr (bc_ok<A, TTv, MSv>()) {                                             \
-    if (tt == TTv && (MSv == 8 ? nsrc <= 8 : MSv == 16 ? (nsrc > 8 && nsrc <= 16) : nsrc > 16)) { \
-      launch_bc<A, TTv, MSv>(pl, a, mode, tiles, st);                               \
-      return true;                                                                  \
-    }                                                                               \
+// One tile of one phase.
+template <int A, int TTU, int TTD>
+__device__ __forceinline__ void oc_tile(const DevPlan &P, const OcJob &J, uint32_t phase, uint32_t tile,
+                                        uint32_t *lds) {
+  switch (phase) {
+    case OC_INTT_ROW: tile_intt_row(P, J, tile, lds); break;
+    case OC_INTT_COL: tile_intt_col<A>(P, J, tile, false, lds); break;
+    case OC_UP_P: tile_up<A, TTU>(P, J, tile, true, J.ttu, lds); break;
+    case OC_ROW_P: tile_row<true>(P, J, tile, lds); break;
+    case OC_UP_Q: tile_up<A, TTU>(P, J, tile, false, J.ttu, lds); break;
+    case OC_INTT_COL_DN: tile_intt_col<A>(P, J, tile, true, lds); break;
+    case OC_DN: tile_dn<A, TTD>(P, J, tile, J.ttd, lds); break;
+    case OC_ROW_Q: tile_row<false>(P, J, tile, lds); break;
   }
-  KS_TRY(1, 8) KS_TRY(1, 16) KS_TRY(1, 32)
-  KS_TRY(2, 8) KS_TRY(2, 16) KS_TRY(2, 32)
-  KS_TRY(4, 8) KS_TRY(4, 16) KS_TRY(4, 32)
-#undef KS_TRY
-  return false;
+}
+
+template <int A, int TT>
+constexpr int oc_lds_words() {
+  return (TT * ColGeom<A>::LDS > kRowLds) ? TT * ColGeom<A>::LDS : kRowLds;
+}
+
+// One launch per phase: grid x = tiles (max over jobs), grid z = job.
+template <int A, int PHASE, int TT>
+__global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, const OcJob *jobs) {
+  __shared__ uint32_t lds[oc_lds_words<A, TT>()];
+  const OcJob J = jobs ? jobs[blockIdx.z] : one;
+  if (blockIdx.x >= J.tiles[PHASE]) return;
+  oc_tile<A, TT, TT>(P, J, PHASE, blockIdx.x, lds);
+}
+
+static const char *const kOcPhaseName[OC_NPHASE] = {"oc.intt_row", "oc.intt_col.up", "oc.bconv_col.up_p",
+                                                   "oc.row.p", "oc.bconv_col.up_q", "oc.intt_col.down",
+                                                   "oc.bconv_col.down", "oc.row.q"};
+
+template <int A, int PHASE, int TT>
+static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
+                         hipStream_t st) {
+  if (!tiles) return;  // e.g. no Q target outside the only digit at level 0
+  KS_LAUNCH(pl, kOcPhaseName[PHASE], (k_oc_phase<A, PHASE, TT>), dim3(tiles, 1, count), dim3(kOcThreads), 0, st,
+            pl.dev, one, jobs);
+}
+
+template <int A, int TT>
+static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
+                             const uint32_t *max_tiles, hipStream_t st) {
+  launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
+  launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
+  launch_phase<A, OC_UP_P, TT>(pl, one, jobs, count, max_tiles[OC_UP_P], st);
+  launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
+  launch_phase<A, OC_UP_Q, TT>(pl, one, jobs, count, max_tiles[OC_UP_Q], st);
+  launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
+  launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
+  launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
 }
 
 template <int A>
-hipError_t oc_cols(const Plan &pl, const OcArgs &a, hipStream_t st) {
-  const uint32_t L1 = a.level + 1, T = L1 + pl.num_p, K = pl.num_p;
-  const uint32_t cols = 1u << pl.dev.logb;
-  constexpr int NT = 16 * SubNtt<A>::TPS;
-  const uint32_t want = pl.cfg.tile_towers ? pl.cfg.tile_towers : 1;
-  // step 2: inverse column pass of the inputs
-  KS_LAUNCH(pl, "oc.intt_col.up", (k_oc_intt_col<A, 16>), dim3(cols / 16, L1), dim3(NT), 0, st, pl.dev, a.xt, a.level, 0);
-  // step 3: ModUp conversion + forward column pass
-  const uint32_t tt_up = bc_tile<A>(want, pl.alpha);
-  uint32_t tiles = 0;
-  const uint32_t D = num_digits(pl, a.level);
-  for (uint32_t j = 0; j < D; j++) {
-    uint32_t lo, hi;
-    digit_range(pl, a.level, j, &lo, &hi);
-    tiles += (T - (hi - lo) + tt_up - 1) / tt_up;
-  }
-  if (!dispatch_bc<A>(pl, a, 0, tt_up, pl.alpha, tiles, st)) return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // step 4: special towers, row pass
-  const uint32_t rows = 1u << pl.dev.loga;
-  const uint32_t RB = rows >= 8 ? 8 : rows;
-  if (RB == 8) KS_LAUNCH(pl, "oc.row.p", (k_oc_row<8, true>), dim3(rows / 8, K), dim3(128), 0, st, pl.dev, a);
-  else KS_LAUNCH(pl, "oc.row.p", (k_oc_row<4, true>), dim3(rows / 4, K), dim3(64), 0, st, pl.dev, a);
-  // step 5: inverse column pass of the special towers
-  KS_LAUNCH(pl, "oc.intt_col.down", (k_oc_intt_col<A, 16>), dim3(cols / 16, 2 * K), dim3(NT), 0, st, pl.dev, a.zp, a.level, 1);
-  // step 6: ModDown conversion + forward column pass
-  const uint32_t tt_dn = bc_tile<A>(want, K);
-  if (!dispatch_bc<A>(pl, a, 1, tt_dn, K, 2 * ((L1 + tt_dn - 1) / tt_dn), st)) return hipErrorInvalidValue;
-  // step 7: Q towers, row pass with ModDown
-  if (RB == 8) KS_LAUNCH(pl, "oc.row.q", (k_oc_row<8, false>), dim3(rows / 8, L1), dim3(128), 0, st, pl.dev, a);
-  else KS_LAUNCH(pl, "oc.row.q", (k_oc_row<4, false>), dim3(rows / 4, L1), dim3(64), 0, st, pl.dev, a);
+hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
+                     uint32_t tt, hipStream_t st) {
+  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, st);
+  else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, st);
   return hipGetLastError();
 }
 

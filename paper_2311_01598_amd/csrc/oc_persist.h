@@ -1,0 +1,109 @@
+// oc_persist.h -- one persistent launch for a batch of Output-Centric key
+// switches at mixed levels (work queue with per-job phase counters).
+//
+// Work items are the tiles of every (phase, job), listed phase-major then
+// job-major (the segment table).  Each workgroup takes the next item with an
+// atomic increment, waits until the phases that item depends on are complete
+// for its job, runs the tile, and bumps the (job, phase) completion counter.
+// Every dependency points to an earlier phase, so an item only ever waits on
+// items dequeued before it, each held by a running workgroup: the wait
+// always ends, whatever the number of resident workgroups.  Each wait is
+// nevertheless bounded (spin_limit polls); exceeding it sets the error flag
+// and the item runs anyway (wrong values, valid addresses), so the kernel
+// always drains.
+#pragma once
+#include "oc_kernels.h"
+
+namespace ks {
+
+// Phases each phase waits for (bit q = phase q complete for the same job).
+__host__ __device__ constexpr uint32_t oc_deps(uint32_t phase) {
+  return phase == OC_INTT_COL      ? (1u << OC_INTT_ROW)
+         : phase == OC_UP_P        ? (1u << OC_INTT_COL)
+         : phase == OC_ROW_P       ? (1u << OC_UP_P)
+         : phase == OC_UP_Q        ? (1u << OC_INTT_COL)
+         : phase == OC_INTT_COL_DN ? (1u << OC_ROW_P)
+         : phase == OC_DN          ? (1u << OC_INTT_COL_DN)
+         : phase == OC_ROW_Q       ? ((1u << OC_DN) | (1u << OC_UP_Q))
+                                   : 0u;
+}
+
+// Clears the control words with an ordinary kernel (a fill kernel rather
+// than a memset node, so the launch captures cleanly into a graph).
+template <int A>
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t *p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+// ctl: [0] queue head, [1] error flag, [2..3] unused, [4 + job*8 + phase] done counters.
+template <int A>
+__global__ __launch_bounds__(kOcThreads) void k_oc_persistent(DevPlan P, const OcJob *jobs, const OcSeg *segs,
+                                                              uint32_t nsegs, uint32_t total, uint32_t *ctl,
+                                                              uint32_t spin_limit) {
+  __shared__ uint32_t lds[oc_lds_words<A, 1>()];
+  __shared__ uint32_t s_item;
+  uint32_t *done = ctl + 4;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    uint32_t lo = 0, hi = nsegs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (segs[mid].start <= item) lo = mid;
+      else hi = mid;
+    }
+    const OcSeg sg = segs[lo];
+    const OcJob J = jobs[sg.job];
+    if (threadIdx.x == 0) {
+      // relaxed agent-scope polls (coherent loads, no cache invalidation per
+      // poll), one acquire fence once the counts are reached
+      const uint32_t deps = oc_deps(sg.phase);
+      for (uint32_t q = 0; q < OC_NPHASE; q++) {
+        if (!((deps >> q) & 1u)) continue;
+        const uint32_t need = J.tiles[q];
+        uint32_t *cnt = &done[sg.job * OC_NPHASE + q];
+        uint32_t spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (++spins > spin_limit) {
+            atomicOr(&ctl[1], 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    oc_tile<A, 1, 1>(P, J, sg.phase, item - sg.start, lds);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&done[sg.job * OC_NPHASE + sg.phase], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int A>
+hipError_t oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs, uint32_t total,
+                         uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st) {
+  static int per_cu = 0, cus = 0;
+  if (!per_cu) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return hipErrorUnknown;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_oc_persistent<A>, kOcThreads, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    cus = prop.multiProcessorCount;
+  }
+  const uint32_t nctl = 4 + count * OC_NPHASE;
+  KS_LAUNCH(pl, "oc.zero_ctl", k_zero_words<A>, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
+  const uint32_t grid = std::min<uint32_t>((uint32_t)(per_cu * cus), total);
+  KS_LAUNCH(pl, "oc.persistent", k_oc_persistent<A>, dim3(grid), dim3(kOcThreads), 0, st, pl.dev, jobs, segs, nsegs,
+            total, ctl, spin_limit);
+  return hipGetLastError();
+}
+
+}  // namespace ks

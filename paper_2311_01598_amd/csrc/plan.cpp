@@ -250,6 +250,40 @@ void plan_free(Plan *pl) {
   for (hipEvent_t e : pl->trace.pool) (void)hipEventDestroy(e);
   pl->trace.marks.clear();
   pl->trace.pool.clear();
+  std::lock_guard<std::mutex> g2(pl->staging.mu);
+  for (auto &s : pl->staging.slots) {
+    (void)hipEventSynchronize(s.done);
+    (void)hipEventDestroy(s.done);
+    (void)hipHostFree(s.host);
+  }
+  pl->staging.slots.clear();
+}
+
+hipError_t upload_async(const Plan &pl, void *dst, const void *src, size_t bytes, hipStream_t st) {
+  Staging &sg = pl.staging;
+  std::lock_guard<std::mutex> g(sg.mu);
+  StagingSlot *slot = nullptr;
+  for (auto &s : sg.slots)
+    if (s.bytes >= bytes && hipEventQuery(s.done) == hipSuccess) {
+      slot = &s;
+      break;
+    }
+  if (!slot) {
+    StagingSlot s;
+    s.bytes = std::max<size_t>(bytes, 64 << 10);
+    hipError_t e = hipHostMalloc(&s.host, s.bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
+      (void)hipHostFree(s.host);
+      return e;
+    }
+    sg.slots.push_back(s);
+    slot = &sg.slots.back();
+  }
+  std::memcpy(slot->host, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, slot->host, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(slot->done, st);
 }
 
 bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t *stop) {

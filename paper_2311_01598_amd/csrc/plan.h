@@ -57,6 +57,19 @@ struct Trace {
   std::vector<TraceMark> marks;
 };
 
+// Pinned host buffers for asynchronous uploads (batch job tables): a slot
+// is reused only after the event recorded behind its copy has completed,
+// so the source stays valid for as long as the copy may read it.
+struct StagingSlot {
+  void *host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+};
+struct Staging {
+  std::mutex mu;
+  std::vector<StagingSlot> slots;
+};
+
 struct Plan {
   uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
   int device = -1;
@@ -68,7 +81,12 @@ struct Plan {
   std::mutex lock;  // guards the graph cache and config
   void *graph_cache = nullptr;
   mutable Trace trace;
+  mutable Staging staging;
 };
+
+// Asynchronous host-to-device copy of `bytes` from `src` through a pinned
+// staging slot (src may be freed as soon as this returns).
+hipError_t upload_async(const Plan &pl, void *dst, const void *src, size_t bytes, hipStream_t st);
 
 // True (with two events to attach to the launch) while tracing is on.
 bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t *stop);
