@@ -66,6 +66,65 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
+def batched_rate(ks, plan, evks, mods, count, reps, np, torch, synth):
+    """Key switches per second for `count` ciphertexts of the bench workload
+    in one batch call (shared key per call, keys rotating across calls)."""
+    n, l1 = plan.n, LEVEL + 1
+    plan.configure("oc")
+    ins = [torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 200 + i)).view(np.int32)).cuda()
+           for i in range(count)]
+    outs = [torch.empty((2, l1, n), dtype=torch.int32, device="cuda") for _ in range(count)]
+    ws = plan.workspace([LEVEL] * count)
+    jobs = lambda r: [(evks[r % len(evks)], LEVEL, x, o) for x, o in zip(ins, outs)]
+    plan.keyswitch_batch(jobs(0), workspace=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for r in range(reps):
+        plan.keyswitch_batch(jobs(r), workspace=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    return {"ciphertexts_per_call": count, "calls": reps, "ks_per_s": round(count * reps / (ms / 1e3), 1),
+            "ms_per_call": round(ms / reps, 4)}
+
+
+def mixed_rate(ks, dnum, reps, np, torch, synth):
+    """64 ciphertexts at levels with l+1 ~ U[8, 24], N=2^16, K = alpha, one
+    shared key: OC batched vs the same 64 switched one at a time with MP."""
+    alpha = -(-NUM_Q // dnum)
+    plan = ks.Plan(LOG_N, NUM_Q, dnum, alpha)
+    n, mods = plan.n, plan.moduli
+    levels = synth.batch_levels(64, 8, 24, synth.seed_for(3, dnum))
+    evk = torch.from_numpy(synth.uniform_evk(mods, dnum, n, synth.seed_for(3, 100 + dnum)).view(np.int32)).cuda()
+    ins = [torch.from_numpy(synth.uniform_limbs(mods[:l + 1], n, synth.seed_for(3, 300 + i)).view(np.int32)).cuda()
+           for i, l in enumerate(levels)]
+    outs = [torch.empty((2, l + 1, n), dtype=torch.int32, device="cuda") for l in levels]
+    jobs = [(evk, l, x, o) for l, x, o in zip(levels, ins, outs)]
+    res = {}
+    for name, sched, batched in (("oc_batched", "oc", True), ("mp_one_at_a_time", "mp", False)):
+        plan.configure(sched)
+        ws = plan.workspace(levels if batched else [max(levels)])
+
+        def once():
+            if batched:
+                plan.keyswitch_batch(jobs, workspace=ws)
+            else:
+                for e, l, x, o in jobs:
+                    plan.keyswitch(e, l, x, out=o, workspace=ws)
+        once()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            once()
+        b.record()
+        torch.cuda.synchronize()
+        res[name] = round(64 * reps / (a.elapsed_time(b) / 1e3), 1)
+    plan.close()
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +138,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy 3 times (counter calibration) and exit")
     ap.add_argument("--rates", action="store_true", help="also run the ALU / copy rate probes")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="ciphertexts per call in the batched measurement of the same workload (0 = skip)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="also time 64-ciphertext batches at levels l+1 ~ U[8,24] for dnum 2, 3, 4")
     return ap.parse_args()
 
 
@@ -186,6 +249,12 @@ def main():
     res["whole_keyswitch"] = {"muls": tot_muls, "mul_frac": round(tot_muls * ks_per_s / MUL_PEAK_PER_S, 4),
                               "hbm_frac": round(nbytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
     res["stages"] = stages
+    if args.batch:
+        res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)
+    if args.mixed:
+        res["mixed_batches"] = {}
+        for dn in (2, 3, 4):
+            res["mixed_batches"][f"dnum{dn}"] = mixed_rate(ks, dn, max(3, args.steps // 40), np, torch, synth)
     if args.rates:
         res["device_rates"] = {k: round(v / 1e12, 4) for k, v in ks.ks_device_rates().items()}
     if args.compare:

@@ -72,7 +72,8 @@ struct OcSeg {
   uint32_t start, job, phase, pad;
 };
 
-constexpr int kRB = 16;  // rows per OC row tile
+constexpr int kRB = 16;   // rows per OC inverse-row tile (one transform per row)
+constexpr int kRBQ = 4;   // rows per OC ROW_P / ROW_Q tile (four transforms per row in parallel)
 
 __host__ __device__ __forceinline__ uint32_t oc_gidx(uint32_t num_q, uint32_t level, uint32_t t) {
   return t <= level ? t : num_q + (t - level - 1);
@@ -82,7 +83,7 @@ __host__ __device__ __forceinline__ uint32_t cdiv(uint32_t a, uint32_t b) { retu
 // Tile counts of every phase for a job at `level`.
 __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint32_t alpha, uint32_t K,
                                                uint32_t level, uint32_t ttu, uint32_t ttd, uint32_t *n) {
-  const uint32_t L1 = level + 1, rbk = (1u << loga) / kRB, ndig = cdiv(L1, alpha);
+  const uint32_t L1 = level + 1, rbk = (1u << loga) / kRB, rbq = (1u << loga) / kRBQ, ndig = cdiv(L1, alpha);
   uint32_t upq = 0;
   for (uint32_t j = 0; j < ndig; j++) {
     const uint32_t lo = j * alpha, s = (lo + alpha < L1 ? lo + alpha : L1) - lo;
@@ -91,11 +92,11 @@ __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint3
   n[OC_INTT_ROW] = rbk * L1;
   n[OC_INTT_COL] = cb * L1;
   n[OC_UP_P] = cb * ndig * cdiv(K, ttu);
-  n[OC_ROW_P] = rbk * K;
+  n[OC_ROW_P] = rbq * K;
   n[OC_UP_Q] = cb * upq;
   n[OC_INTT_COL_DN] = cb * 2 * K;
   n[OC_DN] = cb * 2 * cdiv(L1, ttd);
-  n[OC_ROW_Q] = rbk * L1;
+  n[OC_ROW_Q] = rbq * L1;
 }
 
 // Effective targets per basis-conversion tile (1 or 2) for a column pass of

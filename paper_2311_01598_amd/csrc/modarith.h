@@ -30,10 +30,19 @@ __device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) {
   return d < a ? d : a;  // a >= m ? a - m : a
 }
 
+// -q mod 2^32, hidden from the optimiser (which would otherwise turn
+// h * (-q) back into a subtraction of h * q) so a w - h q folds into one
+// multiply-add.  The empty asm emits nothing and is shared between uses.
+__device__ __forceinline__ uint32_t neg_mod(uint32_t q) {
+  uint32_t nq = 0u - q;
+  asm("" : "+v"(nq));
+  return nq;
+}
+
 // a * w mod q in [0, 2q), any a < 2^32.
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
-  uint32_t h = __umulhi(a, wp);
-  return a * w - h * q;
+  const uint32_t h = __umulhi(a, wp);
+  return a * w + h * neg_mod(q);
 }
 
 __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
@@ -43,7 +52,7 @@ __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
 // T * 2^-32 mod q, canonical, for any T < 2^64.
 __device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
   uint32_t hi = (uint32_t)(T >> 32), lo = (uint32_t)T;
-  hi -= __umulhi(hi, m.mu) * m.q;        // [0, 2q)
+  hi += __umulhi(hi, m.mu) * neg_mod(m.q);  // hi - floor(hi mu / 2^32) q, in [0, 2q)
   uint32_t u = lo * m.qinv;
   uint64_t s = (uint64_t)u * m.q + (((uint64_t)hi << 32) | lo);
   uint32_t r = (uint32_t)(s >> 32);      // [0, 3q)
@@ -52,18 +61,24 @@ __device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
 }
 
 // Harvey forward (Cooley-Tukey) butterfly, inputs and outputs in [0, 4q).
-__device__ __forceinline__ void bfly_ct(uint32_t &x, uint32_t &y, uint32_t w, uint32_t wp, uint32_t q) {
-  uint32_t two_q = q << 1;
-  uint32_t a = csub(x, two_q);
-  uint32_t t = mul_shoup(y, w, wp, q);
-  x = a + t;
-  y = a + two_q - t;
+// The forward twiddle tables hold (-w mod 2^32, w') so that the Shoup
+// product comes out negated: nt = h q + y (-w) = -(y w - h q) = -t mod 2^32
+// with t in [0, 2q); then x' = a + t = a - nt and y' = a + 2q - t =
+// a + 2q + nt, a single three-input add.
+__device__ __forceinline__ void bfly_ct(uint32_t &x, uint32_t &y, uint32_t wneg, uint32_t wp, uint32_t q) {
+  const uint32_t two_q = q << 1;
+  const uint32_t a = csub(x, two_q);
+  const uint32_t h = __umulhi(y, wp);
+  const uint32_t nt = h * q + y * wneg;
+  x = a - nt;
+  y = a + two_q + nt;
 }
 
-// Harvey inverse (Gentleman-Sande) butterfly, inputs and outputs in [0, 2q).
+// Harvey inverse (Gentleman-Sande) butterfly, inputs and outputs in [0, 2q);
+// inverse tables hold (w, w').
 __device__ __forceinline__ void bfly_gs(uint32_t &x, uint32_t &y, uint32_t w, uint32_t wp, uint32_t q) {
-  uint32_t two_q = q << 1;
-  uint32_t a = x, b = y;
+  const uint32_t two_q = q << 1;
+  const uint32_t a = x, b = y;
   x = csub(a + b, two_q);
   y = mul_shoup(a + two_q - b, w, wp, q);
 }

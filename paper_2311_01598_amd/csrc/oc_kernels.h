@@ -238,6 +238,17 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   for (int e = 0; e < TT; e++)
 #pragma unroll
     for (int u = 0; u < E; u++) y[e][u] = 0;
+  // Element u of this thread sits at row (tig + u * 2^LOB) of the column
+  // block: the per-u part of the address is uniform (scalar base), the
+  // per-thread part one 32-bit offset.  Source i+1 is loaded while source i
+  // is accumulated (double buffer), so one memory latency overlaps the next.
+  constexpr int LOB = Ph1::LOB;
+  const uint32_t voff = (uint32_t)tig * 256u + c0 + w;
+  auto load_src = [&](uint32_t (&xv)[E], uint32_t i) {
+    const uint32_t *sp = src + (size_t)i * N;
+#pragma unroll
+    for (int u = 0; u < E; u++) xv[u] = (sp + ((size_t)u << (LOB + 8)))[voff];
+  };
   for (uint32_t i0 = 0; i0 < nsrc; i0 += 16) {
     const uint32_t i1 = min(nsrc, i0 + 16);
     uint64_t acc[TT][E];
@@ -245,17 +256,19 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     for (int e = 0; e < TT; e++)
 #pragma unroll
       for (int u = 0; u < E; u++) acc[e][u] = 0;
+    uint32_t xa[E], xb[E];
+    load_src(xa, i0);
     for (uint32_t i = i0; i < i1; i++) {
-      const uint32_t *s = src + (size_t)i * N + c0 + w;
+      if (i + 1 < i1) load_src(xb, i + 1);
       uint32_t c[TT];
 #pragma unroll
       for (int e = 0; e < TT; e++) c[e] = cbase[(size_t)i * cstride + tcol[e]];
 #pragma unroll
-      for (int u = 0; u < E; u++) {
-        const uint32_t xv = s[(size_t)Ph1::elem(tig, u) * 256];
+      for (int u = 0; u < E; u++)
 #pragma unroll
-        for (int e = 0; e < TT; e++) acc[e][u] = mad64(xv, c[e], acc[e][u]);
-      }
+        for (int e = 0; e < TT; e++) acc[e][u] = mad64(xa[u], c[e], acc[e][u]);
+#pragma unroll
+      for (int u = 0; u < E; u++) xa[u] = xb[u];
     }
 #pragma unroll
     for (int e = 0; e < TT; e++)
@@ -369,74 +382,189 @@ __device__ __forceinline__ void tile_dn(const DevPlan &P, const OcJob &J, uint32
   tile_bconv_col<A, TT>(P, J.zp + (size_t)s * P.num_p * N, P.num_p, P.dn_conv, P.num_q, tg, tcol, tout, ntgt, c0, lds);
 }
 
-// ROW_P / ROW_Q tiles: (tower, row block).
+// ROW_P / ROW_Q tiles: (tower, block of kRB4 = 4 rows).  A row's
+// transforms are independent of each other (one per foreign digit, plus the
+// two ModDown terms for a Q tower), so the 64 threads of a row form 4 slots
+// of 16 threads, each slot running one row transform into its own LDS row;
+// then all 64 threads finish element-wise, 4 consecutive words each: key
+// multiply-accumulate over the digits, REDC, and either (Q) the ModDown
+// subtraction and P^-1, or (P) the inverse row transforms of both
+// accumulators (slots 0 and 1).
+constexpr int kSlots = 4;
+constexpr int kRB4 = kOcThreads / (16 * kSlots);  // rows per tile
+static_assert(kRB4 == kRBQ, "tile shape matches the host tile count");
+constexpr int kRowBufs = kSlots * kRB4;           // LDS rows used per round
+__device__ __forceinline__ uint32_t *row_buf(uint32_t *lds, int b, int r) { return lds + (b * kRB4 + r) * kPad; }
+
+// One round: slot `slot` transforms src (if non-null) into LDS buffer `slot`
+// of row r (phase-2 order at rl(k)).  Every thread executes the barriers.
+__device__ __forceinline__ void row_round_fwd(const uint32_t *src, uint32_t *lrow, int tig, const RowTw &tw,
+                                              uint32_t q) {
+  uint32_t x[16];
+  if (src) {
+#pragma unroll
+    for (int u = 0; u < 16; u++) x[u] = src[tig + 16 * u];
+    ct_regs<4>(x, tw.p1, q);
+#pragma unroll
+    for (int u = 0; u < 16; u++) lrow[rl(tig + 16 * u)] = x[u];
+  }
+  __syncthreads();
+  if (src) {
+#pragma unroll
+    for (int u = 0; u < 16; u++) x[u] = lrow[rl(16 * tig + u)];
+    ct_regs<4>(x, tw.p2, q);
+#pragma unroll
+    for (int u = 0; u < 16; u++) lrow[rl(16 * tig + u)] = x[u];  // same words: no other reader
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void lds4(uint32_t (&v)[4], const uint32_t *lrow, int k0) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) v[i] = lrow[rl(k0 + i)];
+}
+__device__ __forceinline__ void ld4(uint32_t (&v)[4], const uint32_t *p) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+
 template <bool IS_P>
 __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
-  const uint32_t rbk = (1u << P.loga) / kRB, unit = tile / rbk, blk = tile % rbk;
+  const uint32_t rbk = (1u << P.loga) / kRB4, unit = tile / rbk, blk = tile % rbk;
   const uint32_t t = IS_P ? L1 + unit : unit;
   const uint32_t g = oc_gidx(P.num_q, level, t);
   const ModQ m = P.mods[g];
   const uint32_t q = m.q;
-  const int rr = threadIdx.x >> 4, tig = threadIdx.x & 15;
-  const uint32_t row = blk * kRB + rr, M = (1u << P.loga) + row;
+  const int r = threadIdx.x >> 6, slot = (threadIdx.x >> 4) & 3, tig = threadIdx.x & 15;
+  const int k0 = 4 * (threadIdx.x & 63);  // element-wise part: words k0..k0+3 of the row
+  const uint32_t row = blk * kRB4 + r, M = (1u << P.loga) + row;
   const size_t roff = (size_t)row * 256;
-  uint32_t *lr = lds + rr * kPad;
   const uint32_t ndig = cdiv(L1, P.alpha);
+  const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;  // digit holding tower t (bypassed)
   RowTw twf;
   load_row_tw(twf, P.tw_fwd + (size_t)g * N, tig, M);
 
-  // at most 16 digits (checked at plan creation): 16 products < 2^64 need one REDC
-  uint64_t acc0[16], acc1[16];
-#pragma unroll
-  for (int u = 0; u < 16; u++) acc0[u] = acc1[u] = 0;
-  for (uint32_t j = 0; j < ndig; j++) {
-    const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, L1);
-    uint32_t x[16];
-    if (!IS_P && t >= lo && t < hi) {
-      load16(x, J.d + (size_t)t * N + roff + 16 * tig);  // own digit: bypass
-    } else {
-      row_fwd(x, J.ycol + ((size_t)j * T + t) * N + roff, lr, tig, twf, q);
-#pragma unroll
-      for (int u = 0; u < 16; u++) x[u] = canon4(x[u], q);
+  // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the foreign digits
+  const uint32_t njobs = IS_P ? ndig : ndig + 1;
+  auto job_src = [&](uint32_t jb, uint32_t *digit) -> const uint32_t * {
+    if (!IS_P && jb < 2) {
+      *digit = 0xffffffffu;
+      return J.wcol + ((size_t)jb * L1 + t) * N + roff;
     }
-    uint32_t e0[16], e1[16];
-    load16(e0, J.evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + roff + 16 * tig);
-    load16(e1, J.evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + roff + 16 * tig);
+    uint32_t j = IS_P ? jb : jb - 2;
+    if (!IS_P && j >= own) j++;  // skip the own digit
+    *digit = j;
+    return J.ycol + ((size_t)j * T + t) * N + roff;
+  };
+  // at most 16 digits (checked at plan creation): one REDC per sum
+  uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
+  uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0};
+  auto mac = [&](const uint32_t (&y)[4], uint32_t j) {
+    uint32_t e0[4], e1[4];
+    ld4(e0, J.evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + roff + k0);
+    ld4(e1, J.evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + roff + k0);
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-      acc0[u] = mad64(x[u], e0[u], acc0[u]);
-      acc1[u] = mad64(x[u], e1[u], acc1[u]);
+    for (int i = 0; i < 4; i++) {
+      acc0[i] = mad64(y[i], e0[i], acc0[i]);
+      acc1[i] = mad64(y[i], e1[i], acc1[i]);
     }
+  };
+  if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
+    uint32_t y[4];
+    ld4(y, J.d + (size_t)t * N + roff + k0);
+    mac(y, own);
   }
-  uint32_t r0[16], r1[16];
+  for (uint32_t base = 0; base < njobs; base += kSlots) {
+    uint32_t dig = 0;
+    const uint32_t jb = base + slot;
+    const uint32_t *src = jb < njobs ? job_src(jb, &dig) : nullptr;
+    // key words of this round's digits, loaded before the transforms so the
+    // loads overlap them
+    uint32_t ek[kSlots][2][4];
 #pragma unroll
-  for (int u = 0; u < 16; u++) {
-    r0[u] = redc64(acc0[u], m);
-    r1[u] = redc64(acc1[u], m);
+    for (int s2 = 0; s2 < kSlots; s2++) {
+      const uint32_t jb2 = base + s2;
+      uint32_t d2 = 0xffffffffu;
+      if (jb2 < njobs) (void)job_src(jb2, &d2);
+      if (d2 != 0xffffffffu) {
+        ld4(ek[s2][0], J.evk + (((size_t)d2 * 2 + 0) * P.ntot + g) * N + roff + k0);
+        ld4(ek[s2][1], J.evk + (((size_t)d2 * 2 + 1) * P.ntot + g) * N + roff + k0);
+      }
+    }
+    row_round_fwd(src, row_buf(lds, slot, r), tig, twf, q);
+#pragma unroll
+    for (int s2 = 0; s2 < kSlots; s2++) {
+      const uint32_t jb2 = base + s2;
+      if (jb2 >= njobs) break;
+      uint32_t y[4];
+      lds4(y, row_buf(lds, s2, r), k0);
+#pragma unroll
+      for (int i = 0; i < 4; i++) y[i] = canon4(y[i], q);
+      uint32_t d2;
+      (void)job_src(jb2, &d2);
+      if (d2 == 0xffffffffu) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) (jb2 == 0 ? w0 : w1)[i] = y[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          acc0[i] = mad64(y[i], ek[s2][0][i], acc0[i]);
+          acc1[i] = mad64(y[i], ek[s2][1][i], acc1[i]);
+        }
+      }
+    }
+    __syncthreads();  // LDS rows are rewritten by the next round
+  }
+  uint32_t r0[4], r1[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    r0[i] = redc64(acc0[i], m);
+    r1[i] = redc64(acc1[i], m);
   }
   if (IS_P) {
-    const uint32_t k = unit;
+    // ModDown P1 for this special tower: inverse row transforms of both
+    // accumulators by slots 0 and 1 (values canonical, < 2q as required)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      row_buf(lds, 0, r)[rl(k0 + i)] = r0[i];
+      row_buf(lds, 1, r)[rl(k0 + i)] = r1[i];
+    }
+    __syncthreads();
     RowTw twi;
     load_row_tw(twi, P.tw_inv + (size_t)g * N, tig, M);
-    row_inv(r0, J.zp + ((size_t)0 * P.num_p + k) * N + roff, lr, tig, twi, q);
-    row_inv(r1, J.zp + ((size_t)1 * P.num_p + k) * N + roff, lr, tig, twi, q);
+    uint32_t x[16];
+    uint32_t *lrow = row_buf(lds, slot & 1, r);
+    const bool act = slot < 2;
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 16; u++) x[u] = lrow[rl(16 * tig + u)];
+      gs_regs<4>(x, twi.p2, q);
+#pragma unroll
+      for (int u = 0; u < 16; u++) lrow[rl(16 * tig + u)] = x[u];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 16; u++) x[u] = lrow[rl(tig + 16 * u)];
+      gs_regs<4>(x, twi.p1, q);
+      uint32_t *dst = J.zp + ((size_t)slot * P.num_p + unit) * N + roff;
+#pragma unroll
+      for (int u = 0; u < 16; u++) dst[tig + 16 * u] = x[u];
+    }
   } else {
     const uint2 f = P.dn_fin[t];
+    uint32_t o0[4], o1[4];
 #pragma unroll
-    for (int s = 0; s < 2; s++) {
-      uint32_t wv[16];
-      row_fwd(wv, J.wcol + ((size_t)s * L1 + t) * N + roff, lr, tig, twf, q);
-      uint32_t o[16];
-#pragma unroll
-      for (int u = 0; u < 16; u++) {
-        const uint32_t av = s ? r1[u] : r0[u];
-        o[u] = csub(mul_shoup(av + q - canon4(wv[u], q), f.x, f.y, q), q);
-      }
-      store16(J.out + ((size_t)s * L1 + t) * N + roff + 16 * tig, o);
+    for (int i = 0; i < 4; i++) {
+      o0[i] = csub(mul_shoup(r0[i] + q - w0[i], f.x, f.y, q), q);
+      o1[i] = csub(mul_shoup(r1[i] + q - w1[i], f.x, f.y, q), q);
     }
+    *reinterpret_cast<uint4 *>(J.out + ((size_t)0 * L1 + t) * N + roff + k0) = make_uint4(o0[0], o0[1], o0[2], o0[3]);
+    *reinterpret_cast<uint4 *>(J.out + ((size_t)1 * L1 + t) * N + roff + k0) = make_uint4(o1[0], o1[1], o1[2], o1[3]);
   }
+  __syncthreads();
 }
 
 // One tile of one phase.
@@ -459,6 +587,7 @@ template <int A, int TT>
 constexpr int oc_lds_words() {
   return (TT * ColGeom<A>::LDS > kRowLds) ? TT * ColGeom<A>::LDS : kRowLds;
 }
+static_assert(kRowBufs * kPad <= kRowLds, "row tiles fit the LDS of the other tiles");
 
 // One launch per phase: grid x = tiles (max over jobs), grid z = job.
 template <int A, int PHASE, int TT>

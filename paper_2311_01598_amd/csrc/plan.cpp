@@ -158,7 +158,8 @@ ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
     }
     for (uint32_t i = 0; i < n; i++) {
       uint32_t r = bitrev(i, p->log_n);
-      twf[(size_t)g * n + i] = shoup_pair(pw[r], q);
+      // forward entries carry -w mod 2^32 (see bfly_ct)
+      twf[(size_t)g * n + i] = make_uint2(0u - pw[r], shoup_of(pw[r], q));
       twi[(size_t)g * n + i] = shoup_pair(pwi[r], q);
     }
   }

@@ -23,7 +23,7 @@ constexpr uint32_t kRowLog = 8;       // NTT row length 2^8 (second pass)
 
 // Device view of a plan: plain pointers and scalars, passed by value.
 struct DevPlan {
-  const uint2 *tw_fwd;   // [ntot][N] (psi^brv(i), Shoup companion)
+  const uint2 *tw_fwd;   // [ntot][N] (-psi^brv(i) mod 2^32, Shoup companion of psi^brv(i))
   const uint2 *tw_inv;   // [ntot][N] (psi^-brv(i), Shoup companion)
   const ModQ *mods;      // [ntot]
   // ModUp basis conversion, digit j holding s towers (the last digit of a
