@@ -177,6 +177,27 @@ ks_status_t ks_trace_read(ks_plan_t plan, uint32_t max, const char **names, uint
  * doubles.  Allocates and frees 2 GiB of device memory; synchronous. */
 ks_status_t ks_device_rates(double *out, void *stream);
 
+/* Cost model of the autotuner (not part of the key switch): an fp32 MLP
+ * with F inputs, two hidden layers of H units with ReLU, and one linear
+ * output.  Parameters are one device float array of ks_mlp_param_count(F,H)
+ * values laid out W1[F][H], b1[H], W2[H][H], b2[H], W3[H], b3.  X is
+ * [B][F], Y and T are [B].  `act` ([2][B][H]) receives the post-ReLU hidden
+ * activations the backward pass needs; `scratch` is [2][B][H].  All
+ * pointers are device pointers; calls are asynchronous on `stream`;
+ * reductions are deterministic.  F <= 256, H <= 1024. */
+uint32_t ks_mlp_param_count(uint32_t F, uint32_t H);
+ks_status_t ks_mlp_forward(uint32_t F, uint32_t H, uint32_t B, const float *params, const float *X, float *Y,
+                           float *act, void *stream);
+/* dY = 2 (Y - T) / B and *loss = mean((Y - T)^2) (loss is a device float). */
+ks_status_t ks_mlp_mse_grad(uint32_t B, const float *Y, const float *T, float *dY, float *loss, void *stream);
+/* Gradients of the loss with respect to every parameter, given dY and the
+ * activations of the matching forward call; grads has the params layout. */
+ks_status_t ks_mlp_backward(uint32_t F, uint32_t H, uint32_t B, const float *params, const float *X,
+                            const float *act, const float *dY, float *grads, float *scratch, void *stream);
+/* One Adam step (Kingma & Ba) on n parameters; step counts from 1. */
+ks_status_t ks_mlp_adam(uint32_t n, float *params, const float *grads, float *m, float *v, float lr, float beta1,
+                        float beta2, float eps, uint32_t step, void *stream);
+
 const char *ks_status_string(ks_status_t s);
 
 #ifdef __cplusplus

@@ -62,6 +62,13 @@ _SIGS = {
     "ks_trace_read": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_char_p), _U32P,
                                      ctypes.POINTER(ctypes.c_double), _U32P]),
     "ks_device_rates": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _VP]),
+    "ks_mlp_param_count": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32]),
+    "ks_mlp_forward": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
+    "ks_mlp_mse_grad": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
+    "ks_mlp_backward": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP,
+                                       _VP, _VP]),
+    "ks_mlp_adam": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_uint32, _VP]),
     "ks_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
@@ -235,6 +242,29 @@ def ks_device_rates(stream=None):
     out = (ctypes.c_double * 7)()
     _check(_lib.ks_device_rates(out, _stream(stream)), "ks_device_rates")
     return dict(zip(RATE_NAMES, list(out)))
+
+
+def ks_mlp_param_count(F, H):
+    return int(_lib.ks_mlp_param_count(F, H))
+
+
+def ks_mlp_forward(F, H, B, params, X, Y, act, stream=None):
+    _check(_lib.ks_mlp_forward(F, H, B, _ptr(params), _ptr(X), _ptr(Y), _ptr(act), _stream(stream)),
+           "ks_mlp_forward")
+
+
+def ks_mlp_mse_grad(B, Y, T, dY, loss, stream=None):
+    _check(_lib.ks_mlp_mse_grad(B, _ptr(Y), _ptr(T), _ptr(dY), _ptr(loss), _stream(stream)), "ks_mlp_mse_grad")
+
+
+def ks_mlp_backward(F, H, B, params, X, act, dY, grads, scratch, stream=None):
+    _check(_lib.ks_mlp_backward(F, H, B, _ptr(params), _ptr(X), _ptr(act), _ptr(dY), _ptr(grads), _ptr(scratch),
+                                _stream(stream)), "ks_mlp_backward")
+
+
+def ks_mlp_adam(n, params, grads, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check(_lib.ks_mlp_adam(n, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), lr, beta1, beta2, eps, step,
+                            _stream(stream)), "ks_mlp_adam")
 
 
 class Plan:

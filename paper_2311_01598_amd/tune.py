@@ -1,0 +1,214 @@
+"""Autotuner: exhaustive search over launch configurations, a timing
+database, and a tune cache.
+
+A configuration is (schedule, tile_towers, col_width, row_block): the
+execution order of Sec. IV (MP, DC or OC) and its tile shapes.  All
+configurations compute identical bits, so the tuner only measures time.
+Exhaustive search times every configuration (median of `reps` runs after a
+warm-up) and is the fallback and the judge of the cost-model-pruned search
+(costmodel.py), which times only the predicted best few.
+
+Command line (on a GPU machine):
+    python -m paper_2311_01598_amd.tune collect --out timings.jsonl [--quick]
+    python -m paper_2311_01598_amd.tune experiment --db timings.jsonl --out result.json
+"""
+import argparse
+import itertools
+import json
+import os
+import random
+import sys
+import time
+
+import numpy as np
+
+SCHEDULES = ("mp", "dc", "oc")
+
+
+def config_space():
+    """Every configuration the tuner considers (20)."""
+    out = []
+    for cw, rb in itertools.product((8, 16, 32), (4, 8, 16)):
+        out.append({"schedule": "mp", "tile_towers": 1, "col_width": cw, "row_block": rb})
+    for cw, rb in itertools.product((8, 16, 32), (4, 8, 16)):
+        out.append({"schedule": "dc", "tile_towers": 1, "col_width": cw, "row_block": rb})
+    for tt in (1, 2):
+        out.append({"schedule": "oc", "tile_towers": tt, "col_width": 16, "row_block": 8})
+    return out
+
+
+def config_key(c):
+    return f"{c['schedule']}/t{c['tile_towers']}/c{c['col_width']}/r{c['row_block']}"
+
+
+class Workload:
+    """Synthetic inputs for timing one (plan, level, count)."""
+
+    def __init__(self, plan, level, count, seed=0):
+        import torch
+
+        import synth
+        self.plan, self.level, self.count = plan, level, count
+        mods = plan.moduli
+        self.evk = torch.from_numpy(synth.uniform_evk(mods, plan.dnum, plan.n, seed).view(np.int32)).cuda()
+        self.ins = [torch.from_numpy(synth.uniform_limbs(mods[:level + 1], plan.n, seed + 1 + i).view(np.int32)).cuda()
+                    for i in range(count)]
+        self.outs = [torch.empty((2, level + 1, plan.n), dtype=torch.int32, device="cuda") for _ in range(count)]
+
+    def run(self, ws):
+        if self.count == 1:
+            self.plan.keyswitch(self.evk, self.level, self.ins[0], out=self.outs[0], workspace=ws)
+        else:
+            self.plan.keyswitch_batch([(self.evk, self.level, x, o) for x, o in zip(self.ins, self.outs)],
+                                      workspace=ws)
+
+
+def time_config(work, cfg, reps=5):
+    """Median milliseconds per key switch of `work` under configuration `cfg`."""
+    import torch
+    plan = work.plan
+    plan.configure(cfg["schedule"], tile_towers=cfg["tile_towers"], col_width=cfg["col_width"],
+                   row_block=cfg["row_block"])
+    ws = plan.workspace([work.level] * work.count)
+    work.run(ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        work.run(ws)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / work.count)
+    del ws
+    return float(np.median(ts))
+
+
+def exhaustive(work, reps=5, configs=None):
+    """Time every configuration; returns (best config, {key: ms})."""
+    configs = configs or config_space()
+    times = {config_key(c): time_config(work, c, reps) for c in configs}
+    best = min(configs, key=lambda c: times[config_key(c)])
+    return best, times
+
+
+def record(params, level, count, cfg, ms):
+    log_n, num_q, dnum, num_p = params
+    return {"log_n": log_n, "num_q": num_q, "dnum": dnum, "num_p": num_p, "level": level, "count": count,
+            **cfg, "ms": ms}
+
+
+class TuneCache:
+    """Best configuration per (device, parameters, level, count), as JSON."""
+
+    def __init__(self, path):
+        self.path = path
+        self.data = json.load(open(path)) if path and os.path.exists(path) else {}
+
+    @staticmethod
+    def key(device, params, level, count):
+        return f"{device}|{'/'.join(map(str, params))}|l{level}|c{count}"
+
+    def get(self, device, params, level, count):
+        return self.data.get(self.key(device, params, level, count))
+
+    def put(self, device, params, level, count, cfg):
+        self.data[self.key(device, params, level, count)] = cfg
+        if self.path:
+            tmp = self.path + ".tmp"
+            json.dump(self.data, open(tmp, "w"), indent=1)
+            os.replace(tmp, self.path)
+
+
+def tune(plan, level, count=1, cache=None, device="gpu0", reps=5):
+    """Configure `plan` for (level, count): the cached choice, else exhaustive."""
+    params = (plan.log_n, plan.num_q, plan.dnum, plan.num_p)
+    cfg = cache.get(device, params, level, count) if cache else None
+    if cfg is None:
+        cfg, _ = exhaustive(Workload(plan, level, count), reps)
+        if cache:
+            cache.put(device, params, level, count, cfg)
+    plan.configure(cfg["schedule"], tile_towers=cfg["tile_towers"], col_width=cfg["col_width"],
+                   row_block=cfg["row_block"])
+    return cfg
+
+
+# ------------------------------------------------------------------ collection
+def collect_grid(quick=False):
+    """(log_n, num_q, dnum, levels, counts) points of the timing database:
+    N in 2^14..2^17, up to 48 towers, dnum 1..6 (alpha <= 32)."""
+    pts = []
+    logs = (14, 15) if quick else (14, 15, 16, 17)
+    towers = (8, 16) if quick else (8, 16, 24, 32, 40, 48)
+    dnums = (1, 2, 3) if quick else (1, 2, 3, 4, 6)
+    for log_n, nq, dn in itertools.product(logs, towers, dnums):
+        alpha = -(-nq // dn)
+        if alpha > 32 or dn > nq:
+            continue
+        levels = sorted({nq - 1, max(0, nq // 2 - 1)})
+        counts = (1,) if quick else (1, 4)
+        pts.append((log_n, nq, dn, levels, counts))
+    return pts
+
+
+def collect(out, quick=False, reps=5, log=print):
+    import paper_2311_01598_amd as ks
+    t0 = time.time()
+    pts = collect_grid(quick)
+    n = 0
+    with open(out, "a") as f:
+        for pi, (log_n, nq, dn, levels, counts) in enumerate(pts):
+            plan = ks.Plan(log_n, nq, dn)
+            params = (log_n, nq, dn, plan.num_p)
+            for level in levels:
+                for count in counts:
+                    work = Workload(plan, level, count, seed=1000 * pi + level)
+                    for cfg in config_space():
+                        ms = time_config(work, cfg, reps)
+                        f.write(json.dumps(record(params, level, count, cfg, ms)) + "\n")
+                        n += 1
+                    del work
+            f.flush()
+            plan.close()
+            log(f"[collect] {pi + 1}/{len(pts)} N=2^{log_n} towers={nq} dnum={dn}: {n} timings, "
+                f"{time.time() - t0:.0f} s", flush=True)
+    return n
+
+
+def load_db(path):
+    return [json.loads(l) for l in open(path) if l.strip()]
+
+
+def group_workloads(rows):
+    """{(log_n, num_q, dnum, num_p, level, count): {config key: ms}}."""
+    out = {}
+    for r in rows:
+        k = (r["log_n"], r["num_q"], r["dnum"], r["num_p"], r["level"], r["count"])
+        out.setdefault(k, {})[config_key(r)] = r["ms"]
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--out", required=True)
+    c.add_argument("--quick", action="store_true")
+    c.add_argument("--reps", type=int, default=5)
+    e = sub.add_parser("experiment")
+    e.add_argument("--db", required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--top", type=int, default=3)
+    e.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    if a.cmd == "collect":
+        collect(a.out, a.quick, a.reps)
+    else:
+        from . import costmodel
+        res = costmodel.experiment(load_db(a.db), top_m=a.top, seed=a.seed)
+        json.dump(res, open(a.out, "w"), indent=1)
+        print(json.dumps(res["summary"]), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
