@@ -125,6 +125,63 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
     return res
 
 
+def serving_rate(ks, count, np, torch, synth, seed=5):
+    """Serving workload: Poisson arrivals of key-switch requests, each for the
+    relinearisation key or one of 16 rotation keys (17 keys resident per ring
+    degree), N in {2^16, 2^17}, l+1 ~ U[8, 48], dnum=3.  Reports saturation
+    throughput (all requests queued at once), p50/p99 latency at 60 % of that
+    rate, and the same requests switched one at a time with MP."""
+    from paper_2311_01598_amd.serve import Request, Server, poisson_arrivals
+    plans, keys, pool = {}, {}, {}
+    for log_n in (16, 17):
+        p = ks.Plan(log_n, 48, 3)
+        plans[log_n] = p
+        base = torch.from_numpy(synth.uniform_evk(p.moduli, 3, p.n, synth.seed_for(4, log_n)).view(np.int32)).cuda()
+        keys[log_n] = [base] + [base.clone() for _ in range(16)]
+        pool[log_n] = [torch.from_numpy(synth.uniform_limbs(p.moduli[:48], p.n, synth.seed_for(4, 100 * log_n + i))
+                                        .view(np.int32)).cuda() for i in range(4)]
+    rng = np.random.default_rng(synth.seed_for(4, seed))
+
+    def requests():
+        out = []
+        for i in range(count):
+            log_n = int(rng.choice((16, 17)))
+            level = int(rng.integers(7, 48))
+            d = pool[log_n][i % 4][:level + 1]
+            out.append(Request(i, int(rng.integers(0, 17)), log_n, level, d, 0.0))
+        return out
+    budget = 8 << 30
+    res = {"requests": count, "keys_per_degree": 17, "budget_gib": budget >> 30, "streams": 2, "max_batch": 16}
+    sat = Server(plans, keys, budget, streams=2, max_batch=16)
+    reqs = requests()
+    sat.run([(0.0, r) for r in reqs[:64]])  # warm-up
+    sat = Server(plans, keys, budget, streams=2, max_batch=16)
+    st = sat.run([(0.0, r) for r in reqs])
+    res["saturation"] = {"ks_per_s": round(st["ks_per_s"], 1), "batches": st["batches"]}
+    rate = 0.6 * st["ks_per_s"]
+    srv = Server(plans, keys, budget, streams=2, max_batch=16)
+    reqs = requests()
+    st = srv.run(list(zip(poisson_arrivals(rate, count, synth.seed_for(4, seed + 1)), reqs)))
+    res["poisson"] = {"offered_per_s": round(rate, 1), "ks_per_s": round(st["ks_per_s"], 1),
+                      "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "batches": st["batches"],
+                      "high_water_gib": round(st["high_water_bytes"] / 2**30, 3)}
+    # the same request mix, one key switch per call with MP on one stream
+    for p in plans.values():
+        p.configure("mp")
+    ws = {k: p.workspace([47]) for k, p in plans.items()}
+    outs = {k: torch.empty(2 * 48 * p.n, dtype=torch.int32, device="cuda") for k, p in plans.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        plans[r.log_n].keyswitch(keys[r.log_n][r.key], r.level, r.d, out=outs[r.log_n][:2 * (r.level + 1) * plans[r.log_n].n],
+                                 workspace=ws[r.log_n])
+    torch.cuda.synchronize()
+    res["mp_one_at_a_time_ks_per_s"] = round(count / (time.perf_counter() - t0), 1)
+    for p in plans.values():
+        p.close()
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +199,8 @@ def parse():
                     help="ciphertexts per call in the batched measurement of the same workload (0 = skip)")
     ap.add_argument("--mixed", action="store_true",
                     help="also time 64-ciphertext batches at levels l+1 ~ U[8,24] for dnum 2, 3, 4")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests in the serving measurement (0 = skip)")
     return ap.parse_args()
 
 
@@ -255,6 +314,8 @@ def main():
         res["mixed_batches"] = {}
         for dn in (2, 3, 4):
             res["mixed_batches"][f"dnum{dn}"] = mixed_rate(ks, dn, max(3, args.steps // 40), np, torch, synth)
+    if args.serve_requests:
+        res["serving"] = serving_rate(ks, args.serve_requests, np, torch, synth)
     if args.rates:
         res["device_rates"] = {k: round(v / 1e12, 4) for k, v in ks.ks_device_rates().items()}
     if args.compare:

@@ -141,7 +141,10 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
  * launch per phase over all jobs, or one persistent work-queue launch, and
  * the launches are captured once per (count, workspace, configuration) in a
  * hipGraph that is replayed afterwards.  The job table travels in the
- * workspace, so concurrent batches need distinct workspaces. */
+ * workspace, so concurrent batches need distinct workspaces.  For tests of
+ * failure handling, the environment variable KS_FAULT_INJECT=<n> makes the
+ * n-th call after the variable took its current value return KS_ERR_DEVICE
+ * without enqueuing work. */
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs,
                                void *workspace, size_t workspace_bytes, void *stream);
 

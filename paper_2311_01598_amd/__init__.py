@@ -304,10 +304,10 @@ class Plan:
         ks_keyswitch(self.handle, evk, level, d, out, workspace, stream=stream)
         return out
 
-    def keyswitch_batch(self, jobs, workspace=None, stream=None):
+    def keyswitch_batch(self, jobs, workspace=None, stream=None, workspace_bytes=None):
         if workspace is None:
             workspace = self.workspace([j[1] for j in jobs])
-        ks_keyswitch_batch(self.handle, jobs, workspace, stream=stream)
+        ks_keyswitch_batch(self.handle, jobs, workspace, workspace_bytes, stream=stream)
 
     def ntt(self, data, g, inverse=False, stream=None):
         ks_ntt(self.handle, list(g), inverse, data, stream=stream)

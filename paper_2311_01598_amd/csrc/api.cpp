@@ -1,8 +1,11 @@
 // api.cpp -- the C ABI (include/ks.h): validation, workspace layout and the
 // three execution orders of Sec. IV as launch sequences.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "kernels.h"
 
@@ -447,9 +450,28 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, co
   return run_one(pl, sch, evk, level, in, out, (uint32_t *)workspace, (hipStream_t)stream);
 }
 
+// Failure-handling tests: KS_FAULT_INJECT=<n> makes the n-th call (1-based)
+// of ks_keyswitch_batch after the variable took its current value report
+// KS_ERR_DEVICE without enqueuing anything.
+static bool injected_fault() {
+  static std::mutex mu;
+  static std::string seen;
+  static uint64_t calls = 0;
+  const char *e = std::getenv("KS_FAULT_INJECT");
+  const std::string now = e ? e : "";
+  std::lock_guard<std::mutex> g(mu);
+  if (now != seen) {
+    seen = now;
+    calls = 0;
+  }
+  if (now.empty()) return false;
+  return ++calls == std::strtoull(now.c_str(), nullptr, 10);
+}
+
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
                                size_t workspace_bytes, void *stream) {
   if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
+  if (injected_fault()) return KS_ERR_DEVICE;
   Plan &pl = plan->p;
   const ks_schedule_t sch = effective(pl);
   if (!count) return KS_OK;
