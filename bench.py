@@ -48,9 +48,8 @@ def stage_muls(log_n, l1, k, alpha):
     return {
         "oc.intt_row": l1 * row_ntt,
         "oc.intt_col.up": l1 * (col_ntt + 3 * n),
-        "oc.bconv_col.up_p": up_p,
+        "oc.bconv_col.up": up_p + up_q,
         "oc.row.p": k * (ndig * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt),
-        "oc.bconv_col.up_q": up_q,
         "oc.intt_col.down": 2 * k * (col_ntt + 3 * n),
         "oc.bconv_col.down": 2 * l1 * (n * (k + 4) + col_ntt),
         "oc.row.q": l1 * ((ndig - 1) * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt + 2 * 3 * n),

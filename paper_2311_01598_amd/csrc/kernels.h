@@ -52,6 +52,10 @@ hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *
 enum OcPhase : uint32_t {
   OC_INTT_ROW = 0, OC_INTT_COL, OC_UP_P, OC_ROW_P, OC_UP_Q, OC_INTT_COL_DN, OC_DN, OC_ROW_Q, OC_NPHASE
 };
+// Launch-only phase: the UP_P and UP_Q tiles of a job in one grid (UP_P
+// first).  Both depend only on INTT_COL, so one launch fills the device with
+// both instead of running them one after the other.
+constexpr uint32_t OC_UP_PQ = OC_NPHASE;
 
 // One key switch as the OC kernels see it (device-visible, by value or in a
 // job table).  Workspace regions: xt [l+1][N] ModUp P1 output, ycol

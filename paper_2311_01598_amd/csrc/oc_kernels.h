@@ -594,13 +594,19 @@ template <int A, int PHASE, int TT>
 __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, const OcJob *jobs) {
   __shared__ uint32_t lds[oc_lds_words<A, TT>()];
   const OcJob J = jobs ? jobs[blockIdx.z] : one;
-  if (blockIdx.x >= J.tiles[PHASE]) return;
-  oc_tile<A, TT, TT>(P, J, PHASE, blockIdx.x, lds);
+  if constexpr (PHASE == OC_UP_PQ) {
+    const uint32_t np = J.tiles[OC_UP_P];
+    if (blockIdx.x < np) tile_up<A, TT>(P, J, blockIdx.x, true, J.ttu, lds);
+    else if (blockIdx.x - np < J.tiles[OC_UP_Q]) tile_up<A, TT>(P, J, blockIdx.x - np, false, J.ttu, lds);
+  } else {
+    if (blockIdx.x >= J.tiles[PHASE]) return;
+    oc_tile<A, TT, TT>(P, J, PHASE, blockIdx.x, lds);
+  }
 }
 
-static const char *const kOcPhaseName[OC_NPHASE] = {"oc.intt_row", "oc.intt_col.up", "oc.bconv_col.up_p",
-                                                   "oc.row.p", "oc.bconv_col.up_q", "oc.intt_col.down",
-                                                   "oc.bconv_col.down", "oc.row.q"};
+static const char *const kOcPhaseName[OC_NPHASE + 1] = {
+    "oc.intt_row", "oc.intt_col.up", "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
+    "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q", "oc.bconv_col.up"};
 
 template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
@@ -615,9 +621,9 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
                              const uint32_t *max_tiles, hipStream_t st) {
   launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
   launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
-  launch_phase<A, OC_UP_P, TT>(pl, one, jobs, count, max_tiles[OC_UP_P], st);
+  // a job's merged grid needs at most its own UP_P + UP_Q tiles
+  launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
   launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
-  launch_phase<A, OC_UP_Q, TT>(pl, one, jobs, count, max_tiles[OC_UP_Q], st);
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
   launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
