@@ -18,12 +18,50 @@
 
 namespace ks {
 
+// Global-memory views of generic pointers.  Buffers reached through a job
+// table or a plan struct are generic (flat) pointers to the compiler; a flat
+// access counts against both the memory and the LDS wait counters, so an LDS
+// wait would also wait for every outstanding HBM load.  Every HBM access of
+// the kernels goes through one of these casts instead.
+#define KS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const KS_GLOBAL T *gp(const T *p) {
+  return (const KS_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ KS_GLOBAL T *gp(T *p) {
+  return (KS_GLOBAL T *)p;
+}
+// Vector loads and stores through native vector types (HIP's uint2 / uint4
+// classes cannot be copied out of another address space).
+typedef uint32_t ks_v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t ks_v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint2 ldg2(const uint2 *p) {
+  const ks_v2u v = *(const KS_GLOBAL ks_v2u *)p;
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ldg4(const void *p) {
+  const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg4(void *p, uint4 v) {
+  ks_v4u t;
+  t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+  *(KS_GLOBAL ks_v4u *)p = t;
+}
+
 struct ModQ {
   uint32_t q;        // modulus
   uint32_t qinv;     // -q^-1 mod 2^32
   uint32_t mu;       // floor(2^32 / q)
   uint32_t pad;
 };
+__device__ __forceinline__ ModQ ldmod(const ModQ *p) {
+  const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;
+  ModQ m;
+  m.q = v.x; m.qinv = v.y; m.mu = v.z; m.pad = v.w;
+  return m;
+}
 
 __device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) {
   uint32_t d = a - m;

@@ -43,7 +43,7 @@ __device__ __forceinline__ void ct_group(uint32_t (&x)[1 << R], int g, uint32_t 
 #pragma unroll
     for (int u = 0; u < (1 << R); u++) {
       if (u & half) continue;
-      const uint2 w = tw[node + (uint32_t)(u >> (R - t))];
+      const uint2 w = ldg2(tw + node + (uint32_t)(u >> (R - t)));
       bfly_ct(x[u], x[u + half], w.x, w.y, q);
     }
   }
@@ -61,7 +61,7 @@ __device__ __forceinline__ void gs_group(uint32_t (&x)[1 << R], int g, uint32_t 
 #pragma unroll
     for (int u = 0; u < (1 << R); u++) {
       if (u & half) continue;
-      const uint2 w = tw[node + (uint32_t)(u >> (R - t))];
+      const uint2 w = ldg2(tw + node + (uint32_t)(u >> (R - t)));
       bfly_gs(x[u], x[u + half], w.x, w.y, q);
     }
   }

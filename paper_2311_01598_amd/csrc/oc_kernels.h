@@ -63,7 +63,7 @@ __device__ __forceinline__ void load_group_tw(GroupTw<R> &gt, const uint2 *__res
   for (int t = 0; t < R; t++) {
     const uint32_t node = (M << (S0 + t - 1)) + (hi << t);
 #pragma unroll
-    for (int k = 0; k < (1 << t); k++) gt.w[(1 << t) - 1 + k] = tw[node + k];
+    for (int k = 0; k < (1 << t); k++) gt.w[(1 << t) - 1 + k] = ldg2(tw + node + k);
   }
 }
 template <int R>
@@ -104,17 +104,15 @@ __device__ __forceinline__ void load_row_tw(RowTw &r, const uint2 *__restrict__ 
 }
 
 __device__ __forceinline__ void load16(uint32_t (&x)[16], const uint32_t *p) {
-  const uint4 *v = reinterpret_cast<const uint4 *>(p);
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    const uint4 t = v[i];
+    const uint4 t = ldg4(p + 4 * i);
     x[4 * i] = t.x; x[4 * i + 1] = t.y; x[4 * i + 2] = t.z; x[4 * i + 3] = t.w;
   }
 }
 __device__ __forceinline__ void store16(uint32_t *p, const uint32_t (&x)[16]) {
-  uint4 *v = reinterpret_cast<uint4 *>(p);
 #pragma unroll
-  for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+  for (int i = 0; i < 4; i++) stg4(p + 4 * i, make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]));
 }
 
 // Forward transform of a row read from global in phase-1 layout; result in
@@ -122,7 +120,7 @@ __device__ __forceinline__ void store16(uint32_t *p, const uint32_t (&x)[16]) {
 __device__ __forceinline__ void row_fwd(uint32_t (&x)[16], const uint32_t *row, uint32_t *lr, int tig,
                                         const RowTw &tw, uint32_t q) {
 #pragma unroll
-  for (int u = 0; u < 16; u++) x[u] = row[tig + 16 * u];
+  for (int u = 0; u < 16; u++) x[u] = gp(row)[tig + 16 * u];
   ct_regs<4>(x, tw.p1, q);
 #pragma unroll
   for (int u = 0; u < 16; u++) lr[rl(tig + 16 * u)] = x[u];
@@ -145,7 +143,7 @@ __device__ __forceinline__ void row_inv(uint32_t (&x)[16], uint32_t *row, uint32
   for (int u = 0; u < 16; u++) x[u] = lr[rl(tig + 16 * u)];
   gs_regs<4>(x, tw.p1, q);
 #pragma unroll
-  for (int u = 0; u < 16; u++) row[tig + 16 * u] = x[u];
+  for (int u = 0; u < 16; u++) gp(row)[tig + 16 * u] = x[u];
   __syncthreads();
 }
 
@@ -161,7 +159,7 @@ __device__ __forceinline__ void tile_intt_row(const DevPlan &P, const OcJob &J, 
   load_row_tw(tw, P.tw_inv + (size_t)i * N, tig, M);
   uint32_t x[16];
   load16(x, J.d + roff + 16 * tig);
-  row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, P.mods[i].q);
+  row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, ldmod(P.mods + i).q);
 }
 
 // INTT_COL / INTT_COL_DN: inverse column pass of one limb, then
@@ -179,15 +177,15 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   if (!down) {
     const uint32_t j = li / P.alpha, lo = j * P.alpha, s = min(lo + P.alpha, J.level + 1) - lo;
     g = li;
-    pre = P.up_pre[((size_t)j * P.alpha + (s - 1)) * P.alpha + (li - lo)];
+    pre = ldg2(P.up_pre + ((size_t)j * P.alpha + (s - 1)) * P.alpha + (li - lo));
     col = J.xt + (size_t)li * N + c0;
   } else {
     const uint32_t k = li % P.num_p;
     g = P.num_q + k;
-    pre = P.dn_pre[k];
+    pre = ldg2(P.dn_pre + k);
     col = J.zp + (size_t)li * N + c0;
   }
-  const uint32_t q = P.mods[g].q;
+  const uint32_t q = ldmod(P.mods + g).q;
   const uint2 *tw = P.tw_inv + (size_t)g * N;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
   if constexpr (R2 > 0) {
@@ -197,7 +195,7 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
       const int gg = tig + gi * TPS;
       uint32_t x[1 << R2];
 #pragma unroll
-      for (int u = 0; u < (1 << R2); u++) x[u] = col[(size_t)Ph::elem(gg, u) * rowlen + w];
+      for (int u = 0; u < (1 << R2); u++) x[u] = gp(col)[(size_t)Ph::elem(gg, u) * rowlen + w];
       gs_group<A, 1 + R1, R2>(x, gg, 1u, tw, q);
 #pragma unroll
       for (int u = 0; u < (1 << R2); u++) lds[Ph::elem(gg, u) * W + w] = x[u];
@@ -208,11 +206,11 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   uint32_t x[1 << R1];
 #pragma unroll
   for (int u = 0; u < (1 << R1); u++)
-    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : col[(size_t)Ph::elem(tig, u) * rowlen + w];
+    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : gp(col)[(size_t)Ph::elem(tig, u) * rowlen + w];
   gs_group<A, 1, R1>(x, tig, 1u, tw, q);
 #pragma unroll
   for (int u = 0; u < (1 << R1); u++)
-    col[(size_t)Ph::elem(tig, u) * rowlen + w] = csub(mul_shoup(x[u], pre.x, pre.y, q), q);
+    gp(col)[(size_t)Ph::elem(tig, u) * rowlen + w] = csub(mul_shoup(x[u], pre.x, pre.y, q), q);
   __syncthreads();
 }
 
@@ -232,7 +230,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   using Ph1 = Phase<A, 1, R1>;
   ModQ mq[TT];
 #pragma unroll
-  for (int e = 0; e < TT; e++) mq[e] = P.mods[tg[e]];
+  for (int e = 0; e < TT; e++) mq[e] = ldmod(P.mods + tg[e]);
   uint32_t y[TT][E];
 #pragma unroll
   for (int e = 0; e < TT; e++)
@@ -247,7 +245,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   auto load_src = [&](uint32_t (&xv)[E], uint32_t i) {
     const uint32_t *sp = src + (size_t)i * N;
 #pragma unroll
-    for (int u = 0; u < E; u++) xv[u] = (sp + ((size_t)u << (LOB + 8)))[voff];
+    for (int u = 0; u < E; u++) xv[u] = gp(sp + ((size_t)u << (LOB + 8)))[voff];
   };
   for (uint32_t i0 = 0; i0 < nsrc; i0 += 16) {
     const uint32_t i1 = min(nsrc, i0 + 16);
@@ -262,7 +260,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
       if (i + 1 < i1) load_src(xb, i + 1);
       uint32_t c[TT];
 #pragma unroll
-      for (int e = 0; e < TT; e++) c[e] = cbase[(size_t)i * cstride + tcol[e]];
+      for (int e = 0; e < TT; e++) c[e] = gp(cbase)[(size_t)i * cstride + tcol[e]];
 #pragma unroll
       for (int u = 0; u < E; u++)
 #pragma unroll
@@ -285,7 +283,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
         for (int u = 0; u < E; u++) lds[e * G::LDS + Ph1::elem(tig, u) * W + w] = y[e][u];
       } else {
 #pragma unroll
-        for (int u = 0; u < E; u++) tout[e][(size_t)Ph1::elem(tig, u) * 256 + c0 + w] = y[e][u];
+        for (int u = 0; u < E; u++) gp(tout[e])[(size_t)Ph1::elem(tig, u) * 256 + c0 + w] = y[e][u];
       }
     }
   }
@@ -304,7 +302,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
           for (int u = 0; u < (1 << R2); u++) x[u] = lds[e * G::LDS + Ph2::elem(gg, u) * W + w];
           ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
 #pragma unroll
-          for (int u = 0; u < (1 << R2); u++) tout[e][(size_t)Ph2::elem(gg, u) * 256 + c0 + w] = x[u];
+          for (int u = 0; u < (1 << R2); u++) gp(tout[e])[(size_t)Ph2::elem(gg, u) * 256 + c0 + w] = x[u];
         }
       }
     }
@@ -403,7 +401,7 @@ __device__ __forceinline__ void row_round_fwd(const uint32_t *src, uint32_t *lro
   uint32_t x[16];
   if (src) {
 #pragma unroll
-    for (int u = 0; u < 16; u++) x[u] = src[tig + 16 * u];
+    for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
     ct_regs<4>(x, tw.p1, q);
 #pragma unroll
     for (int u = 0; u < 16; u++) lrow[rl(tig + 16 * u)] = x[u];
@@ -424,7 +422,7 @@ __device__ __forceinline__ void lds4(uint32_t (&v)[4], const uint32_t *lrow, int
   for (int i = 0; i < 4; i++) v[i] = lrow[rl(k0 + i)];
 }
 __device__ __forceinline__ void ld4(uint32_t (&v)[4], const uint32_t *p) {
-  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  const uint4 t = ldg4(p);
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
@@ -435,7 +433,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const uint32_t rbk = (1u << P.loga) / kRB4, unit = tile / rbk, blk = tile % rbk;
   const uint32_t t = IS_P ? L1 + unit : unit;
   const uint32_t g = oc_gidx(P.num_q, level, t);
-  const ModQ m = P.mods[g];
+  const ModQ m = ldmod(P.mods + g);
   const uint32_t q = m.q;
   const int r = threadIdx.x >> 6, slot = (threadIdx.x >> 4) & 3, tig = threadIdx.x & 15;
   const int k0 = 4 * (threadIdx.x & 63);  // element-wise part: words k0..k0+3 of the row
@@ -551,18 +549,18 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       gs_regs<4>(x, twi.p1, q);
       uint32_t *dst = J.zp + ((size_t)slot * P.num_p + unit) * N + roff;
 #pragma unroll
-      for (int u = 0; u < 16; u++) dst[tig + 16 * u] = x[u];
+      for (int u = 0; u < 16; u++) gp(dst)[tig + 16 * u] = x[u];
     }
   } else {
-    const uint2 f = P.dn_fin[t];
+    const uint2 f = ldg2(P.dn_fin + t);
     uint32_t o0[4], o1[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       o0[i] = csub(mul_shoup(r0[i] + q - w0[i], f.x, f.y, q), q);
       o1[i] = csub(mul_shoup(r1[i] + q - w1[i], f.x, f.y, q), q);
     }
-    *reinterpret_cast<uint4 *>(J.out + ((size_t)0 * L1 + t) * N + roff + k0) = make_uint4(o0[0], o0[1], o0[2], o0[3]);
-    *reinterpret_cast<uint4 *>(J.out + ((size_t)1 * L1 + t) * N + roff + k0) = make_uint4(o1[0], o1[1], o1[2], o1[3]);
+    stg4(J.out + ((size_t)0 * L1 + t) * N + roff + k0, make_uint4(o0[0], o0[1], o0[2], o0[3]));
+    stg4(J.out + ((size_t)1 * L1 + t) * N + roff + k0, make_uint4(o1[0], o1[1], o1[2], o1[3]));
   }
   __syncthreads();
 }
@@ -593,7 +591,17 @@ static_assert(kRowBufs * kPad <= kRowLds, "row tiles fit the LDS of the other ti
 template <int A, int PHASE, int TT>
 __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, const OcJob *jobs) {
   __shared__ uint32_t lds[oc_lds_words<A, TT>()];
-  const OcJob J = jobs ? jobs[blockIdx.z] : one;
+  // the job table is read-only while the kernel runs: scalar loads keep
+  // every job field (pointers, level, tile counts) uniform in SGPRs
+  OcJob J = one;
+  if (jobs) {
+    static_assert(sizeof(OcJob) % 4 == 0, "job entries are whole words");
+    const __attribute__((address_space(4))) uint32_t *src =
+        (const __attribute__((address_space(4))) uint32_t *)(jobs + blockIdx.z);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&J);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(OcJob) / 4); i++) dst[i] = src[i];
+  }
   if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     if (blockIdx.x < np) tile_up<A, TT>(P, J, blockIdx.x, true, J.ttu, lds);

@@ -180,6 +180,35 @@ def test_batch_equals_single(ks):
     plan.close()
 
 
+def test_repeated_runs_are_bit_identical(ks):
+    """Every schedule and OC tile width 10 times, single and batched, on a
+    workload of several tiles per phase: exact arithmetic turns any race
+    (a missing barrier, an overlapping write) into a bit difference."""
+    p = oracle.Params(14, 12, 3, 4)
+    mods = oracle.moduli(p)
+    plan = ks.Plan(14, 12, 3, 4)
+    evk_d = dev(synth.uniform_evk(mods, 3, p.n, seed=21))
+    levels = [11, 6, 0, 9]
+    ins = [dev(synth.uniform_limbs(mods[:l + 1], p.n, seed=22 + i)) for i, l in enumerate(levels)]
+    first = None
+    for sched, tile in (("mp", 1), ("dc", 1), ("oc", 1), ("oc", 2)):
+        say(f"[repeat] sched={sched} tile={tile}")
+        plan.configure(sched, tile_towers=tile)
+        for rep in range(10):
+            outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in levels]
+            if rep % 2:
+                plan.keyswitch_batch([(evk_d, l, x, o) for l, x, o in zip(levels, ins, outs)])
+            else:
+                for l, x, o in zip(levels, ins, outs):
+                    plan.keyswitch(evk_d, l, x, out=o)
+            got = [host(o) for o in outs]
+            if first is None:
+                first = got
+            for a, b in zip(got, first):
+                assert np.array_equal(a, b), (sched, tile, rep)
+    plan.close()
+
+
 @pytest.fixture(scope="module")
 def small_batch():
     p = oracle.Params(13, 8, 3, 3)
