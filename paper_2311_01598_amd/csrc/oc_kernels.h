@@ -394,23 +394,75 @@ static_assert(kRB4 == kRBQ, "tile shape matches the host tile count");
 constexpr int kRowBufs = kSlots * kRB4;           // LDS rows used per round
 __device__ __forceinline__ uint32_t *row_buf(uint32_t *lds, int b, int r) { return lds + (b * kRB4 + r) * kPad; }
 
-// One round: slot `slot` transforms src (if non-null) into LDS buffer `slot`
-// of row r (phase-2 order at rl(k)).  Every thread executes the barriers.
-__device__ __forceinline__ void row_round_fwd(const uint32_t *src, uint32_t *lrow, int tig, const RowTw &tw,
-                                              uint32_t q) {
-  uint32_t x[16];
-  if (src) {
+// The row tiles keep the twiddles of their 4 rows in LDS, in heap order: a
+// row's entry i in [1, 256) is stage s = floor(log2 i) + 1, index
+// i - 2^(s-1) of that stage, i.e. table entry ((M - 1) << (s - 1)) + i of the
+// row's node M.  One cooperative, coalesced fill per tile replaces 30
+// register-resident twiddle pairs per thread.
+constexpr int kRowTw = 256;                          // uint2 entries per row
+constexpr int kRowTileLds = kRowBufs * kPad + 2 * kRB4 * kRowTw;
+__device__ __forceinline__ uint2 *row_tw(uint32_t *lds) { return reinterpret_cast<uint2 *>(lds + kRowBufs * kPad); }
+
+// Issue the twiddle loads of the tile's rows (node of row 0: m0); the LDS
+// stores are separate so that other loads can be issued in between.
+__device__ __forceinline__ void row_tw_issue(uint2 (&t)[kRB4 * kRowTw / kOcThreads], const uint2 *tw, uint32_t m0) {
 #pragma unroll
-    for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
-    ct_regs<4>(x, tw.p1, q);
+  for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) {
+    const int e = (int)threadIdx.x + k * kOcThreads, r = e >> 8, i = e & 255;
+    const int lvl = 31 - __clz(i | 1);
+    t[k] = ldg2(tw + ((size_t)(m0 + r - 1) << lvl) + (i | (i == 0)));  // entry 0 unused: read entry 1
+  }
+}
+__device__ __forceinline__ void row_tw_store(uint2 *twl, const uint2 (&t)[kRB4 * kRowTw / kOcThreads]) {
+#pragma unroll
+  for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) twl[threadIdx.x + k * kOcThreads] = t[k];
+}
+
+// Four forward / inverse stages on 16 registers with twiddles from a row's
+// heap (stage base S0 = 1 for row stages 1-4 with hi = 0, S0 = 5 for stages
+// 5-8 with hi = the thread's index in the row).
+template <int S0>
+__device__ __forceinline__ void ct_lds(uint32_t (&x)[16], const uint2 *twr, int hi, uint32_t q) {
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const int half = 1 << (3 - t);
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+      if (u & half) continue;
+      const uint2 w = twr[(1 << (S0 - 1 + t)) + (hi << t) + (u >> (4 - t))];
+      bfly_ct(x[u], x[u + half], w.x, w.y, q);
+    }
+  }
+}
+template <int S0>
+__device__ __forceinline__ void gs_lds(uint32_t (&x)[16], const uint2 *twr, int hi, uint32_t q) {
+#pragma unroll
+  for (int t = 3; t >= 0; t--) {
+    const int half = 1 << (3 - t);
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+      if (u & half) continue;
+      const uint2 w = twr[(1 << (S0 - 1 + t)) + (hi << t) + (u >> (4 - t))];
+      bfly_gs(x[u], x[u + half], w.x, w.y, q);
+    }
+  }
+}
+
+// Forward row transform of x (loaded from the source row in phase-1 order
+// k = tig + 16u) into LDS row lrow (phase-2 order at rl(k)); `act` = this
+// slot has a job.  Every thread executes the barriers.
+__device__ __forceinline__ void row_round_fwd(uint32_t (&x)[16], bool act, uint32_t *lrow, int tig,
+                                              const uint2 *twr, uint32_t q) {
+  if (act) {
+    ct_lds<1>(x, twr, 0, q);
 #pragma unroll
     for (int u = 0; u < 16; u++) lrow[rl(tig + 16 * u)] = x[u];
   }
   __syncthreads();
-  if (src) {
+  if (act) {
 #pragma unroll
     for (int u = 0; u < 16; u++) x[u] = lrow[rl(16 * tig + u)];
-    ct_regs<4>(x, tw.p2, q);
+    ct_lds<5>(x, twr, tig, q);
 #pragma unroll
     for (int u = 0; u < 16; u++) lrow[rl(16 * tig + u)] = x[u];  // same words: no other reader
   }
@@ -437,61 +489,77 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const uint32_t q = m.q;
   const int r = threadIdx.x >> 6, slot = (threadIdx.x >> 4) & 3, tig = threadIdx.x & 15;
   const int k0 = 4 * (threadIdx.x & 63);  // element-wise part: words k0..k0+3 of the row
-  const uint32_t row = blk * kRB4 + r, M = (1u << P.loga) + row;
-  const size_t roff = (size_t)row * 256;
+  const uint32_t row0 = blk * kRB4, m0 = (1u << P.loga) + row0;
+  const size_t roff = (size_t)(row0 + r) * 256;
   const uint32_t ndig = cdiv(L1, P.alpha);
   const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;  // digit holding tower t (bypassed)
-  RowTw twf;
-  load_row_tw(twf, P.tw_fwd + (size_t)g * N, tig, M);
+  uint2 *twl = row_tw(lds);
+  const uint2 *twr = twl + r * kRowTw;
+  const uint32_t *evk_t = J.evk + (size_t)g * N + roff + k0;  // + (2 digit + poly) ntot N
+  const size_t evk_step = (size_t)P.ntot * N;
 
-  // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the foreign digits
+  // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the
+  // foreign digits.  Job jb of a round runs in slot jb % 4.
   const uint32_t njobs = IS_P ? ndig : ndig + 1;
-  auto job_src = [&](uint32_t jb, uint32_t *digit) -> const uint32_t * {
-    if (!IS_P && jb < 2) {
-      *digit = 0xffffffffu;
-      return J.wcol + ((size_t)jb * L1 + t) * N + roff;
-    }
+  auto job_digit = [&](uint32_t jb) -> uint32_t {
+    if (!IS_P && jb < 2) return 0xffffffffu;
     uint32_t j = IS_P ? jb : jb - 2;
     if (!IS_P && j >= own) j++;  // skip the own digit
-    *digit = j;
+    return j;
+  };
+  auto job_src = [&](uint32_t jb) -> const uint32_t * {
+    const uint32_t j = job_digit(jb);
+    if (j == 0xffffffffu) return J.wcol + ((size_t)jb * L1 + t) * N + roff;
     return J.ycol + ((size_t)j * T + t) * N + roff;
   };
-  // at most 16 digits (checked at plan creation): one REDC per sum
-  uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
-  uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0};
-  auto mac = [&](const uint32_t (&y)[4], uint32_t j) {
-    uint32_t e0[4], e1[4];
-    ld4(e0, J.evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + roff + k0);
-    ld4(e1, J.evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + roff + k0);
+  // Loads are unconditional (an idle slot re-reads the round's last row, a
+  // job without a key reads a key row the tile reads anyway) so that the
+  // number of loads in flight is the same on every path and each wait
+  // covers exactly the loads it needs.
+  auto load_src = [&](uint32_t (&x)[16], uint32_t base) {
+    const uint32_t *src = job_src(min(base + slot, njobs - 1));
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      acc0[i] = mad64(y[i], e0[i], acc0[i]);
-      acc1[i] = mad64(y[i], e1[i], acc1[i]);
-    }
+    for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
   };
-  if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
-    uint32_t y[4];
-    ld4(y, J.d + (size_t)t * N + roff + k0);
-    mac(y, own);
-  }
-  for (uint32_t base = 0; base < njobs; base += kSlots) {
-    uint32_t dig = 0;
-    const uint32_t jb = base + slot;
-    const uint32_t *src = jb < njobs ? job_src(jb, &dig) : nullptr;
-    // key words of this round's digits, loaded before the transforms so the
-    // loads overlap them
-    uint32_t ek[kSlots][2][4];
+  uint32_t ek[kSlots][2][4];
+  const uint32_t dummy = IS_P ? 0 : own;
+  auto load_keys = [&](uint32_t base) {
 #pragma unroll
     for (int s2 = 0; s2 < kSlots; s2++) {
       const uint32_t jb2 = base + s2;
-      uint32_t d2 = 0xffffffffu;
-      if (jb2 < njobs) (void)job_src(jb2, &d2);
-      if (d2 != 0xffffffffu) {
-        ld4(ek[s2][0], J.evk + (((size_t)d2 * 2 + 0) * P.ntot + g) * N + roff + k0);
-        ld4(ek[s2][1], J.evk + (((size_t)d2 * 2 + 1) * P.ntot + g) * N + roff + k0);
-      }
+      uint32_t d2 = jb2 < njobs ? job_digit(jb2) : 0xffffffffu;
+      d2 = d2 == 0xffffffffu ? dummy : d2;
+      ld4(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
+      ld4(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
     }
-    row_round_fwd(src, row_buf(lds, slot, r), tig, twf, q);
+  };
+
+  // Loads in the order they are needed (the memory counter completes in
+  // order): twiddles, the first round's source rows, the own digit (Q), the
+  // first round's key words.
+  uint2 tw4[kRB4 * kRowTw / kOcThreads];
+  row_tw_issue(tw4, P.tw_fwd + (size_t)g * N, m0);
+  uint32_t x[16];
+  load_src(x, 0);
+  uint32_t yo[4], eo0[4], eo1[4];
+  if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
+    ld4(yo, J.d + (size_t)t * N + roff + k0);
+    ld4(eo0, evk_t + (2 * own + 0) * evk_step);
+    ld4(eo1, evk_t + (2 * own + 1) * evk_step);
+  }
+  load_keys(0);
+  row_tw_store(twl, tw4);
+  __syncthreads();
+
+  // at most 16 digits (checked at plan creation): one REDC per sum
+  uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
+  uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0};
+  for (uint32_t base = 0; base < njobs; base += kSlots) {
+    if (base) {
+      load_src(x, base);
+      load_keys(base);
+    }
+    row_round_fwd(x, base + slot < njobs, row_buf(lds, slot, r), tig, twr, q);
 #pragma unroll
     for (int s2 = 0; s2 < kSlots; s2++) {
       const uint32_t jb2 = base + s2;
@@ -500,9 +568,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       lds4(y, row_buf(lds, s2, r), k0);
 #pragma unroll
       for (int i = 0; i < 4; i++) y[i] = canon4(y[i], q);
-      uint32_t d2;
-      (void)job_src(jb2, &d2);
-      if (d2 == 0xffffffffu) {
+      if (job_digit(jb2) == 0xffffffffu) {
 #pragma unroll
         for (int i = 0; i < 4; i++) (jb2 == 0 ? w0 : w1)[i] = y[i];
       } else {
@@ -515,6 +581,13 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     }
     __syncthreads();  // LDS rows are rewritten by the next round
   }
+  if (!IS_P) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      acc0[i] = mad64(yo[i], eo0[i], acc0[i]);
+      acc1[i] = mad64(yo[i], eo1[i], acc1[i]);
+    }
+  }
   uint32_t r0[4], r1[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
@@ -524,21 +597,20 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   if (IS_P) {
     // ModDown P1 for this special tower: inverse row transforms of both
     // accumulators by slots 0 and 1 (values canonical, < 2q as required)
+    row_tw_issue(tw4, P.tw_inv + (size_t)g * N, m0);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       row_buf(lds, 0, r)[rl(k0 + i)] = r0[i];
       row_buf(lds, 1, r)[rl(k0 + i)] = r1[i];
     }
+    row_tw_store(twl, tw4);
     __syncthreads();
-    RowTw twi;
-    load_row_tw(twi, P.tw_inv + (size_t)g * N, tig, M);
-    uint32_t x[16];
     uint32_t *lrow = row_buf(lds, slot & 1, r);
     const bool act = slot < 2;
     if (act) {
 #pragma unroll
       for (int u = 0; u < 16; u++) x[u] = lrow[rl(16 * tig + u)];
-      gs_regs<4>(x, twi.p2, q);
+      gs_lds<5>(x, twr, tig, q);
 #pragma unroll
       for (int u = 0; u < 16; u++) lrow[rl(16 * tig + u)] = x[u];
     }
@@ -546,7 +618,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     if (act) {
 #pragma unroll
       for (int u = 0; u < 16; u++) x[u] = lrow[rl(tig + 16 * u)];
-      gs_regs<4>(x, twi.p1, q);
+      gs_lds<1>(x, twr, 0, q);
       uint32_t *dst = J.zp + ((size_t)slot * P.num_p + unit) * N + roff;
 #pragma unroll
       for (int u = 0; u < 16; u++) gp(dst)[tig + 16 * u] = x[u];
@@ -582,15 +654,24 @@ __device__ __forceinline__ void oc_tile(const DevPlan &P, const OcJob &J, uint32
 }
 
 template <int A, int TT>
-constexpr int oc_lds_words() {
-  return (TT * ColGeom<A>::LDS > kRowLds) ? TT * ColGeom<A>::LDS : kRowLds;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// LDS words of one phase's tiles, and of any phase (persistent kernel)
+template <int A, int PHASE, int TT>
+constexpr int oc_phase_lds_words() {
+  return (PHASE == OC_ROW_P || PHASE == OC_ROW_Q) ? kRowTileLds
+         : PHASE == OC_INTT_ROW                   ? kRowLds
+         : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS
+                                                           : TT * ColGeom<A>::LDS;
 }
-static_assert(kRowBufs * kPad <= kRowLds, "row tiles fit the LDS of the other tiles");
+template <int A, int TT>
+constexpr int oc_lds_words() {
+  return cmax<A, TT>(cmax<A, TT>(TT * ColGeom<A>::LDS, kRowLds), kRowTileLds);
+}
 
 // One launch per phase: grid x = tiles (max over jobs), grid z = job.
 template <int A, int PHASE, int TT>
 __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, const OcJob *jobs) {
-  __shared__ uint32_t lds[oc_lds_words<A, TT>()];
+  __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>()];
   // the job table is read-only while the kernel runs: scalar loads keep
   // every job field (pointers, level, tile counts) uniform in SGPRs
   OcJob J = one;
