@@ -44,6 +44,19 @@ __device__ __forceinline__ uint4 ldg4(const void *p) {
   const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// Raw buffer access: one 128-bit resource (base, size in bytes) in SGPRs, a
+// per-thread byte offset in a VGPR and a uniform byte offset in an SGPR, so
+// a strided walk over a limb costs no vector address arithmetic.  Accesses
+// past the size read 0 / are dropped by the hardware bounds check.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+}
 __device__ __forceinline__ void stg4(void *p, uint4 v) {
   ks_v4u t;
   t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;

@@ -188,14 +188,17 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   const uint32_t q = ldmod(P.mods + g).q;
   const uint2 *tw = P.tw_inv + (size_t)g * N;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
+  // the limb (col - c0) as a buffer: byte offset (row * 256 + c0 + w) * 4
+  const __amdgpu_buffer_rsrc_t rc = buf_rsrc(col - c0, (uint32_t)(N * 4));
   if constexpr (R2 > 0) {
     using Ph = Phase<A, 1 + R1, R2>;
 #pragma unroll
     for (int gi = 0; gi < Ph::GROUPS / TPS; gi++) {
       const int gg = tig + gi * TPS;
+      const uint32_t vb = ((uint32_t)Ph::base(gg) * rowlen + c0 + w) * 4u;
       uint32_t x[1 << R2];
 #pragma unroll
-      for (int u = 0; u < (1 << R2); u++) x[u] = gp(col)[(size_t)Ph::elem(gg, u) * rowlen + w];
+      for (int u = 0; u < (1 << R2); u++) x[u] = buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
       gs_group<A, 1 + R1, R2>(x, gg, 1u, tw, q);
 #pragma unroll
       for (int u = 0; u < (1 << R2); u++) lds[Ph::elem(gg, u) * W + w] = x[u];
@@ -203,14 +206,15 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
     __syncthreads();
   }
   using Ph = Phase<A, 1, R1>;
+  const uint32_t vb = ((uint32_t)Ph::base(tig) * rowlen + c0 + w) * 4u;
   uint32_t x[1 << R1];
 #pragma unroll
   for (int u = 0; u < (1 << R1); u++)
-    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : gp(col)[(size_t)Ph::elem(tig, u) * rowlen + w];
+    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
   gs_group<A, 1, R1>(x, tig, 1u, tw, q);
 #pragma unroll
   for (int u = 0; u < (1 << R1); u++)
-    gp(col)[(size_t)Ph::elem(tig, u) * rowlen + w] = csub(mul_shoup(x[u], pre.x, pre.y, q), q);
+    buf_st(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u, csub(mul_shoup(x[u], pre.x, pre.y, q), q));
   __syncthreads();
 }
 
@@ -241,11 +245,12 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   // per-thread part one 32-bit offset.  Source i+1 is loaded while source i
   // is accumulated (double buffer), so one memory latency overlaps the next.
   constexpr int LOB = Ph1::LOB;
-  const uint32_t voff = (uint32_t)tig * 256u + c0 + w;
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(src, (uint32_t)(nsrc * N * 4));
+  const uint32_t vsrc = ((uint32_t)tig * 256u + c0 + w) * 4u;
   auto load_src = [&](uint32_t (&xv)[E], uint32_t i) {
-    const uint32_t *sp = src + (size_t)i * N;
+    const uint32_t sb = (uint32_t)(i * N) * 4u;
 #pragma unroll
-    for (int u = 0; u < E; u++) xv[u] = gp(sp + ((size_t)u << (LOB + 8)))[voff];
+    for (int u = 0; u < E; u++) xv[u] = buf_ld(rs, vsrc, sb + ((uint32_t)u << (LOB + 10)));
   };
   for (uint32_t i0 = 0; i0 < nsrc; i0 += 16) {
     const uint32_t i1 = min(nsrc, i0 + 16);
@@ -254,19 +259,27 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     for (int e = 0; e < TT; e++)
 #pragma unroll
       for (int u = 0; u < E; u++) acc[e][u] = 0;
-    uint32_t xa[E], xb[E];
-    load_src(xa, i0);
-    for (uint32_t i = i0; i < i1; i++) {
-      if (i + 1 < i1) load_src(xb, i + 1);
+    // Two register buffers in ping-pong, unrolled by two so that no buffer
+    // is copied (a copy would wait for the load in flight).  Loads past the
+    // end re-read the last source and the odd tail multiplies by a zero
+    // constant, so the loop body has no branch and each wait covers exactly
+    // the buffer about to be used.
+    auto macc = [&](const uint32_t (&xv)[E], uint32_t i, bool live) {
       uint32_t c[TT];
 #pragma unroll
-      for (int e = 0; e < TT; e++) c[e] = gp(cbase)[(size_t)i * cstride + tcol[e]];
+      for (int e = 0; e < TT; e++) c[e] = live ? gp(cbase)[(size_t)i * cstride + tcol[e]] : 0u;
 #pragma unroll
       for (int u = 0; u < E; u++)
 #pragma unroll
-        for (int e = 0; e < TT; e++) acc[e][u] = mad64(xa[u], c[e], acc[e][u]);
-#pragma unroll
-      for (int u = 0; u < E; u++) xa[u] = xb[u];
+        for (int e = 0; e < TT; e++) acc[e][u] = mad64(xv[u], c[e], acc[e][u]);
+    };
+    uint32_t xa[E], xb[E];
+    load_src(xa, i0);
+    for (uint32_t i = i0; i < i1; i += 2) {
+      load_src(xb, min(i + 1, i1 - 1));
+      macc(xa, i, true);
+      load_src(xa, min(i + 2, i1 - 1));
+      macc(xb, i + 1, i + 1 < i1);
     }
 #pragma unroll
     for (int e = 0; e < TT; e++)
@@ -282,8 +295,10 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
         for (int u = 0; u < E; u++) lds[e * G::LDS + Ph1::elem(tig, u) * W + w] = y[e][u];
       } else {
+        const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
+        const uint32_t vb = ((uint32_t)Ph1::base(tig) * 256u + c0 + w) * 4u;
 #pragma unroll
-        for (int u = 0; u < E; u++) gp(tout[e])[(size_t)Ph1::elem(tig, u) * 256 + c0 + w] = y[e][u];
+        for (int u = 0; u < E; u++) buf_st(rt, vb, (uint32_t)u << (LOB + 10), y[e][u]);
       }
     }
   }
@@ -294,6 +309,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     for (int e = 0; e < TT; e++) {
       if ((uint32_t)e < ntgt) {
         const uint2 *tw = P.tw_fwd + (size_t)tg[e] * N;
+        const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
 #pragma unroll
         for (int gi = 0; gi < Ph2::GROUPS / TPS; gi++) {
           const int gg = tig + gi * TPS;
@@ -301,8 +317,9 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
           for (int u = 0; u < (1 << R2); u++) x[u] = lds[e * G::LDS + Ph2::elem(gg, u) * W + w];
           ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
+          const uint32_t vb = ((uint32_t)Ph2::base(gg) * 256u + c0 + w) * 4u;
 #pragma unroll
-          for (int u = 0; u < (1 << R2); u++) gp(tout[e])[(size_t)Ph2::elem(gg, u) * 256 + c0 + w] = x[u];
+          for (int u = 0; u < (1 << R2); u++) buf_st(rt, vb, (uint32_t)u << (Ph2::LOB + 10), x[u]);
         }
       }
     }
