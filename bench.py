@@ -69,23 +69,32 @@ def batched_rate(ks, plan, evks, mods, count, reps, np, torch, synth):
     """Key switches per second for `count` ciphertexts of the bench workload
     in one batch call (shared key per call, keys rotating across calls)."""
     n, l1 = plan.n, LEVEL + 1
-    plan.configure("oc")
     ins = [torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 200 + i)).view(np.int32)).cuda()
            for i in range(count)]
     outs = [torch.empty((2, l1, n), dtype=torch.int32, device="cuda") for _ in range(count)]
-    ws = plan.workspace([LEVEL] * count)
     jobs = lambda r: [(evks[r % len(evks)], LEVEL, x, o) for x, o in zip(ins, outs)]
-    plan.keyswitch_batch(jobs(0), workspace=ws)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for r in range(reps):
-        plan.keyswitch_batch(jobs(r), workspace=ws)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
-    return {"ciphertexts_per_call": count, "calls": reps, "ks_per_s": round(count * reps / (ms / 1e3), 1),
-            "ms_per_call": round(ms / reps, 4)}
+    # OC with 1 or 2 target towers per conversion tile (the tuner's OC
+    # choices); the faster one is reported
+    best = None
+    for tt in (1, 2):
+        plan.configure("oc", tile_towers=tt)
+        ws = plan.workspace([LEVEL] * count)
+        plan.keyswitch_batch(jobs(0), workspace=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for r in range(reps):
+            plan.keyswitch_batch(jobs(r), workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        cur = {"ciphertexts_per_call": count, "calls": reps, "ks_per_s": round(count * reps / (ms / 1e3), 1),
+               "ms_per_call": round(ms / reps, 4), "tile_towers": tt}
+        if best is None or cur["ks_per_s"] > best["ks_per_s"]:
+            best = cur
+        del ws
+    plan.configure("oc")
+    return best
 
 
 def mixed_rate(ks, dnum, reps, np, torch, synth):
@@ -101,8 +110,9 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
     outs = [torch.empty((2, l + 1, n), dtype=torch.int32, device="cuda") for l in levels]
     jobs = [(evk, l, x, o) for l, x, o in zip(levels, ins, outs)]
     res = {}
-    for name, sched, batched in (("oc_batched", "oc", True), ("mp_one_at_a_time", "mp", False)):
-        plan.configure(sched)
+    for name, sched, batched, tt in (("oc_batched", "oc", True, 1), ("oc_batched", "oc", True, 2),
+                                     ("mp_one_at_a_time", "mp", False, 1)):
+        plan.configure(sched, tile_towers=tt)
         ws = plan.workspace(levels if batched else [max(levels)])
 
         def once():
@@ -119,7 +129,7 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
             once()
         b.record()
         torch.cuda.synchronize()
-        res[name] = round(64 * reps / (a.elapsed_time(b) / 1e3), 1)
+        res[name] = max(res.get(name, 0.0), round(64 * reps / (a.elapsed_time(b) / 1e3), 1))
     plan.close()
     return res
 

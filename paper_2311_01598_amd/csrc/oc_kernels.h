@@ -241,9 +241,8 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
     for (int u = 0; u < E; u++) y[e][u] = 0;
   // Element u of this thread sits at row (tig + u * 2^LOB) of the column
-  // block: the per-u part of the address is uniform (scalar base), the
-  // per-thread part one 32-bit offset.  Source i+1 is loaded while source i
-  // is accumulated (double buffer), so one memory latency overlaps the next.
+  // block: the per-thread part of its byte offset is one VGPR, the source
+  // and row parts are uniform (no vector address arithmetic per load).
   constexpr int LOB = Ph1::LOB;
   const __amdgpu_buffer_rsrc_t rs = buf_rsrc(src, (uint32_t)(nsrc * N * 4));
   const uint32_t vsrc = ((uint32_t)tig * 256u + c0 + w) * 4u;
@@ -409,16 +408,29 @@ constexpr int kSlots = 4;
 constexpr int kRB4 = kOcThreads / (16 * kSlots);  // rows per tile
 static_assert(kRB4 == kRBQ, "tile shape matches the host tile count");
 constexpr int kRowBufs = kSlots * kRB4;           // LDS rows used per round
-__device__ __forceinline__ uint32_t *row_buf(uint32_t *lds, int b, int r) { return lds + (b * kRB4 + r) * kPad; }
+// Buffer of slot b in row r: the 4 slots of a row (one wave) sit kPad = 272
+// words apart, i.e. 16 banks apart, so the slots' accesses do not collide.
+__device__ __forceinline__ uint32_t *row_buf(uint32_t *lds, int b, int r) { return lds + (r * kSlots + b) * kPad; }
 
 // The row tiles keep the twiddles of their 4 rows in LDS, in heap order: a
 // row's entry i in [1, 256) is stage s = floor(log2 i) + 1, index
-// i - 2^(s-1) of that stage, i.e. table entry ((M - 1) << (s - 1)) + i of the
-// row's node M.  One cooperative, coalesced fill per tile replaces 30
-// register-resident twiddle pairs per thread.
-constexpr int kRowTw = 256;                          // uint2 entries per row
-constexpr int kRowTileLds = kRowBufs * kPad + 2 * kRB4 * kRowTw;
+// j = i - 2^(s-1) of that stage, i.e. table entry ((M - 1) << (s - 1)) + i of
+// the row's node M.  One cooperative, coalesced fill per tile replaces 30
+// register-resident twiddle pairs per thread.  Stages 5-8 (t = s - 5) are
+// read by the 16 threads of a row at j = tig * 2^t + k; they are stored at
+// 2^(s-1) + k * 16 + tig so that the 16 threads read 16 consecutive entries,
+// and rows are 260 entries apart so that the 4 rows of a wave fall on
+// different banks.
+constexpr int kRowTw = 256;    // heap entries per row
+constexpr int kRowTwS = 260;   // LDS stride between rows (uint2)
+constexpr int kRowTileLds = kRowBufs * kPad + 2 * kRB4 * kRowTwS;
 __device__ __forceinline__ uint2 *row_tw(uint32_t *lds) { return reinterpret_cast<uint2 *>(lds + kRowBufs * kPad); }
+__device__ __forceinline__ int row_tw_slot(int i) {  // LDS position of heap entry i in its row
+  const int lvl = 31 - __clz(i | 1);
+  if (lvl < 4) return i;
+  const int t = lvl - 4, j = i - (1 << lvl);
+  return (1 << lvl) + ((j & ((1 << t) - 1)) << 4) + (j >> t);
+}
 
 // Issue the twiddle loads of the tile's rows (node of row 0: m0); the LDS
 // stores are separate so that other loads can be issued in between.
@@ -432,34 +444,42 @@ __device__ __forceinline__ void row_tw_issue(uint2 (&t)[kRB4 * kRowTw / kOcThrea
 }
 __device__ __forceinline__ void row_tw_store(uint2 *twl, const uint2 (&t)[kRB4 * kRowTw / kOcThreads]) {
 #pragma unroll
-  for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) twl[threadIdx.x + k * kOcThreads] = t[k];
+  for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) {
+    const int e = (int)threadIdx.x + k * kOcThreads, r = e >> 8, i = e & 255;
+    twl[r * kRowTwS + row_tw_slot(i)] = t[k];
+  }
 }
 
 // Four forward / inverse stages on 16 registers with twiddles from a row's
-// heap (stage base S0 = 1 for row stages 1-4 with hi = 0, S0 = 5 for stages
-// 5-8 with hi = the thread's index in the row).
+// LDS heap: S0 = 1 for row stages 1-4 (every thread of the row reads the
+// same entries), S0 = 5 for stages 5-8 (thread tig, transposed layout).
 template <int S0>
-__device__ __forceinline__ void ct_lds(uint32_t (&x)[16], const uint2 *twr, int hi, uint32_t q) {
+__device__ __forceinline__ uint2 row_tw_at(const uint2 *twr, int tig, int t, int k) {
+  if constexpr (S0 == 1) return twr[(1 << t) + k];
+  else return twr[(1 << (4 + t)) + (k << 4) + tig];
+}
+template <int S0>
+__device__ __forceinline__ void ct_lds(uint32_t (&x)[16], const uint2 *twr, int tig, uint32_t q) {
 #pragma unroll
   for (int t = 0; t < 4; t++) {
     const int half = 1 << (3 - t);
 #pragma unroll
     for (int u = 0; u < 16; u++) {
       if (u & half) continue;
-      const uint2 w = twr[(1 << (S0 - 1 + t)) + (hi << t) + (u >> (4 - t))];
+      const uint2 w = row_tw_at<S0>(twr, tig, t, u >> (4 - t));
       bfly_ct(x[u], x[u + half], w.x, w.y, q);
     }
   }
 }
 template <int S0>
-__device__ __forceinline__ void gs_lds(uint32_t (&x)[16], const uint2 *twr, int hi, uint32_t q) {
+__device__ __forceinline__ void gs_lds(uint32_t (&x)[16], const uint2 *twr, int tig, uint32_t q) {
 #pragma unroll
   for (int t = 3; t >= 0; t--) {
     const int half = 1 << (3 - t);
 #pragma unroll
     for (int u = 0; u < 16; u++) {
       if (u & half) continue;
-      const uint2 w = twr[(1 << (S0 - 1 + t)) + (hi << t) + (u >> (4 - t))];
+      const uint2 w = row_tw_at<S0>(twr, tig, t, u >> (4 - t));
       bfly_gs(x[u], x[u + half], w.x, w.y, q);
     }
   }
@@ -471,7 +491,7 @@ __device__ __forceinline__ void gs_lds(uint32_t (&x)[16], const uint2 *twr, int 
 __device__ __forceinline__ void row_round_fwd(uint32_t (&x)[16], bool act, uint32_t *lrow, int tig,
                                               const uint2 *twr, uint32_t q) {
   if (act) {
-    ct_lds<1>(x, twr, 0, q);
+    ct_lds<1>(x, twr, tig, q);
 #pragma unroll
     for (int u = 0; u < 16; u++) lrow[rl(tig + 16 * u)] = x[u];
   }
@@ -511,7 +531,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const uint32_t ndig = cdiv(L1, P.alpha);
   const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;  // digit holding tower t (bypassed)
   uint2 *twl = row_tw(lds);
-  const uint2 *twr = twl + r * kRowTw;
+  const uint2 *twr = twl + r * kRowTwS;
   const uint32_t *evk_t = J.evk + (size_t)g * N + roff + k0;  // + (2 digit + poly) ntot N
   const size_t evk_step = (size_t)P.ntot * N;
 
@@ -635,7 +655,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     if (act) {
 #pragma unroll
       for (int u = 0; u < 16; u++) x[u] = lrow[rl(tig + 16 * u)];
-      gs_lds<1>(x, twr, 0, q);
+      gs_lds<1>(x, twr, tig, q);
       uint32_t *dst = J.zp + ((size_t)slot * P.num_p + unit) * N + roff;
 #pragma unroll
       for (int u = 0; u < 16; u++) gp(dst)[tig + 16 * u] = x[u];

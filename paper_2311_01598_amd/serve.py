@@ -73,8 +73,8 @@ class Server:
         import torch
         self.torch = torch
         self.plans, self.keys = plans, keys
-        for p in plans.values():
-            p.configure("oc", batch_mode=1)
+        for p in plans.values():  # OC, two targets per conversion tile: the faster choice for batches
+            p.configure("oc", batch_mode=1, tile_towers=2)
         self.budget = budget_bytes
         self.pool = HbmPool(budget_bytes)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]

@@ -68,8 +68,10 @@ def _requests(plan, count, seed):
 
 
 def _alone(plan, keys, r):
-    plan.configure("oc", batch_mode=1)
-    return plan.keyswitch(keys[r.key], r.level, r.d)
+    plan.configure("mp")  # a different schedule: identical bits are required
+    out = plan.keyswitch(keys[r.key], r.level, r.d)
+    plan.configure("oc", batch_mode=1, tile_towers=2)
+    return out
 
 
 @pytest.mark.gpu
