@@ -31,10 +31,17 @@ struct Phase {
   __device__ static __forceinline__ int elem(int g, int u) { return base(g) + (u << LOB); }
 };
 
+// Twiddle sources: a global table (entries read with a global load) or a
+// copy of its first entries staged in LDS.
+struct LdsTw {
+  const uint2 *p;
+};
+__device__ __forceinline__ uint2 tw_at(const uint2 *tw, uint32_t i) { return ldg2(tw + i); }
+__device__ __forceinline__ uint2 tw_at(LdsTw tw, uint32_t i) { return tw.p[i]; }
+
 // Forward stages S0..S0+R-1 on one register group.
-template <int A, int S0, int R>
-__device__ __forceinline__ void ct_group(uint32_t (&x)[1 << R], int g, uint32_t M, const uint2 *__restrict__ tw,
-                                         uint32_t q) {
+template <int A, int S0, int R, class TW>
+__device__ __forceinline__ void ct_group(uint32_t (&x)[1 << R], int g, uint32_t M, TW tw, uint32_t q) {
   const uint32_t hi = (uint32_t)Phase<A, S0, R>::hi(g);
 #pragma unroll
   for (int t = 0; t < R; t++) {
@@ -43,16 +50,15 @@ __device__ __forceinline__ void ct_group(uint32_t (&x)[1 << R], int g, uint32_t 
 #pragma unroll
     for (int u = 0; u < (1 << R); u++) {
       if (u & half) continue;
-      const uint2 w = ldg2(tw + node + (uint32_t)(u >> (R - t)));
+      const uint2 w = tw_at(tw, node + (uint32_t)(u >> (R - t)));
       bfly_ct(x[u], x[u + half], w.x, w.y, q);
     }
   }
 }
 
 // Inverse stages S0+R-1..S0 on one register group.
-template <int A, int S0, int R>
-__device__ __forceinline__ void gs_group(uint32_t (&x)[1 << R], int g, uint32_t M, const uint2 *__restrict__ tw,
-                                         uint32_t q) {
+template <int A, int S0, int R, class TW>
+__device__ __forceinline__ void gs_group(uint32_t (&x)[1 << R], int g, uint32_t M, TW tw, uint32_t q) {
   const uint32_t hi = (uint32_t)Phase<A, S0, R>::hi(g);
 #pragma unroll
   for (int t = R - 1; t >= 0; t--) {
@@ -61,7 +67,7 @@ __device__ __forceinline__ void gs_group(uint32_t (&x)[1 << R], int g, uint32_t 
 #pragma unroll
     for (int u = 0; u < (1 << R); u++) {
       if (u & half) continue;
-      const uint2 w = ldg2(tw + node + (uint32_t)(u >> (R - t)));
+      const uint2 w = tw_at(tw, node + (uint32_t)(u >> (R - t)));
       bfly_gs(x[u], x[u + half], w.x, w.y, q);
     }
   }

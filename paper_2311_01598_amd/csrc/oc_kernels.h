@@ -162,6 +162,30 @@ __device__ __forceinline__ void tile_intt_row(const DevPlan &P, const OcJob &J, 
   row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, ldmod(P.mods + i).q);
 }
 
+// Column passes (node 1) use only the first 2^A entries of a modulus'
+// twiddle table: a tile stages them in LDS once (one coalesced load per
+// thread per 256 entries) instead of every thread loading its 2 x 15 pairs
+// from global memory on the critical path.
+template <int A>
+struct ColTw {
+  static constexpr int PER = (1 << A) > kOcThreads ? (1 << A) / kOcThreads : 1;  // entries per thread
+  uint2 v[PER];
+  __device__ __forceinline__ void issue(const uint2 *tw) {
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const uint32_t i = threadIdx.x + k * kOcThreads;
+      v[k] = ldg2(tw + (i < (1u << A) ? i : 0u));
+    }
+  }
+  __device__ __forceinline__ void store(uint2 *twl) const {
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const uint32_t i = threadIdx.x + k * kOcThreads;
+      if (i < (1u << A)) twl[i] = v[k];
+    }
+  }
+};
+
 // INTT_COL / INTT_COL_DN: inverse column pass of one limb, then
 // x~ = [v * c]_m canonical with the per-source constant c.
 template <int A>
@@ -186,31 +210,46 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
     col = J.zp + (size_t)li * N + c0;
   }
   const uint32_t q = ldmod(P.mods + g).q;
-  const uint2 *tw = P.tw_inv + (size_t)g * N;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
+  // twiddles first (staged in LDS after the data region), then the data
+  ColTw<A> ct;
+  ct.issue(P.tw_inv + (size_t)g * N);
+  uint2 *twl = reinterpret_cast<uint2 *>(lds + G::LDS);
+  const LdsTw tw{twl};
   // the limb (col - c0) as a buffer: byte offset (row * 256 + c0 + w) * 4
   const __amdgpu_buffer_rsrc_t rc = buf_rsrc(col - c0, (uint32_t)(N * 4));
-  if constexpr (R2 > 0) {
-    using Ph = Phase<A, 1 + R1, R2>;
-#pragma unroll
-    for (int gi = 0; gi < Ph::GROUPS / TPS; gi++) {
-      const int gg = tig + gi * TPS;
-      const uint32_t vb = ((uint32_t)Ph::base(gg) * rowlen + c0 + w) * 4u;
-      uint32_t x[1 << R2];
-#pragma unroll
-      for (int u = 0; u < (1 << R2); u++) x[u] = buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
-      gs_group<A, 1 + R1, R2>(x, gg, 1u, tw, q);
-#pragma unroll
-      for (int u = 0; u < (1 << R2); u++) lds[Ph::elem(gg, u) * W + w] = x[u];
-    }
-    __syncthreads();
-  }
   using Ph = Phase<A, 1, R1>;
   const uint32_t vb = ((uint32_t)Ph::base(tig) * rowlen + c0 + w) * 4u;
   uint32_t x[1 << R1];
+  if constexpr (R2 > 0) {
+    using Ph2 = Phase<A, 1 + R1, R2>;
+    constexpr int GPT = Ph2::GROUPS / TPS;
+    uint32_t x2[GPT][1 << R2];
 #pragma unroll
-  for (int u = 0; u < (1 << R1); u++)
-    x[u] = R2 > 0 ? lds[Ph::elem(tig, u) * W + w] : buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
+    for (int gi = 0; gi < GPT; gi++) {
+      const int gg = tig + gi * TPS;
+      const uint32_t vb2 = ((uint32_t)Ph2::base(gg) * rowlen + c0 + w) * 4u;
+#pragma unroll
+      for (int u = 0; u < (1 << R2); u++) x2[gi][u] = buf_ld(rc, vb2, ((uint32_t)u << Ph2::LOB) * rowlen * 4u);
+    }
+    ct.store(twl);
+    __syncthreads();
+#pragma unroll
+    for (int gi = 0; gi < GPT; gi++) {
+      const int gg = tig + gi * TPS;
+      gs_group<A, 1 + R1, R2>(x2[gi], gg, 1u, tw, q);
+#pragma unroll
+      for (int u = 0; u < (1 << R2); u++) lds[Ph2::elem(gg, u) * W + w] = x2[gi][u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (1 << R1); u++) x[u] = lds[Ph::elem(tig, u) * W + w];
+  } else {
+#pragma unroll
+    for (int u = 0; u < (1 << R1); u++) x[u] = buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
+    ct.store(twl);
+    __syncthreads();
+  }
   gs_group<A, 1, R1>(x, tig, 1u, tw, q);
 #pragma unroll
   for (int u = 0; u < (1 << R1); u++)
@@ -235,6 +274,12 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   ModQ mq[TT];
 #pragma unroll
   for (int e = 0; e < TT; e++) mq[e] = ldmod(P.mods + tg[e]);
+  // the targets' column twiddles, staged in LDS after the data regions once
+  // the conversion is done
+  ColTw<A> ct[TT];
+#pragma unroll
+  for (int e = 0; e < TT; e++) ct[e].issue(P.tw_fwd + (size_t)tg[e] * N);
+  uint2 *twl = reinterpret_cast<uint2 *>(lds + TT * G::LDS);
   uint32_t y[TT][E];
 #pragma unroll
   for (int e = 0; e < TT; e++)
@@ -286,9 +331,12 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
       for (int u = 0; u < E; u++) y[e][u] = csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
   }
 #pragma unroll
+  for (int e = 0; e < TT; e++) ct[e].store(twl + e * (1 << A));
+  __syncthreads();
+#pragma unroll
   for (int e = 0; e < TT; e++) {
     if ((uint32_t)e < ntgt) {
-      const uint2 *tw = P.tw_fwd + (size_t)tg[e] * N;
+      const LdsTw tw{twl + e * (1 << A)};
       ct_group<A, 1, R1>(y[e], tig, 1u, tw, mq[e].q);
       if constexpr (R2 > 0) {
 #pragma unroll
@@ -307,7 +355,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
     for (int e = 0; e < TT; e++) {
       if ((uint32_t)e < ntgt) {
-        const uint2 *tw = P.tw_fwd + (size_t)tg[e] * N;
+        const LdsTw tw{twl + e * (1 << A)};
         const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
 #pragma unroll
         for (int gi = 0; gi < Ph2::GROUPS / TPS; gi++) {
@@ -697,12 +745,30 @@ template <int A, int PHASE, int TT>
 constexpr int oc_phase_lds_words() {
   return (PHASE == OC_ROW_P || PHASE == OC_ROW_Q) ? kRowTileLds
          : PHASE == OC_INTT_ROW                   ? kRowLds
-         : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS
-                                                           : TT * ColGeom<A>::LDS;
+         : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS + 2 * (1 << A)
+                                                           : TT * (ColGeom<A>::LDS + 2 * (1 << A));
 }
 template <int A, int TT>
 constexpr int oc_lds_words() {
-  return cmax<A, TT>(cmax<A, TT>(TT * ColGeom<A>::LDS, kRowLds), kRowTileLds);
+  return cmax<A, TT>(cmax<A, TT>(TT * (ColGeom<A>::LDS + 2 * (1 << A)), kRowLds), kRowTileLds);
+}
+
+// Blocks of a launch are dealt to the 8 XCDs in turn (block b runs on XCD
+// b % 8, each XCD with its own L2).  A column-tile index is unit * CB +
+// column block; the remap gives XCD x the column blocks [x CB/8, (x+1) CB/8)
+// of every unit, so the two 64-byte halves of a 128-byte line, and a source
+// column read by many conversion targets, stay in one L2.  A bijection on
+// [0, T) for every T that is a multiple of CB (tile counts of column phases
+// are), so the per-job range checks stay valid.
+template <int CB>
+__device__ __forceinline__ uint32_t xcd_col_tile(uint32_t b) {
+  if constexpr (CB % 8 != 0) {
+    return b;
+  } else {
+    constexpr uint32_t per = CB / 8;
+    const uint32_t x = b & 7u, k = b >> 3;
+    return (k / per) * CB + x * per + (k % per);
+  }
 }
 
 // One launch per phase: grid x = tiles (max over jobs), grid z = job.
@@ -720,13 +786,16 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(OcJob) / 4); i++) dst[i] = src[i];
   }
+  constexpr bool COL = PHASE != OC_INTT_ROW && PHASE != OC_ROW_P && PHASE != OC_ROW_Q;
   if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
-    if (blockIdx.x < np) tile_up<A, TT>(P, J, blockIdx.x, true, J.ttu, lds);
-    else if (blockIdx.x - np < J.tiles[OC_UP_Q]) tile_up<A, TT>(P, J, blockIdx.x - np, false, J.ttu, lds);
+    if (blockIdx.x < np) tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(blockIdx.x), true, J.ttu, lds);
+    else if (blockIdx.x - np < J.tiles[OC_UP_Q])
+      tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(blockIdx.x - np), false, J.ttu, lds);
   } else {
     if (blockIdx.x >= J.tiles[PHASE]) return;
-    oc_tile<A, TT, TT>(P, J, PHASE, blockIdx.x, lds);
+    const uint32_t tile = COL ? xcd_col_tile<ColGeom<A>::CB>(blockIdx.x) : blockIdx.x;
+    oc_tile<A, TT, TT>(P, J, PHASE, tile, lds);
   }
 }
 
