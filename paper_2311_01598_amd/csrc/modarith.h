@@ -57,6 +57,18 @@ __device__ __forceinline__ uint32_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t vo
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
   __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
 }
+// Streaming variants for data touched once per key switch (the key words,
+// the output): non-temporal hints, so that they do not push the reused
+// tables and intermediates out of the caches.
+__device__ __forceinline__ uint4 ldg4_nt(const void *p) {
+  const ks_v4u v = __builtin_nontemporal_load((const KS_GLOBAL ks_v4u *)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg4_nt(void *p, uint4 v) {
+  ks_v4u t;
+  t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+  __builtin_nontemporal_store(t, (KS_GLOBAL ks_v4u *)p);
+}
 __device__ __forceinline__ void stg4(void *p, uint4 v) {
   ks_v4u t;
   t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;

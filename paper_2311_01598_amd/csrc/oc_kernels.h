@@ -562,6 +562,10 @@ __device__ __forceinline__ void ld4(uint32_t (&v)[4], const uint32_t *p) {
   const uint4 t = ldg4(p);
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
+__device__ __forceinline__ void ld4_nt(uint32_t (&v)[4], const uint32_t *p) {
+  const uint4 t = ldg4_nt(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
 
 template <bool IS_P>
 __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
@@ -614,8 +618,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       const uint32_t jb2 = base + s2;
       uint32_t d2 = jb2 < njobs ? job_digit(jb2) : 0xffffffffu;
       d2 = d2 == 0xffffffffu ? dummy : d2;
-      ld4(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
-      ld4(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
+      ld4_nt(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
+      ld4_nt(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
     }
   };
 
@@ -629,8 +633,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   uint32_t yo[4], eo0[4], eo1[4];
   if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
     ld4(yo, J.d + (size_t)t * N + roff + k0);
-    ld4(eo0, evk_t + (2 * own + 0) * evk_step);
-    ld4(eo1, evk_t + (2 * own + 1) * evk_step);
+    ld4_nt(eo0, evk_t + (2 * own + 0) * evk_step);
+    ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
   }
   load_keys(0);
   row_tw_store(twl, tw4);
@@ -716,8 +720,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       o0[i] = csub(mul_shoup(r0[i] + q - w0[i], f.x, f.y, q), q);
       o1[i] = csub(mul_shoup(r1[i] + q - w1[i], f.x, f.y, q), q);
     }
-    stg4(J.out + ((size_t)0 * L1 + t) * N + roff + k0, make_uint4(o0[0], o0[1], o0[2], o0[3]));
-    stg4(J.out + ((size_t)1 * L1 + t) * N + roff + k0, make_uint4(o1[0], o1[1], o1[2], o1[3]));
+    stg4_nt(J.out + ((size_t)0 * L1 + t) * N + roff + k0, make_uint4(o0[0], o0[1], o0[2], o0[3]));
+    stg4_nt(J.out + ((size_t)1 * L1 + t) * N + roff + k0, make_uint4(o1[0], o1[1], o1[2], o1[3]));
   }
   __syncthreads();
 }
