@@ -56,6 +56,25 @@ def stage_muls(log_n, l1, k, alpha):
     }
 
 
+def stage_bytes(log_n, l1, k, alpha):
+    """Algorithmic HBM bytes per launch of each Output-Centric stage: every
+    buffer the stage must read or write, once (inputs, key words, outputs and
+    the intermediates handed between stages; constant tables excluded)."""
+    limb = 4 << log_n
+    sizes = [min(alpha, l1 - lo) for lo in range(0, l1, alpha)]
+    ndig = len(sizes)
+    up_targets = sum(k + (l1 - s) for s in sizes)
+    return {
+        "oc.intt_row": limb * 2 * l1,                                     # d in, xt out
+        "oc.intt_col.up": limb * 2 * l1,                                  # xt in place
+        "oc.bconv_col.up": limb * (l1 + up_targets),                      # xt in, ycol out
+        "oc.row.p": limb * (ndig * k + 2 * ndig * k + 2 * k),             # ycol, key, zp out
+        "oc.intt_col.down": limb * 2 * 2 * k,                             # zp in place
+        "oc.bconv_col.down": limb * (2 * k + 2 * l1),                     # zp in, wcol out
+        "oc.row.q": limb * ((ndig - 1) * l1 + 2 * l1 + l1 + 2 * ndig * l1 + 2 * l1),  # ycol, wcol, d, key, out
+    }
+
+
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -300,22 +319,42 @@ def main():
         "latency_ms": {"p50": round(lat[len(lat) // 2], 4), "p99": round(lat[min(len(lat) - 1, int(len(lat) * 0.99))], 4)},
     }
     muls = stage_muls(LOG_N, l1, NUM_P, plan.alpha)
-    stages = {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(v[0], 1), 3)} for k, v in trace.items()}
+    sbytes = stage_bytes(LOG_N, l1, NUM_P, plan.alpha)
+    stages = {}
+    for k, v in trace.items():
+        st = {"launches": v[0], "avg_us": round(1e3 * v[1] / max(v[0], 1), 3)}
+        if k in muls:
+            t = 1e-3 * v[1] / max(v[0], 1)
+            st.update({"mul_frac": round(muls[k] / t / MUL_PEAK_PER_S, 4),
+                       "hbm_frac": round(sbytes[k] / t / (HBM_PEAK_GBS * 1e9), 4),
+                       "bound": "hbm" if sbytes[k] / (HBM_PEAK_GBS * 1e9) >= muls[k] / MUL_PEAK_PER_S else "alu"})
+        stages[k] = st
+    # dominant kernel: the longest stage; its bound is the roofline its
+    # algorithmic work reaches first (bytes at the HBM peak vs multiplies at
+    # the integer multiply peak)
     dom = max((k for k in trace if k in muls), key=lambda k: trace[k][1] / max(trace[k][0], 1))
     dom_s = 1e-3 * trace[dom][1] / trace[dom][0]
-    achieved = muls[dom] / dom_s
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         prof = json.load(open(PROFILE_TRAFFIC))
         if prof.get("source_digest") == kernel_source_digest() and dom in prof.get("kernels", {}):
             traffic = prof["kernels"][dom]["bytes_per_launch"]
-    res["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 4),
-                       "peak": round(MUL_PEAK_PER_S / 1e12, 4), "unit": "Tmul/s (32-bit integer multiplies)",
-                       "frac": round(achieved / MUL_PEAK_PER_S, 4), "traffic": traffic,
-                       "avg_us": round(dom_s * 1e6, 3), "muls_per_launch": muls[dom]}
+    if stages[dom]["bound"] == "hbm":
+        achieved = sbytes[dom] / dom_s
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved / 1e9, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / (HBM_PEAK_GBS * 1e9), 4),
+                           "traffic": traffic, "avg_us": round(dom_s * 1e6, 3), "bytes_per_launch": sbytes[dom]}
+    else:
+        achieved = muls[dom] / dom_s
+        res["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 4),
+                           "peak": round(MUL_PEAK_PER_S / 1e12, 4), "unit": "Tmul/s (32-bit integer multiplies)",
+                           "frac": round(achieved / MUL_PEAK_PER_S, 4), "traffic": traffic,
+                           "avg_us": round(dom_s * 1e6, 3), "muls_per_launch": muls[dom]}
     tot_muls = sum(muls.values())
     res["whole_keyswitch"] = {"muls": tot_muls, "mul_frac": round(tot_muls * ks_per_s / MUL_PEAK_PER_S, 4),
-                              "hbm_frac": round(nbytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
+                              "hbm_frac": round(nbytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4),
+                              "stage_bytes": sum(sbytes.values()),
+                              "stage_bytes_frac": round(sum(sbytes.values()) * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
     res["stages"] = stages
     if args.batch:
         res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)

@@ -81,6 +81,17 @@ struct ModQ {
   uint32_t mu;       // floor(2^32 / q)
   uint32_t pad;
 };
+// Shoup companion floor(w 2^32 / q) of w < q from qrecip = 2^32 / q (double):
+// the double product is within 2^-20 of the exact quotient, so its floor r
+// is off by at most one; the remainder w 2^32 - r q (exact modulo 2^32,
+// and within (-2^31, 2^31) because it lies in [-q, 2q)) tells which way.
+__device__ __forceinline__ uint32_t shoup_companion(uint32_t w, uint32_t q, double qrecip) {
+  uint32_t r = (uint32_t)((double)w * qrecip);
+  const int32_t t = (int32_t)(0u - r * q);
+  r = t < 0 ? r - 1u : r;
+  r = t >= (int32_t)q ? r + 1u : r;
+  return r;
+}
 __device__ __forceinline__ ModQ ldmod(const ModQ *p) {
   const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;
   ModQ m;

@@ -169,19 +169,21 @@ __device__ __forceinline__ void tile_intt_row(const DevPlan &P, const OcJob &J, 
 template <int A>
 struct ColTw {
   static constexpr int PER = (1 << A) > kOcThreads ? (1 << A) / kOcThreads : 1;  // entries per thread
-  uint2 v[PER];
-  __device__ __forceinline__ void issue(const uint2 *tw) {
+  uint32_t v[PER];
+  // tw32: the modulus' 4-byte table (psi^brv or psi^-brv)
+  __device__ __forceinline__ void issue(const uint32_t *tw32) {
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const uint32_t i = threadIdx.x + k * kOcThreads;
-      v[k] = ldg2(tw + (i < (1u << A) ? i : 0u));
+      v[k] = gp(tw32)[i < (1u << A) ? i : 0u];
     }
   }
-  __device__ __forceinline__ void store(uint2 *twl) const {
+  // forward tables hold -w mod 2^32 next to the companion of w (see bfly_ct)
+  __device__ __forceinline__ void store(uint2 *twl, uint32_t q, double qr, bool fwd) const {
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const uint32_t i = threadIdx.x + k * kOcThreads;
-      if (i < (1u << A)) twl[i] = v[k];
+      if (i < (1u << A)) twl[i] = make_uint2(fwd ? 0u - v[k] : v[k], shoup_companion(v[k], q, qr));
     }
   }
 };
@@ -213,7 +215,8 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
   // twiddles first (staged in LDS after the data region), then the data
   ColTw<A> ct;
-  ct.issue(P.tw_inv + (size_t)g * N);
+  ct.issue(P.tw_inv32 + (size_t)g * N);
+  const double qr = gp(P.qrecip)[g];
   uint2 *twl = reinterpret_cast<uint2 *>(lds + G::LDS);
   const LdsTw tw{twl};
   // the limb (col - c0) as a buffer: byte offset (row * 256 + c0 + w) * 4
@@ -232,7 +235,7 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
 #pragma unroll
       for (int u = 0; u < (1 << R2); u++) x2[gi][u] = buf_ld(rc, vb2, ((uint32_t)u << Ph2::LOB) * rowlen * 4u);
     }
-    ct.store(twl);
+    ct.store(twl, q, qr, false);
     __syncthreads();
 #pragma unroll
     for (int gi = 0; gi < GPT; gi++) {
@@ -247,7 +250,7 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   } else {
 #pragma unroll
     for (int u = 0; u < (1 << R1); u++) x[u] = buf_ld(rc, vb, ((uint32_t)u << Ph::LOB) * rowlen * 4u);
-    ct.store(twl);
+    ct.store(twl, q, qr, false);
     __syncthreads();
   }
   gs_group<A, 1, R1>(x, tig, 1u, tw, q);
@@ -277,8 +280,12 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   // the targets' column twiddles, staged in LDS after the data regions once
   // the conversion is done
   ColTw<A> ct[TT];
+  double qr[TT];
 #pragma unroll
-  for (int e = 0; e < TT; e++) ct[e].issue(P.tw_fwd + (size_t)tg[e] * N);
+  for (int e = 0; e < TT; e++) {
+    ct[e].issue(P.tw_fwd32 + (size_t)tg[e] * N);
+    qr[e] = gp(P.qrecip)[tg[e]];
+  }
   uint2 *twl = reinterpret_cast<uint2 *>(lds + TT * G::LDS);
   uint32_t y[TT][E];
 #pragma unroll
@@ -331,7 +338,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
       for (int u = 0; u < E; u++) y[e][u] = csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
   }
 #pragma unroll
-  for (int e = 0; e < TT; e++) ct[e].store(twl + e * (1 << A));
+  for (int e = 0; e < TT; e++) ct[e].store(twl + e * (1 << A), mq[e].q, qr[e], true);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < TT; e++) {
@@ -480,21 +487,25 @@ __device__ __forceinline__ int row_tw_slot(int i) {  // LDS position of heap ent
   return (1 << lvl) + ((j & ((1 << t) - 1)) << 4) + (j >> t);
 }
 
-// Issue the twiddle loads of the tile's rows (node of row 0: m0); the LDS
-// stores are separate so that other loads can be issued in between.
-__device__ __forceinline__ void row_tw_issue(uint2 (&t)[kRB4 * kRowTw / kOcThreads], const uint2 *tw, uint32_t m0) {
+// Issue the twiddle loads of the tile's rows (node of row 0: m0) from a
+// 4-byte table; the LDS stores (with the Shoup companions derived there) are
+// separate so that other loads can be issued in between.
+__device__ __forceinline__ void row_tw_issue(uint32_t (&t)[kRB4 * kRowTw / kOcThreads], const uint32_t *tw32,
+                                             uint32_t m0) {
 #pragma unroll
   for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) {
     const int e = (int)threadIdx.x + k * kOcThreads, r = e >> 8, i = e & 255;
     const int lvl = 31 - __clz(i | 1);
-    t[k] = ldg2(tw + ((size_t)(m0 + r - 1) << lvl) + (i | (i == 0)));  // entry 0 unused: read entry 1
+    t[k] = gp(tw32)[((size_t)(m0 + r - 1) << lvl) + (i | (i == 0))];  // entry 0 unused: read entry 1
   }
 }
-__device__ __forceinline__ void row_tw_store(uint2 *twl, const uint2 (&t)[kRB4 * kRowTw / kOcThreads]) {
+// fwd: entries (-w mod 2^32, companion of w) as bfly_ct wants them
+__device__ __forceinline__ void row_tw_store(uint2 *twl, const uint32_t (&t)[kRB4 * kRowTw / kOcThreads], uint32_t q,
+                                             double qr, bool fwd) {
 #pragma unroll
   for (int k = 0; k < kRB4 * kRowTw / kOcThreads; k++) {
     const int e = (int)threadIdx.x + k * kOcThreads, r = e >> 8, i = e & 255;
-    twl[r * kRowTwS + row_tw_slot(i)] = t[k];
+    twl[r * kRowTwS + row_tw_slot(i)] = make_uint2(fwd ? 0u - t[k] : t[k], shoup_companion(t[k], q, qr));
   }
 }
 
@@ -626,8 +637,9 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // Loads in the order they are needed (the memory counter completes in
   // order): twiddles, the first round's source rows, the own digit (Q), the
   // first round's key words.
-  uint2 tw4[kRB4 * kRowTw / kOcThreads];
-  row_tw_issue(tw4, P.tw_fwd + (size_t)g * N, m0);
+  uint32_t tw4[kRB4 * kRowTw / kOcThreads];
+  row_tw_issue(tw4, P.tw_fwd32 + (size_t)g * N, m0);
+  const double qr = gp(P.qrecip)[g];
   uint32_t x[16];
   load_src(x, 0);
   uint32_t yo[4], eo0[4], eo1[4];
@@ -637,7 +649,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
   }
   load_keys(0);
-  row_tw_store(twl, tw4);
+  row_tw_store(twl, tw4, q, qr, true);
   __syncthreads();
 
   // at most 16 digits (checked at plan creation): one REDC per sum
@@ -686,13 +698,13 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   if (IS_P) {
     // ModDown P1 for this special tower: inverse row transforms of both
     // accumulators by slots 0 and 1 (values canonical, < 2q as required)
-    row_tw_issue(tw4, P.tw_inv + (size_t)g * N, m0);
+    row_tw_issue(tw4, P.tw_inv32 + (size_t)g * N, m0);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       row_buf(lds, 0, r)[rl(k0 + i)] = r0[i];
       row_buf(lds, 1, r)[rl(k0 + i)] = r1[i];
     }
-    row_tw_store(twl, tw4);
+    row_tw_store(twl, tw4, q, qr, false);
     __syncthreads();
     uint32_t *lrow = row_buf(lds, slot & 1, r);
     const bool act = slot < 2;

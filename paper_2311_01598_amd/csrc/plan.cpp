@@ -148,6 +148,8 @@ ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
 
   // --- twiddles
   std::vector<uint2> twf((size_t)ntot * n), twi((size_t)ntot * n);
+  std::vector<uint32_t> twf32((size_t)ntot * n), twi32((size_t)ntot * n);
+  std::vector<double> qrecip(ntot);
   std::vector<uint32_t> pw(n), pwi(n);
   for (uint32_t g = 0; g < ntot; g++) {
     const uint32_t q = pl->mod[g], s = pl->psi[g], si = inv_mod(s, q);
@@ -161,7 +163,10 @@ ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
       // forward entries carry -w mod 2^32 (see bfly_ct)
       twf[(size_t)g * n + i] = make_uint2(0u - pw[r], shoup_of(pw[r], q));
       twi[(size_t)g * n + i] = shoup_pair(pwi[r], q);
+      twf32[(size_t)g * n + i] = pw[r];
+      twi32[(size_t)g * n + i] = pwi[r];
     }
+    qrecip[g] = 4294967296.0 / (double)q;
   }
   std::vector<ModQ> mq(ntot);
   for (uint32_t g = 0; g < ntot; g++) {
@@ -227,7 +232,8 @@ ks_status_t plan_build(const ks_params_t *p, Plan *pl) {
   if ((st = upload(pl, twf, &d.tw_fwd)) || (st = upload(pl, twi, &d.tw_inv)) || (st = upload(pl, mq, &d.mods)) ||
       (st = upload(pl, up_pre, &d.up_pre)) || (st = upload(pl, up_conv, &d.up_conv)) ||
       (st = upload(pl, dn_pre, &d.dn_pre)) || (st = upload(pl, dn_conv, &d.dn_conv)) ||
-      (st = upload(pl, dn_fin, &d.dn_fin)))
+      (st = upload(pl, dn_fin, &d.dn_fin)) || (st = upload(pl, twf32, &d.tw_fwd32)) ||
+      (st = upload(pl, twi32, &d.tw_inv32)) || (st = upload(pl, qrecip, &d.qrecip)))
     return st;
   d.log_n = p->log_n;
   d.logb = kRowLog;

@@ -26,6 +26,11 @@ struct DevPlan {
   const uint2 *tw_fwd;   // [ntot][N] (-psi^brv(i) mod 2^32, Shoup companion of psi^brv(i))
   const uint2 *tw_inv;   // [ntot][N] (psi^-brv(i), Shoup companion)
   const ModQ *mods;      // [ntot]
+  // The same tables as plain residues (4 bytes per entry: psi^brv(i) and
+  // psi^-brv(i)) for kernels that stage twiddles through LDS and derive the
+  // Shoup companions there, with qrecip[g] = 2^32 / m_g in double precision.
+  const uint32_t *tw_fwd32, *tw_inv32;
+  const double *qrecip;
   // ModUp basis conversion, digit j holding s towers (the last digit of a
   // lower level may be partial):
   //   up_pre [(j*alpha + s-1)*alpha + i]          Shoup pair of N^-1 [qhat_i^-1]_{q_i}
