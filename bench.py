@@ -94,9 +94,9 @@ def batched_rate(ks, plan, evks, mods, count, reps, np, torch, synth):
     jobs = lambda r: [(evks[r % len(evks)], LEVEL, x, o) for x, o in zip(ins, outs)]
     # OC with 1 or 2 target towers per conversion tile (the tuner's OC
     # choices); the faster one is reported
-    best = None
-    for tt in (1, 2):
-        plan.configure("oc", tile_towers=tt)
+    best, table = None, {}
+    for tt, mode in ((1, 1), (2, 1), (2, 3)):
+        plan.configure("oc", tile_towers=tt, batch_mode=mode)
         ws = plan.workspace([LEVEL] * count)
         plan.keyswitch_batch(jobs(0), workspace=ws)
         torch.cuda.synchronize()
@@ -108,11 +108,13 @@ def batched_rate(ks, plan, evks, mods, count, reps, np, torch, synth):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
         cur = {"ciphertexts_per_call": count, "calls": reps, "ks_per_s": round(count * reps / (ms / 1e3), 1),
-               "ms_per_call": round(ms / reps, 4), "tile_towers": tt}
+               "ms_per_call": round(ms / reps, 4), "tile_towers": tt, "batch_mode": mode}
+        table[f"t{tt}/m{mode}"] = cur["ks_per_s"]
         if best is None or cur["ks_per_s"] > best["ks_per_s"]:
             best = cur
         del ws
-    plan.configure("oc")
+    plan.configure("oc", tile_towers=1, batch_mode=1)
+    best["configs"] = table
     return best
 
 
@@ -129,9 +131,9 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
     outs = [torch.empty((2, l + 1, n), dtype=torch.int32, device="cuda") for l in levels]
     jobs = [(evk, l, x, o) for l, x, o in zip(levels, ins, outs)]
     res = {}
-    for name, sched, batched, tt in (("oc_batched", "oc", True, 1), ("oc_batched", "oc", True, 2),
-                                     ("mp_one_at_a_time", "mp", False, 1)):
-        plan.configure(sched, tile_towers=tt)
+    for name, sched, batched, tt, mode in (("oc_batched", "oc", True, 1, 1), ("oc_batched", "oc", True, 2, 1),
+                                           ("oc_batched", "oc", True, 2, 3), ("mp_one_at_a_time", "mp", False, 1, 1)):
+        plan.configure(sched, tile_towers=tt, batch_mode=mode)
         ws = plan.workspace(levels if batched else [max(levels)])
 
         def once():
@@ -148,7 +150,10 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
             once()
         b.record()
         torch.cuda.synchronize()
-        res[name] = max(res.get(name, 0.0), round(64 * reps / (a.elapsed_time(b) / 1e3), 1))
+        rate = round(64 * reps / (a.elapsed_time(b) / 1e3), 1)
+        res[name] = max(res.get(name, 0.0), rate)
+        if batched:
+            res.setdefault("oc_configs", {})[f"t{tt}/m{mode}"] = rate
     plan.close()
     return res
 

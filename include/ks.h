@@ -82,7 +82,10 @@ typedef struct {
   uint32_t row_block;    /* MP/DC: rows per row-pass workgroup (4, 8, 16) */
   uint32_t batch_mode;   /* OC batches: 1 = one launch per phase over all jobs,
                             2 = one persistent work-queue launch (currently
-                            switched off: KS_ERR_UNSUPPORTED) */
+                            switched off: KS_ERR_UNSUPPORTED), 3 = as 1 but
+                            the second half of the jobs on a second stream
+                            owned by the plan (forked from and joined back
+                            to `stream` with events) */
   uint32_t graph;        /* batches: 1 = capture the launches in a hipGraph and
                             replay it (currently switched off:
                             KS_ERR_UNSUPPORTED), 2 = launch directly */

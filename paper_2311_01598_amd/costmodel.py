@@ -1,4 +1,4 @@
-"""Learned cost model of the autotuner: an fp32 MLP (13 features -> 64 -> 64
+"""Learned cost model of the autotuner: an fp32 MLP (14 features -> 64 -> 64
 -> 1, ReLU) that predicts log(milliseconds per key switch) of a
 configuration, trained on the GPU by the library's own kernels
 (ks_mlp_forward / ks_mlp_mse_grad / ks_mlp_backward / ks_mlp_adam).
@@ -14,7 +14,7 @@ import numpy as np
 from . import tune
 
 FEATURES = ("log_n", "towers", "dnum", "alpha", "num_p", "ndig", "log2_count", "is_mp", "is_dc", "is_oc",
-            "tile_towers", "log2_col", "log2_row")
+            "tile_towers", "log2_col", "log2_row", "split")
 HIDDEN = 64
 
 
@@ -24,7 +24,8 @@ def features(log_n, num_q, dnum, num_p, level, count, cfg):
     ndig = -(-towers // alpha)
     s = cfg["schedule"]
     return [log_n, towers, dnum, alpha, num_p, ndig, math.log2(count), s == "mp", s == "dc", s == "oc",
-            cfg["tile_towers"], math.log2(cfg["col_width"]), math.log2(cfg["row_block"])]
+            cfg["tile_towers"], math.log2(cfg["col_width"]), math.log2(cfg["row_block"]),
+            cfg.get("batch_mode", 1) == 3]
 
 
 def record_features(r):
@@ -145,7 +146,7 @@ def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
     hist = model.fit(Xtr, ytr, steps=steps, log_every=max(1, steps // 10))
     reg_pick, reg_pruned, reg_rand, reg_default = [], [], [], []
     per = []
-    default = tune.config_key({"schedule": "oc", "tile_towers": 1, "col_width": 16, "row_block": 8})
+    default = tune.config_key({"schedule": "oc", "tile_towers": 1, "col_width": 16, "row_block": 8, "batch_mode": 1})
     for k, times in groups.items():
         if k[:4] not in test_pts or len(times) < len(cfgs):
             continue

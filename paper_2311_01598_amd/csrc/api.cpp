@@ -207,12 +207,27 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
     return dev_err(launch_oc_persistent(pl, djobs, (const OcSeg *)(ws + lay.segs), count * OC_NPHASE, total, count,
                                         (uint32_t *)(ws + lay.ctl), spin, st));
   const OcJob none{};
-  return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, st));
+  if (mode != 3 || count < 2) return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, st));
+  // Mode 3: the batch runs as two halves, the second on the plan's side stream:
+  // the halves drift apart, so a bandwidth-bound phase of one overlaps a
+  // compute-bound phase of the other.  (Each half launches with the batch's
+  // largest tile counts; tiles past a job's own count return at once.)
+  std::lock_guard<std::mutex> g(pl.fork.mu);
+  Fork *f = nullptr;
+  TRY(fork_get(pl, &f));
+  TRY(hipEventRecord(f->fork, st));
+  TRY(hipStreamWaitEvent(f->side, f->fork, 0));
+  const uint32_t h = count / 2;
+  TRY(launch_oc_phases(pl, none, djobs, h, max_tiles.data(), tt, st));
+  TRY(launch_oc_phases(pl, none, djobs + h, count - h, max_tiles.data(), tt, f->side));
+  TRY(hipEventRecord(f->join, f->side));
+  TRY(hipStreamWaitEvent(st, f->join, 0));
+  return KS_OK;
 }
 
 ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const BatchLayout &lay, char *ws,
                          hipStream_t st) {
-  const uint32_t mode = pl.cfg.batch_mode == 2 ? 2 : 1;
+  const uint32_t mode = pl.cfg.batch_mode;
   const uint32_t tt = mode == 2 ? 1 : oc_tt(pl);
   const uint32_t spin = pl.cfg.spin_limit ? pl.cfg.spin_limit : (1u << 20);
   // host tables
@@ -398,7 +413,7 @@ ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
     return false;
   };
   if (!ok(cfg->tile_towers, {1, 2, 4}) || !ok(cfg->col_width, {8, 16, 32}) || !ok(cfg->row_block, {4, 8, 16}) ||
-      !ok(cfg->batch_mode, {1, 2}) || !ok(cfg->graph, {1, 2}))
+      !ok(cfg->batch_mode, {1, 2, 3}) || !ok(cfg->graph, {1, 2}))
     return KS_ERR_INVALID_ARG;
   // The persistent work-queue launch and graph capture of batches are
   // switched off: a batch run through them stopped making progress on the

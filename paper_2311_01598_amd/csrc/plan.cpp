@@ -264,6 +264,30 @@ void plan_free(Plan *pl) {
     (void)hipHostFree(s.host);
   }
   pl->staging.slots.clear();
+  std::lock_guard<std::mutex> g3(pl->fork.mu);
+  if (pl->fork.side) {
+    (void)hipStreamSynchronize(pl->fork.side);
+    (void)hipStreamDestroy(pl->fork.side);
+  }
+  if (pl->fork.fork) (void)hipEventDestroy(pl->fork.fork);
+  if (pl->fork.join) (void)hipEventDestroy(pl->fork.join);
+  pl->fork.side = nullptr;
+  pl->fork.fork = pl->fork.join = nullptr;
+}
+
+hipError_t fork_get(const Plan &pl, Fork **f) {
+  Fork &k = pl.fork;
+  if (!k.side) {
+    const hipError_t e = hipStreamCreateWithFlags(&k.side, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      k.side = nullptr;
+      return e;
+    }
+  }
+  if (!k.fork && hipEventCreateWithFlags(&k.fork, hipEventDisableTiming) != hipSuccess) return hipErrorUnknown;
+  if (!k.join && hipEventCreateWithFlags(&k.join, hipEventDisableTiming) != hipSuccess) return hipErrorUnknown;
+  *f = &k;
+  return hipSuccess;
 }
 
 hipError_t upload_async(const Plan &pl, void *dst, const void *src, size_t bytes, hipStream_t st) {

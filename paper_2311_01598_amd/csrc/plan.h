@@ -75,6 +75,17 @@ struct Staging {
   std::vector<StagingSlot> slots;
 };
 
+// A second stream (default priority) for work that may overlap the caller's
+// stream inside one call: `fork` is recorded on the caller's stream and
+// waited for by the side stream, `join` the other way round.  Created on
+// first use; `mu` is held while a call enqueues its fork ... join sequence,
+// so calls from several threads or streams stay correctly ordered.
+struct Fork {
+  std::mutex mu;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct Plan {
   uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
   int device = -1;
@@ -87,7 +98,12 @@ struct Plan {
   void *graph_cache = nullptr;
   mutable Trace trace;
   mutable Staging staging;
+  mutable Fork fork;
 };
+
+// The plan's side stream and events, created on first use (caller holds
+// pl.fork.mu).
+hipError_t fork_get(const Plan &pl, Fork **f);
 
 // Asynchronous host-to-device copy of `bytes` from `src` through a pinned
 // staging slot (src may be freed as soon as this returns).

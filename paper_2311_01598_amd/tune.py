@@ -26,19 +26,27 @@ SCHEDULES = ("mp", "dc", "oc")
 
 
 def config_space():
-    """Every configuration the tuner considers (20)."""
+    """Every configuration the tuner considers (21): MP and DC with 3 x 3
+    tile shapes, OC with 1 or 2 targets per conversion tile and, for
+    batches, the two-stream split (batch mode 3)."""
     out = []
     for cw, rb in itertools.product((8, 16, 32), (4, 8, 16)):
         out.append({"schedule": "mp", "tile_towers": 1, "col_width": cw, "row_block": rb})
     for cw, rb in itertools.product((8, 16, 32), (4, 8, 16)):
         out.append({"schedule": "dc", "tile_towers": 1, "col_width": cw, "row_block": rb})
-    for tt in (1, 2):
-        out.append({"schedule": "oc", "tile_towers": tt, "col_width": 16, "row_block": 8})
+    for tt, mode in ((1, 1), (2, 1), (2, 3)):
+        out.append({"schedule": "oc", "tile_towers": tt, "col_width": 16, "row_block": 8, "batch_mode": mode})
     return out
 
 
 def config_key(c):
-    return f"{c['schedule']}/t{c['tile_towers']}/c{c['col_width']}/r{c['row_block']}"
+    k = f"{c['schedule']}/t{c['tile_towers']}/c{c['col_width']}/r{c['row_block']}"
+    return k + "/m3" if c.get("batch_mode", 1) == 3 else k
+
+
+def apply_config(plan, c):
+    plan.configure(c["schedule"], tile_towers=c["tile_towers"], col_width=c["col_width"], row_block=c["row_block"],
+                   batch_mode=c.get("batch_mode", 1))
 
 
 class Workload:
@@ -67,8 +75,7 @@ def time_config(work, cfg, reps=5):
     """Median milliseconds per key switch of `work` under configuration `cfg`."""
     import torch
     plan = work.plan
-    plan.configure(cfg["schedule"], tile_towers=cfg["tile_towers"], col_width=cfg["col_width"],
-                   row_block=cfg["row_block"])
+    apply_config(plan, cfg)
     ws = plan.workspace([work.level] * work.count)
     work.run(ws)
     torch.cuda.synchronize()
@@ -128,8 +135,7 @@ def tune(plan, level, count=1, cache=None, device="gpu0", reps=5):
         cfg, _ = exhaustive(Workload(plan, level, count), reps)
         if cache:
             cache.put(device, params, level, count, cfg)
-    plan.configure(cfg["schedule"], tile_towers=cfg["tile_towers"], col_width=cfg["col_width"],
-                   row_block=cfg["row_block"])
+    apply_config(plan, cfg)
     return cfg
 
 

@@ -6,7 +6,7 @@
 * Exhaustive tuning picks the fastest measured configuration and the tune
   cache returns it.
 * On real timings of small workloads, the trained network's top-3 pruned
-  search has lower regret than timing 3 random configurations, at 3 of 20
+  search has lower regret than timing 3 random configurations, at 3 of 21
   timings per workload.
 """
 import numpy as np
@@ -73,7 +73,7 @@ def test_mlp_kernels_match_oracle(ks, F, H, B):
 def test_training_fits_a_smooth_function(ks):
     from paper_2311_01598_amd import costmodel
     rng = np.random.default_rng(3)
-    X = rng.uniform(-1, 1, (512, 13))
+    X = rng.uniform(-1, 1, (512, len(costmodel.FEATURES)))
     y = np.sin(2 * X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.3 * X[:, 7]
     m = costmodel.CostModel(seed=1)
     hist = m.fit(X, y, steps=1500, lr=3e-3, log_every=500)

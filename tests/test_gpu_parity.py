@@ -225,14 +225,15 @@ SWITCHED_OFF = ("persistent launch and graph capture are switched off: a batch t
 
 
 @pytest.mark.parametrize("mode,graph,tile", [
-    (1, 2, 1), (1, 2, 2),
+    (1, 2, 1), (1, 2, 2), (3, 2, 1), (3, 2, 2),
     pytest.param(1, 1, 1, marks=pytest.mark.skip(reason=SWITCHED_OFF)),
     pytest.param(1, 1, 2, marks=pytest.mark.skip(reason=SWITCHED_OFF)),
     pytest.param(2, 2, 1, marks=pytest.mark.skip(reason=SWITCHED_OFF)),
     pytest.param(2, 1, 1, marks=pytest.mark.skip(reason=SWITCHED_OFF))])
 def test_oc_batch_modes_and_graph_replays(ks, small_batch, mode, graph, tile):
-    """OC batch as one launch per phase (mode 1) or one persistent work-queue
-    launch (mode 2), launched directly (graph 2) or captured once and
+    """OC batch as one launch per phase (mode 1), the same split over two
+    streams (mode 3) or one persistent work-queue launch (mode 2), launched
+    directly (graph 2) or captured once and
     replayed (graph 1): every replay, with eager work between replays, must
     equal the oracle for every job (two different keys, mixed levels)."""
     p, mods, evks, levels, ins, want = small_batch
@@ -281,7 +282,8 @@ def test_persistent_spin_limit_flags_error_and_recovers(ks, small_batch):
     plan.close()
 
 
-def test_batch_64_mixed_levels_n16(ks):
+@pytest.mark.parametrize("mode,tile", [(1, 1), (3, 2)])
+def test_batch_64_mixed_levels_n16(ks, mode, tile):
     """64 ciphertexts at levels with l+1 uniform in [8, 24], N=2^16, dnum 3,
     one shared key: every job of the batch (one launch per phase over all
     jobs) equals the same job switched alone, and sampled jobs equal the
@@ -290,12 +292,12 @@ def test_batch_64_mixed_levels_n16(ks):
     mods = oracle.moduli(p)
     evk = synth.uniform_evk(mods, 3, p.n, synth.seed_for(3, 0))
     levels = synth.batch_levels(64, 8, 24, synth.seed_for(3, 1))
-    plan = ks.Plan(16, 24, 3, 8, schedule="oc", batch_mode=1)
+    plan = ks.Plan(16, 24, 3, 8, schedule="oc", batch_mode=mode, tile_towers=tile)
     evk_d = dev(evk)
     ins = [synth.uniform_limbs(mods[:l + 1], p.n, synth.seed_for(3, 10 + i)) for i, l in enumerate(levels)]
     ins_d = [dev(x) for x in ins]
     outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in levels]
-    say("[batch64] phases")
+    say(f"[batch64] mode={mode} tile={tile}")
     plan.keyswitch_batch([(evk_d, l, x, o) for l, x, o in zip(levels, ins_d, outs)])
     torch.cuda.synchronize()
     ws1 = plan.workspace([max(levels)])
