@@ -172,4 +172,4 @@ def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
         "timings_per_workload": {"exhaustive": len(cfgs), "pruned": top_m},
         "final_train_loss": hist[-1][1] if hist else None,
     }
-    return {"summary": summary, "loss_history": hist, "per_workload": per}
+    return {"summary": summary, "features": list(FEATURES), "loss_history": hist, "per_workload": per}

@@ -11,6 +11,7 @@ warm-up) and is the fallback and the judge of the cost-model-pruned search
 Command line (on a GPU machine):
     python -m paper_2311_01598_amd.tune collect --out timings.jsonl [--quick]
     python -m paper_2311_01598_amd.tune experiment --db timings.jsonl --out result.json
+    python -m paper_2311_01598_amd.tune report --db timings.jsonl --exp result.json --out summary.md
 """
 import argparse
 import itertools
@@ -194,6 +195,42 @@ def group_workloads(rows):
     return out
 
 
+def report(rows, exp, commands=()):
+    """Markdown summary of a timing database and a cost-model experiment."""
+    import collections
+    s = exp["summary"]
+    g = group_workloads(rows)
+    best = collections.Counter(min(t, key=t.get) for t in g.values())
+    sp = []
+    for t in g.values():
+        mp = [v for k, v in t.items() if k.startswith("mp")]
+        oc = [v for k, v in t.items() if k.startswith("oc")]
+        if mp and oc:
+            sp.append(min(mp) / min(oc))
+    sp = np.array(sp)
+    f = lambda d: f"mean {100 * d['mean']:.2f} %, p90 {100 * d['p90']:.2f} %, max {100 * d['max']:.2f} %"
+    lines = ["# Autotuner timing database and cost-model regret (N = 2^14..2^17, up to 48 towers)", "",
+             "Commands (one GPU, MI355X):", ""] + ["    " + c for c in commands] + [
+        "", f"Database: {len(rows)} timings = {len(g)} workloads x {s['configs']} configurations; log N in 14..17,",
+        "towers in {8,16,24,32,40,48}, dnum in {1,2,3,4,6} (alpha <= 32), two levels per point, 1 or 4",
+        "ciphertexts per call; median of 3 timed runs after one warm-up.", "",
+        f"Cost model: fp32 MLP {len(exp.get('features', [])) or 14} -> 64 -> 64 -> 1 (ReLU), target log(ms), trained on the",
+        "GPU by ks_mlp_forward / ks_mlp_mse_grad / ks_mlp_backward / ks_mlp_adam (full batch, Adam).",
+        f"Split by parameter point: {s['train_records']} training timings, {s['test_workloads']} held-out workloads;",
+        f"final standardised training loss {s['final_train_loss']:.2e}.", "",
+        "Top-1 regret on the held-out workloads (time of the chosen configuration / exhaustive best - 1):", "",
+        "| method | timings per workload | regret |", "|---|---|---|",
+        f"| exhaustive search (judge) | {s['configs']} | 0 |",
+        f"| model pick (no timing) | 0 | {f(s['regret_model_pick'])} |",
+        f"| model top-{s['top_m']}, timed | {s['top_m']} | {f(s['regret_pruned_top_m'])} |",
+        f"| {s['top_m']} random configurations, timed | {s['top_m']} | {f(s['regret_random_top_m'])} |",
+        f"| fixed default (oc/t1) | 0 | {f(s['regret_fixed_default'])} |", "",
+        f"Best configuration per workload over the whole database: {dict(best)}.",
+        f"Best OC over best MP configuration, per workload: median {np.median(sp):.2f}x, "
+        f"min {sp.min():.2f}x, max {sp.max():.2f}x."]
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -206,9 +243,20 @@ def main(argv=None):
     e.add_argument("--out", required=True)
     e.add_argument("--top", type=int, default=3)
     e.add_argument("--seed", type=int, default=0)
+    r = sub.add_parser("report")
+    r.add_argument("--db", required=True)
+    r.add_argument("--exp", required=True)
+    r.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
         collect(a.out, a.quick, a.reps)
+    elif a.cmd == "report":
+        cmds = ("python3 -u -m paper_2311_01598_amd.tune collect --out gpurun_out/timings.jsonl --reps 3",
+                "python3 -u -m paper_2311_01598_amd.tune experiment --db gpurun_out/timings.jsonl "
+                "--out gpurun_out/costmodel_experiment.json",
+                "python3 -m paper_2311_01598_amd.tune report --db gpurun_out/timings.jsonl "
+                "--exp gpurun_out/costmodel_experiment.json --out profiles/costmodel_regret_n14-17.md")
+        open(a.out, "w").write(report(load_db(a.db), json.load(open(a.exp)), cmds))
     else:
         from . import costmodel
         res = costmodel.experiment(load_db(a.db), top_m=a.top, seed=a.seed)
