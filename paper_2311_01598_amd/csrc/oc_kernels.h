@@ -7,17 +7,17 @@
 // K special towers.  A 2^16-point transform does not fit one CU, so a
 // tower's transform is split into a column pass and a row pass (see
 // ntt_engine.h) and the unit of work is a tile: an output tower (or a few)
-// times a column block, or a tower times a block of 16 rows.  Phases, in the
-// order they are issued:
+// times a column block, or a tower times a block of rows.  Phases, in
+// dependency order:
 //
 //   INTT_ROW    inverse row pass of the input towers              ModUp P1
 //   INTT_COL    inverse column pass + per-source constant         ModUp P1
 //   UP_P        per (digit, special target, column block): basis
 //               conversion fused with the forward column pass     ModUp P2, P3
+//   UP_Q        as UP_P for the Q targets outside each digit      ModUp P2, P3
 //   ROW_P       per (special tower, row block): forward row pass of
 //               every digit, key multiply-accumulate in registers,
 //               inverse row pass of both accumulators             P3-P5, ModDown P1
-//   UP_Q        as UP_P for the Q targets outside each digit      ModUp P2, P3
 //   INTT_COL_DN inverse column pass of the 2K special towers       ModDown P1
 //   DN          per (poly, Q target, column block): conversion
 //               P -> q_i fused with the forward column pass       ModDown P2, P3
@@ -26,11 +26,13 @@
 //               multiply-accumulate, forward row pass of the
 //               ModDown term, (acc - w) * P^-1                    P3-P5, ModDown P3-P4
 //
-// The special towers go first (the paper's Section 2) so that every Q tower
-// finishes ModUp and ModDown in one tile and its accumulator never leaves
-// registers.  Every tile is one 256-thread workgroup; the same tile bodies
-// serve one launch per phase (single key switch or a batch, job index in
-// grid z) and the persistent work-queue kernel of oc_persist.h.
+// UP_P and UP_Q depend only on INTT_COL and are issued as one launch
+// (OC_UP_PQ, special targets first).  The special towers go first (the
+// paper's Section 2) so that every Q tower finishes ModUp and ModDown in one
+// tile and its accumulator never leaves registers.  Every tile is one
+// 256-thread workgroup; the same tile bodies serve one launch per phase
+// (single key switch or a batch, job index in grid z) and the persistent
+// work-queue kernel of oc_persist.h (switched off).
 #pragma once
 #include "kernels.h"
 #include "ntt_engine.h"
