@@ -44,6 +44,18 @@ __device__ __forceinline__ uint4 ldg4(const void *p) {
   const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// Uniform reads of read-only plan tables through the scalar data cache (the
+// constant address space): the value lands in SGPRs instead of occupying a
+// VGPR in every lane.  Only for addresses that are the same across the wave
+// and tables that no kernel writes.
+#define KS_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ uint32_t ldc(const uint32_t *p) { return *(const KS_CONST uint32_t *)p; }
+__device__ __forceinline__ uint2 ldc2(const uint2 *p) {
+  const KS_CONST uint32_t *w = (const KS_CONST uint32_t *)p;
+  return make_uint2(w[0], w[1]);
+}
+__device__ __forceinline__ double ldcd(const double *p) { return *(const KS_CONST double *)p; }
+
 // Raw buffer access: one 128-bit resource (base, size in bytes) in SGPRs, a
 // per-thread byte offset in a VGPR and a uniform byte offset in an SGPR, so
 // a strided walk over a limb costs no vector address arithmetic.  Accesses
@@ -91,6 +103,12 @@ __device__ __forceinline__ uint32_t shoup_companion(uint32_t w, uint32_t q, doub
   r = t < 0 ? r - 1u : r;
   r = t >= (int32_t)q ? r + 1u : r;
   return r;
+}
+__device__ __forceinline__ ModQ ldmodc(const ModQ *p) {  // uniform address (see ldc)
+  const KS_CONST uint32_t *w = (const KS_CONST uint32_t *)p;
+  ModQ m;
+  m.q = w[0]; m.qinv = w[1]; m.mu = w[2]; m.pad = w[3];
+  return m;
 }
 __device__ __forceinline__ ModQ ldmod(const ModQ *p) {
   const ks_v4u v = *(const KS_GLOBAL ks_v4u *)p;

@@ -161,7 +161,7 @@ __device__ __forceinline__ void tile_intt_row(const DevPlan &P, const OcJob &J, 
   load_row_tw(tw, P.tw_inv + (size_t)i * N, tig, M);
   uint32_t x[16];
   load16(x, J.d + roff + 16 * tig);
-  row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, ldmod(P.mods + i).q);
+  row_inv(x, J.xt + roff, lds + rr * kPad, tig, tw, ldmodc(P.mods + i).q);
 }
 
 // Column passes (node 1) use only the first 2^A entries of a modulus'
@@ -205,20 +205,20 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
   if (!down) {
     const uint32_t j = li / P.alpha, lo = j * P.alpha, s = min(lo + P.alpha, J.level + 1) - lo;
     g = li;
-    pre = ldg2(P.up_pre + ((size_t)j * P.alpha + (s - 1)) * P.alpha + (li - lo));
+    pre = ldc2(P.up_pre + ((size_t)j * P.alpha + (s - 1)) * P.alpha + (li - lo));
     col = J.xt + (size_t)li * N + c0;
   } else {
     const uint32_t k = li % P.num_p;
     g = P.num_q + k;
-    pre = ldg2(P.dn_pre + k);
+    pre = ldc2(P.dn_pre + k);
     col = J.zp + (size_t)li * N + c0;
   }
-  const uint32_t q = ldmod(P.mods + g).q;
+  const uint32_t q = ldmodc(P.mods + g).q;
   const int w = threadIdx.x % W, tig = threadIdx.x / W;
   // twiddles first (staged in LDS after the data region), then the data
   ColTw<A> ct;
   ct.issue(P.tw_inv32 + (size_t)g * N);
-  const double qr = gp(P.qrecip)[g];
+  const double qr = ldcd(P.qrecip + g);
   uint2 *twl = reinterpret_cast<uint2 *>(lds + G::LDS);
   const LdsTw tw{twl};
   // the limb (col - c0) as a buffer: byte offset (row * 256 + c0 + w) * 4
@@ -278,7 +278,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
   using Ph1 = Phase<A, 1, R1>;
   ModQ mq[TT];
 #pragma unroll
-  for (int e = 0; e < TT; e++) mq[e] = ldmod(P.mods + tg[e]);
+  for (int e = 0; e < TT; e++) mq[e] = ldmodc(P.mods + tg[e]);
   // the targets' column twiddles, staged in LDS after the data regions once
   // the conversion is done
   ColTw<A> ct[TT];
@@ -286,7 +286,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
   for (int e = 0; e < TT; e++) {
     ct[e].issue(P.tw_fwd32 + (size_t)tg[e] * N);
-    qr[e] = gp(P.qrecip)[tg[e]];
+    qr[e] = ldcd(P.qrecip + tg[e]);
   }
   uint2 *twl = reinterpret_cast<uint2 *>(lds + TT * G::LDS);
   uint32_t y[TT][E];
@@ -312,27 +312,23 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     for (int e = 0; e < TT; e++)
 #pragma unroll
       for (int u = 0; u < E; u++) acc[e][u] = 0;
-    // Two register buffers in ping-pong, unrolled by two so that no buffer
-    // is copied (a copy would wait for the load in flight).  Loads past the
-    // end re-read the last source and the odd tail multiplies by a zero
-    // constant, so the loop body has no branch and each wait covers exactly
-    // the buffer about to be used.
-    auto macc = [&](const uint32_t (&xv)[E], uint32_t i, bool live) {
+    // One register buffer per source: prefetching the next source into a
+    // second buffer was measured no faster, and the lower register count
+    // (71 instead of 103 VGPRs with one target) lets 7 waves share a SIMD,
+    // which hides the load latency instead.
+    auto macc = [&](const uint32_t (&xv)[E], uint32_t i) {
       uint32_t c[TT];
 #pragma unroll
-      for (int e = 0; e < TT; e++) c[e] = live ? gp(cbase)[(size_t)i * cstride + tcol[e]] : 0u;
+      for (int e = 0; e < TT; e++) c[e] = ldc(cbase + (size_t)i * cstride + tcol[e]);
 #pragma unroll
       for (int u = 0; u < E; u++)
 #pragma unroll
         for (int e = 0; e < TT; e++) acc[e][u] = mad64(xv[u], c[e], acc[e][u]);
     };
-    uint32_t xa[E], xb[E];
-    load_src(xa, i0);
-    for (uint32_t i = i0; i < i1; i += 2) {
-      load_src(xb, min(i + 1, i1 - 1));
-      macc(xa, i, true);
-      load_src(xa, min(i + 2, i1 - 1));
-      macc(xb, i + 1, i + 1 < i1);
+    uint32_t xa[E];
+    for (uint32_t i = i0; i < i1; i++) {
+      load_src(xa, i);
+      macc(xa, i);
     }
 #pragma unroll
     for (int e = 0; e < TT; e++)
@@ -587,7 +583,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const uint32_t rbk = (1u << P.loga) / kRB4, unit = tile / rbk, blk = tile % rbk;
   const uint32_t t = IS_P ? L1 + unit : unit;
   const uint32_t g = oc_gidx(P.num_q, level, t);
-  const ModQ m = ldmod(P.mods + g);
+  const ModQ m = ldmodc(P.mods + g);
   const uint32_t q = m.q;
   const int r = threadIdx.x >> 6, slot = (threadIdx.x >> 4) & 3, tig = threadIdx.x & 15;
   const int k0 = 4 * (threadIdx.x & 63);  // element-wise part: words k0..k0+3 of the row
@@ -641,7 +637,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // first round's key words.
   uint32_t tw4[kRB4 * kRowTw / kOcThreads];
   row_tw_issue(tw4, P.tw_fwd32 + (size_t)g * N, m0);
-  const double qr = gp(P.qrecip)[g];
+  const double qr = ldcd(P.qrecip + g);
   uint32_t x[16];
   load_src(x, 0);
   uint32_t yo[4], eo0[4], eo1[4];
@@ -727,7 +723,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       for (int u = 0; u < 16; u++) gp(dst)[tig + 16 * u] = x[u];
     }
   } else {
-    const uint2 f = ldg2(P.dn_fin + t);
+    const uint2 f = ldc2(P.dn_fin + t);
     uint32_t o0[4], o1[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) {
@@ -807,9 +803,10 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   constexpr bool COL = PHASE != OC_INTT_ROW && PHASE != OC_ROW_P && PHASE != OC_ROW_Q;
   if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
-    if (blockIdx.x < np) tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(blockIdx.x), true, J.ttu, lds);
-    else if (blockIdx.x - np < J.tiles[OC_UP_Q])
-      tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(blockIdx.x - np), false, J.ttu, lds);
+    const bool special = blockIdx.x < np;
+    const uint32_t b = special ? blockIdx.x : blockIdx.x - np;
+    if (!special && b >= J.tiles[OC_UP_Q]) return;
+    tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(b), special, J.ttu, lds);
   } else {
     if (blockIdx.x >= J.tiles[PHASE]) return;
     const uint32_t tile = COL ? xcd_col_tile<ColGeom<A>::CB>(blockIdx.x) : blockIdx.x;
