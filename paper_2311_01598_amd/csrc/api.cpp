@@ -507,11 +507,14 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
     ks_status_t st = check_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, workspace,
                                workspace_bytes, need);
     if (st != KS_OK) return st;
+    // no job's output may overlap another job's output or input (either order)
     const size_t ob = 2 * (size_t)(jobs[i].level + 1) * limb_bytes(pl);
+    const size_t ib = (size_t)(jobs[i].level + 1) * limb_bytes(pl);
     for (uint32_t k = 0; k < i; k++) {
       const size_t okb = 2 * (size_t)(jobs[k].level + 1) * limb_bytes(pl);
       const size_t ikb = (size_t)(jobs[k].level + 1) * limb_bytes(pl);
-      if (overlaps(jobs[i].out, ob, jobs[k].out, okb) || overlaps(jobs[i].out, ob, jobs[k].in, ikb))
+      if (overlaps(jobs[i].out, ob, jobs[k].out, okb) || overlaps(jobs[i].out, ob, jobs[k].in, ikb) ||
+          overlaps(jobs[k].out, okb, jobs[i].in, ib))
         return KS_ERR_INVALID_ARG;
     }
   }

@@ -341,4 +341,16 @@ def test_error_paths(ks):
     with pytest.raises(ks.KsError) as e:
         ks.ks_plan_set_config(plan.handle, 9)
     assert e.value.status == ks.KS_ERR_INVALID_ARG
+    # batches: one job's output may not overlap another job's input, in
+    # either order, nor another job's output
+    plan.configure("oc")
+    d2 = torch.zeros((4, n), dtype=torch.int32, device="cuda")
+    big = torch.empty((4, 4, n), dtype=torch.int32, device="cuda")
+    wsb = plan.workspace([3, 3])
+    for jobs in ([(evk, 3, d, big[0:2]), (evk, 3, big[1], big[2:4])],      # out0 overlaps in1
+                 [(evk, 3, big[1], big[2:4]), (evk, 3, d, big[0:2])],      # out1 overlaps in0
+                 [(evk, 3, d, big[0:2]), (evk, 3, d2, big[1:3])]):         # out0 overlaps out1
+        with pytest.raises(ks.KsError) as e:
+            ks.ks_keyswitch_batch(plan.handle, jobs, wsb)
+        assert e.value.status == ks.KS_ERR_INVALID_ARG
     plan.close()
