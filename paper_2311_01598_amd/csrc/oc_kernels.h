@@ -647,6 +647,10 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
   }
   load_keys(0);
+  // ROW_P: the inverse twiddles of its ModDown P1 pass are loaded now, so
+  // that their latency overlaps the forward round instead of following it
+  uint32_t twi4[kRB4 * kRowTw / kOcThreads];
+  if (IS_P) row_tw_issue(twi4, P.tw_inv32 + (size_t)g * N, m0);
   row_tw_store(twl, tw4, q, qr, true);
   __syncthreads();
 
@@ -696,13 +700,12 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   if (IS_P) {
     // ModDown P1 for this special tower: inverse row transforms of both
     // accumulators by slots 0 and 1 (values canonical, < 2q as required)
-    row_tw_issue(tw4, P.tw_inv32 + (size_t)g * N, m0);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       row_buf(lds, 0, r)[rl(k0 + i)] = r0[i];
       row_buf(lds, 1, r)[rl(k0 + i)] = r1[i];
     }
-    row_tw_store(twl, tw4, q, qr, false);
+    row_tw_store(twl, twi4, q, qr, false);
     __syncthreads();
     uint32_t *lrow = row_buf(lds, slot & 1, r);
     const bool act = slot < 2;
