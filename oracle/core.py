@@ -47,6 +47,9 @@ def lib():
             "oracle_keyswitch": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, _U32P]),
             "oracle_keyswitch_oc": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, _U32P]),
             "oracle_keygen": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, _I8P, _I8P, _U32P]),
+            "oracle_keygen_seeded": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, ctypes.c_uint64, _I8P, _I8P, _U32P]),
+            "oracle_splitmix_at": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
+            "oracle_seeded_a": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, _U32P]),
             "oracle_set_fault": (None, [ctypes.c_int]),
             "oracle_evk_words": (ctypes.c_uint64, [ctypes.c_uint32] * 4),
         }
@@ -186,6 +189,35 @@ def keygen(p, mods, seed):
                             s2.ctypes.data_as(_I8P), evk.ctypes.data_as(_U32P))
     if h < 0:
         raise ValueError("oracle_keygen rejected its arguments")
+    return s, s2, evk, h
+
+
+def splitmix_at(seed, t):
+    """Output t of the counter-based SplitMix64 generator for `seed`."""
+    return int(lib().oracle_splitmix_at(int(seed) & (2**64 - 1), int(t)))
+
+
+def seeded_a(p, mods, a_seed):
+    """The a halves of a key compressed to `a_seed` (Sec. IV-D), returned as a
+    full-layout evk [dnum][2][L+1+K][N] whose b halves are zero."""
+    mods, mp_ = _u32(mods)
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint32)
+    if lib().oracle_seeded_a(ctypes.byref(p.c()), mp_, int(a_seed) & (2**64 - 1), evk.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("oracle_seeded_a rejected its arguments")
+    return evk
+
+
+def keygen_seeded(p, mods, seed, a_seed):
+    """keygen whose a halves are regenerated from `a_seed`: the b halves
+    evk[:, 0] plus a_seed are the whole key."""
+    mods, mp_ = _u32(mods)
+    s = np.zeros(p.n, np.int8)
+    s2 = np.zeros(p.n, np.int8)
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint32)
+    h = lib().oracle_keygen_seeded(ctypes.byref(p.c()), mp_, int(seed), int(a_seed) & (2**64 - 1),
+                                   s.ctypes.data_as(_I8P), s2.ctypes.data_as(_I8P), evk.ctypes.data_as(_U32P))
+    if h < 0:
+        raise ValueError("oracle_keygen_seeded rejected its arguments")
     return s, s2, evk, h
 
 

@@ -445,8 +445,53 @@ static int32_t rng_gauss(rng_t *r) { /* Box-Muller, sigma 3.2, clamp 19 */
 }
 static uint32_t signed_mod(int32_t v, uint32_t m) { return v >= 0 ? (uint32_t)v % m : m - ((uint32_t)(-v) % m); }
 
+/* Seeded key halves (key compression, Sec. IV-D): the a half of every evk
+ * pair comes from a counter-based generator instead of being stored.  The
+ * generator is SplitMix64 (Steele, Lea and Flood 2014) used at a counter:
+ * output t of seed s is the SplitMix64 output mix of s + (t + 1) * gamma.
+ * Word (j, g, k) of the a halves is a = x * 2^-32 mod m_g, x the output at
+ * t = (j * (L+1+K) + g) * N + k. */
+uint64_t oracle_splitmix_at(uint64_t seed, uint64_t t) {
+  uint64_t x = seed + t * 0x9e3779b97f4a7c15ull;
+  return splitmix64(&x);
+}
+
+int oracle_seeded_a(const oracle_params *p, const uint32_t *moduli, uint64_t a_seed, uint32_t *evk) {
+  if (!p || !moduli || !evk) return -1;
+  const uint32_t n = 1u << p->log_n;
+  const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum;
+  const uint32_t K = p->num_p ? p->num_p : alpha, EL = p->num_q + K;
+  for (uint32_t j = 0; j < p->dnum; j++)
+    for (uint32_t g = 0; g < EL; g++) {
+      /* evk order: q_0..q_L then p_0..p_{K-1}; moduli[] holds p's first */
+      const uint32_t m = g < p->num_q ? moduli[K + g] : moduli[g - p->num_q];
+      const uint32_t inv32 = oracle_invmod((uint32_t)((1ull << 32) % m), m);
+      uint32_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
+      for (uint32_t k = 0; k < n; k++) {
+        const uint64_t x = oracle_splitmix_at(a_seed, ((uint64_t)j * EL + g) * n + k);
+        a[k] = mulmod((uint32_t)(x % m), inv32, m);
+      }
+    }
+  return 0;
+}
+
+static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, uint64_t a_seed,
+                       int8_t *s, int8_t *s2, uint32_t *evk);
+
 int oracle_keygen(const oracle_params *p, const uint32_t *moduli, uint64_t seed,
                   int8_t *s, int8_t *s2, uint32_t *evk) {
+  return keygen_impl(p, moduli, seed, 0, 0, s, s2, evk);
+}
+
+int oracle_keygen_seeded(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint64_t a_seed,
+                         int8_t *s, int8_t *s2, uint32_t *evk) {
+  if (oracle_seeded_a(p, moduli, a_seed, evk) != 0) return -1;
+  return keygen_impl(p, moduli, seed, 1, a_seed, s, s2, evk);
+}
+
+static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, uint64_t a_seed,
+                       int8_t *s, int8_t *s2, uint32_t *evk) {
+  (void)a_seed;
   ks_ctx c;
   if (ctx_init(&c, p, moduli, p->num_q - 1) != 0) return -1;
   const uint32_t n = c.n, EL = c.L1 + c.K;
@@ -476,7 +521,7 @@ int oracle_keygen(const oracle_params *p, const uint32_t *moduli, uint64_t seed,
       uint32_t *b = evk + (((size_t)j * 2 + 0) * EL + g) * n;
       uint32_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
       for (uint32_t z = 0; z < n; z++) {
-        a[z] = rng_below(&r, m);
+        if (!seeded) a[z] = rng_below(&r, m); /* seeded: a already holds the generator's words */
         uint32_t v = submod(eh[z], mulmod(a[z], sh[z], m), m);
         b[z] = addmod(v, mulmod(gad, s2h[z], m), m);
       }

@@ -83,6 +83,20 @@ int oracle_keyswitch_oc(const oracle_params *p, const uint32_t *moduli, uint32_t
 int oracle_keygen(const oracle_params *p, const uint32_t *moduli, uint64_t seed,
                   int8_t *s, int8_t *s2, uint32_t *evk);
 
+/* Key compression (Sec. IV-D): a halves regenerated from a seed.
+ * oracle_splitmix_at: output t of the counter-based SplitMix64 generator
+ * (Steele, Lea and Flood 2014) for `seed`: the SplitMix64 mix of
+ * seed + (t + 1) * 0x9e3779b97f4a7c15.
+ * oracle_seeded_a: writes the a half of every pair of a full-layout evk,
+ * word (j, g, k) = x * 2^-32 mod m_g with x the output at
+ * t = (j * (L+1+K) + g) * N + k (g in evk order q_0..q_L, p_0..p_{K-1}).
+ * oracle_keygen_seeded: oracle_keygen with those a halves (the b halves
+ * computed from them), so the b halves plus a_seed are the whole key. */
+uint64_t oracle_splitmix_at(uint64_t seed, uint64_t t);
+int oracle_seeded_a(const oracle_params *p, const uint32_t *moduli, uint64_t a_seed, uint32_t *evk);
+int oracle_keygen_seeded(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint64_t a_seed,
+                         int8_t *s, int8_t *s2, uint32_t *evk);
+
 /* Test hook: plant a deliberate mistake in the oracle's key switch so tests
  * can show their checks catch it.  0 = none; see ks_oracle.c for the list. */
 void oracle_set_fault(int fault);
