@@ -463,8 +463,7 @@ int oracle_seeded_a(const oracle_params *p, const uint32_t *moduli, uint64_t a_s
   const uint32_t K = p->num_p ? p->num_p : alpha, EL = p->num_q + K;
   for (uint32_t j = 0; j < p->dnum; j++)
     for (uint32_t g = 0; g < EL; g++) {
-      /* evk order: q_0..q_L then p_0..p_{K-1}; moduli[] holds p's first */
-      const uint32_t m = g < p->num_q ? moduli[K + g] : moduli[g - p->num_q];
+      const uint32_t m = moduli[g]; /* moduli[] and the key rows share the order q_0..q_L, p_0..p_{K-1} */
       const uint32_t inv32 = oracle_invmod((uint32_t)((1ull << 32) % m), m);
       uint32_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
       for (uint32_t k = 0; k < n; k++) {

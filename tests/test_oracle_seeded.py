@@ -66,7 +66,7 @@ def test_seeded_a_words_follow_the_counter_layout():
     g = _Sequential(a_seed)  # counter order: j, then g, then k
     for j in range(p.dnum):
         for gi in range(EL):
-            m = int(mods[p.num_p + gi]) if gi < p.num_q else int(mods[gi - p.num_q])
+            m = int(mods[gi])  # key rows and moduli share one order: q_0..q_L, p_0..p_{K-1}
             a = ev[j, 1, gi].astype(np.int64)
             assert int(a.max()) < m
             for k in range(p.n):
@@ -80,7 +80,7 @@ def test_seeded_a_is_uniform():
     ev = core.seeded_a(p, mods, 77)
     EL = p.num_q + p.num_p
     for gi in range(EL):
-        m = int(mods[p.num_p + gi]) if gi < p.num_q else int(mods[gi - p.num_q])
+        m = int(mods[gi])
         for j in range(p.dnum):
             a = ev[j, 1, gi].astype(np.float64)
             counts = np.bincount((a * 16 / m).astype(np.int64), minlength=16)
@@ -98,6 +98,8 @@ def test_seeded_key_decrypts_within_bound(log_n, num_q, dnum, num_p, levels):
     mods = oracle.moduli(p)
     s, s2, evk, h = core.keygen_seeded(p, mods, seed=21, a_seed=0xabc)
     assert np.array_equal(evk[:, 1], core.seeded_a(p, mods, 0xabc)[:, 1])
+    for gi, m in enumerate(mods):  # every half canonical for its own row's modulus
+        assert int(evk[:, :, gi].max()) < int(m)
     _, _, evk_plain, _ = oracle.keygen(p, mods, seed=21)
     assert not np.array_equal(evk[:, 1], evk_plain[:, 1])
     rng = np.random.default_rng(3)
