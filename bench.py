@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # at the FP64 vector rate, 64 lanes per clock per CU: 256 CUs x 64 x 2.4 GHz.
 MUL_PEAK_PER_S = 256 * 64 * 2.4e9
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_oc_n16_l24_dnum3.json")
+SEED_MULS = 12  # multiplies per regenerated key word
 
 
 def alg_bytes(n, l1, k, ndig):
@@ -53,6 +54,11 @@ def stage_muls(log_n, l1, k, alpha):
         "oc.intt_col.down": 2 * k * (col_ntt + 3 * n),
         "oc.bconv_col.down": 2 * l1 * (n * (k + 4) + col_ntt),
         "oc.row.q": l1 * ((ndig - 1) * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt + 2 * 3 * n),
+        # compressed keys: each a-half word regenerated (two 64-bit products
+        # of the generator, 4 multiplies each, and one REDC)
+        "oc.row.p.seeded": k * (ndig * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt) + SEED_MULS * ndig * k * n,
+        "oc.row.q.seeded": l1 * ((ndig - 1) * row_ntt + 2 * ndig * n + 2 * 4 * n + 2 * row_ntt + 2 * 3 * n)
+                           + SEED_MULS * ndig * l1 * n,
     }
 
 
@@ -72,6 +78,8 @@ def stage_bytes(log_n, l1, k, alpha):
         "oc.intt_col.down": limb * 2 * 2 * k,                             # zp in place
         "oc.bconv_col.down": limb * (2 * k + 2 * l1),                     # zp in, wcol out
         "oc.row.q": limb * ((ndig - 1) * l1 + 2 * l1 + l1 + 2 * ndig * l1 + 2 * l1),  # ycol, wcol, d, key, out
+        "oc.row.p.seeded": limb * (ndig * k + ndig * k + 2 * k),          # b halves only
+        "oc.row.q.seeded": limb * ((ndig - 1) * l1 + 2 * l1 + l1 + ndig * l1 + 2 * l1),
     }
 
 
@@ -116,6 +124,65 @@ def batched_rate(ks, plan, evks, mods, count, reps, np, torch, synth):
     plan.configure("oc", tile_towers=1, batch_mode=1)
     best["configs"] = table
     return best
+
+
+def seeded_rate(ks, plan, evks, d, steps, warmup, count, np, torch, synth):
+    """Key compression (Sec. IV-D): the bench workload with compressed keys
+    (b halves, 24 MiB each, rotating like the full keys, plus a seed), one key
+    switch per call and `count` per batch call; per-stage times of the two
+    row stages that consume the key."""
+    n, l1 = plan.n, LEVEL + 1
+    keys = [e[:, 0].contiguous() for e in evks]
+    out = torch.empty((2, l1, n), dtype=torch.int32, device="cuda")
+    plan.configure("oc", tile_towers=1, batch_mode=1)
+    ws = plan.workspace([LEVEL])
+
+    def single(k):
+        for i in range(k):
+            plan.keyswitch_seeded(keys[i % len(keys)], 1000 + i % len(keys), LEVEL, d, out=out, workspace=ws)
+    single(warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    for i in range(steps):
+        ev[i].record()
+        plan.keyswitch_seeded(keys[i % len(keys)], 1000 + i % len(keys), LEVEL, d, out=out, workspace=ws)
+    ev[steps].record()
+    torch.cuda.synchronize()
+    lat = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    ms = ev[0].elapsed_time(ev[steps])
+    ks.ks_trace_enable(plan.handle, True)
+    single(steps)
+    ks.ks_trace_enable(plan.handle, False)
+    trace = ks.ks_trace_read(plan.handle)
+    sbytes = stage_bytes(LOG_N, l1, NUM_P, plan.alpha)
+    stages = {}
+    for k in ("oc.row.p.seeded", "oc.row.q.seeded"):
+        if k in trace:
+            t = 1e-3 * trace[k][1] / max(trace[k][0], 1)
+            stages[k] = {"avg_us": round(t * 1e6, 3), "hbm_frac": round(sbytes[k] / t / (HBM_PEAK_GBS * 1e9), 4)}
+    res = {"ks_per_s": round(steps / (ms / 1e3), 1), "p50_ms": round(lat[len(lat) // 2], 4),
+           "p99_ms": round(lat[min(len(lat) - 1, int(len(lat) * 0.99))], 4),
+           "key_bytes_per_ks": DNUM * (l1 + NUM_P) * n * 4, "stages": stages}
+    ins = [torch.from_numpy(synth.uniform_limbs(plan.moduli[:l1], n, synth.seed_for(2, 200 + i)).view(np.int32)).cuda()
+           for i in range(count)]
+    outs = [torch.empty((2, l1, n), dtype=torch.int32, device="cuda") for _ in range(count)]
+    reps = max(5, steps // 20)
+    for tt, mode in ((1, 1), (2, 1), (2, 3)):
+        plan.configure("oc", tile_towers=tt, batch_mode=mode)
+        wsb = plan.workspace([LEVEL] * count)
+        jobs = lambda r: [(keys[r % len(keys)], 1000 + r % len(keys), LEVEL, x, o) for x, o in zip(ins, outs)]
+        plan.keyswitch_batch_seeded(jobs(0), workspace=wsb)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for r in range(reps):
+            plan.keyswitch_batch_seeded(jobs(r), workspace=wsb)
+        b.record()
+        torch.cuda.synchronize()
+        res.setdefault("batched", {})[f"t{tt}/m{mode}"] = round(count * reps / (a.elapsed_time(b) / 1e3), 1)
+        del wsb
+    plan.configure("oc", tile_towers=1, batch_mode=1)
+    return res
 
 
 def mixed_rate(ks, dnum, reps, np, torch, synth):
@@ -230,6 +297,7 @@ def parse():
     ap.add_argument("--rates", action="store_true", help="also run the ALU / copy rate probes")
     ap.add_argument("--batch", type=int, default=16,
                     help="ciphertexts per call in the batched measurement of the same workload (0 = skip)")
+    ap.add_argument("--seeded", type=int, default=1, help="also time compressed keys (0: skip)")
     ap.add_argument("--mixed", action="store_true",
                     help="also time 64-ciphertext batches at levels l+1 ~ U[8,24] for dnum 2, 3, 4")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -355,14 +423,18 @@ def main():
                            "peak": round(MUL_PEAK_PER_S / 1e12, 4), "unit": "Tmul/s (32-bit integer multiplies)",
                            "frac": round(achieved / MUL_PEAK_PER_S, 4), "traffic": traffic,
                            "avg_us": round(dom_s * 1e6, 3), "muls_per_launch": muls[dom]}
-    tot_muls = sum(muls.values())
+    tot_muls = sum(v for k, v in muls.items() if not k.endswith(".seeded"))
+    tot_bytes = sum(v for k, v in sbytes.items() if not k.endswith(".seeded"))
     res["whole_keyswitch"] = {"muls": tot_muls, "mul_frac": round(tot_muls * ks_per_s / MUL_PEAK_PER_S, 4),
                               "hbm_frac": round(nbytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4),
-                              "stage_bytes": sum(sbytes.values()),
-                              "stage_bytes_frac": round(sum(sbytes.values()) * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
+                              "stage_bytes": tot_bytes,
+                              "stage_bytes_frac": round(tot_bytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
     res["stages"] = stages
     if args.batch:
         res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)
+    if args.seeded:
+        res["key_compression"] = seeded_rate(ks, plan, evks, d, args.steps, args.warmup, args.batch or 16, np,
+                                             torch, synth)
     if args.mixed:
         res["mixed_batches"] = {}
         for dn in (2, 3, 4):

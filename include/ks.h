@@ -151,6 +151,49 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs,
                                void *workspace, size_t workspace_bytes, void *stream);
 
+/* Key compression (Sec. IV-D, arithmetic-intensity comparison): the a half
+ * of every key pair is pseudo-random, so it can be regenerated from a seed
+ * where it is consumed instead of being read from memory, which halves the
+ * key traffic of a key switch.  A compressed key is its b halves
+ * evk_b [dnum][L+1+K][N] (device, the same order as the b halves of a full
+ * key) plus a_seed.  Word k of row g (g in key order q_0..q_L, p_0..p_{K-1})
+ * of digit j's a half is x * 2^-32 mod m_g, where x is output t =
+ * (j (L+1+K) + g) N + k of SplitMix64 (Steele, Lea and Flood 2014) used as a
+ * counter-based generator: x = mix(a_seed + (t + 1) * 0x9e3779b97f4a7c15),
+ * mix(z) = z ^= z >> 30, z *= 0xbf58476d1ce4e5b9, z ^= z >> 27,
+ * z *= 0x94d049bb133111eb, z ^= z >> 31 (64-bit arithmetic).  The a_seed
+ * is public, like the a halves it stands for.
+ *
+ * ks_keyswitch_seeded: ks_keyswitch with a compressed key; the result equals
+ * ks_keyswitch with the expanded key.  OC schedule only: another schedule
+ * returns KS_ERR_UNSUPPORTED (expand the key with ks_expand_seeded_a and
+ * call ks_keyswitch instead).  Same rules for alignment, overlap (evk_b
+ * counts as dnum (L+1+K) N words) and workspace as ks_keyswitch. */
+ks_status_t ks_keyswitch_seeded(ks_plan_t plan, const uint32_t *evk_b, uint64_t a_seed, uint32_t level,
+                                const uint32_t *in, uint32_t *out, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
+/* One job of a batch with a compressed key: evk_b [dnum][L+1+K][N] (device)
+ * and its seed; in/out as in ks_job_t. */
+typedef struct {
+  const uint32_t *evk_b;
+  uint64_t a_seed;
+  uint32_t level;
+  const uint32_t *in;
+  uint32_t *out;
+} ks_seeded_job_t;
+
+/* ks_keyswitch_batch with compressed keys (every job's); same rules, OC
+ * schedule only, KS_FAULT_INJECT counts these calls too. */
+ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_seeded_job_t *jobs,
+                                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Writes the a half of every pair of a full-layout key evk [dnum][2][L+1+K]
+ * [N] (device, 16-byte aligned) from a_seed as defined above, enqueued on
+ * `stream`; the b halves are not touched.  For key generation (b is
+ * computed from a) and for schedules that take full keys only. */
+ks_status_t ks_expand_seeded_a(ks_plan_t plan, uint64_t a_seed, uint32_t *evk, void *stream);
+
 /* After a batch: waits for `stream`, then sets *error_flag to 1 if a
  * dependency wait of the persistent launch exceeded its spin limit (the
  * outputs of that batch are then invalid), else 0. */

@@ -42,6 +42,11 @@ class ks_job_t(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class ks_seeded_job_t(ctypes.Structure):
+    _fields_ = [("evk_b", ctypes.c_void_p), ("a_seed", ctypes.c_uint64), ("level", ctypes.c_uint32),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 _U32P = ctypes.POINTER(ctypes.c_uint32)
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -56,6 +61,11 @@ _SIGS = {
     "ks_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
                                           _VP]),
+    "ks_keyswitch_seeded": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP,
+                                           ctypes.c_size_t, _VP]),
+    "ks_keyswitch_batch_seeded": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_seeded_job_t), _VP,
+                                                 ctypes.c_size_t, _VP]),
+    "ks_expand_seeded_a": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
     "ks_batch_status": (ctypes.c_int, [_VP, _VP, _VP, _U32P]),
     "ks_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
     "ks_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -216,6 +226,31 @@ def ks_keyswitch_batch(plan, jobs, workspace, workspace_bytes=None, stream=None)
     _check(st, "ks_keyswitch_batch")
 
 
+def ks_keyswitch_seeded(plan, evk_b, a_seed, level, inp, out, workspace, workspace_bytes=None, stream=None):
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    st = _lib.ks_keyswitch_seeded(plan, _ptr(evk_b), int(a_seed) & (2**64 - 1), int(level), _ptr(inp), _ptr(out),
+                                  _ptr(workspace), int(workspace_bytes), _stream(stream))
+    _check(st, "ks_keyswitch_seeded")
+
+
+def ks_keyswitch_batch_seeded(plan, jobs, workspace, workspace_bytes=None, stream=None):
+    """jobs: list of (evk_b, a_seed, level, in, out)."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_seeded_job_t * len(jobs))()
+    for i, (evk_b, a_seed, level, inp, out) in enumerate(jobs):
+        arr[i] = ks_seeded_job_t(_ptr(evk_b), int(a_seed) & (2**64 - 1), int(level), _ptr(inp), _ptr(out))
+    st = _lib.ks_keyswitch_batch_seeded(plan, len(jobs), arr, _ptr(workspace), int(workspace_bytes),
+                                        _stream(stream))
+    _check(st, "ks_keyswitch_batch_seeded")
+
+
+def ks_expand_seeded_a(plan, a_seed, evk, stream=None):
+    _check(_lib.ks_expand_seeded_a(plan, int(a_seed) & (2**64 - 1), _ptr(evk), _stream(stream)),
+           "ks_expand_seeded_a")
+
+
 def ks_ntt(plan, g, inverse, data, stream=None):
     arr = _u32_array(g)
     _check(_lib.ks_ntt(plan, len(g), arr, int(bool(inverse)), _ptr(data), _stream(stream)), "ks_ntt")
@@ -308,6 +343,25 @@ class Plan:
         if workspace is None:
             workspace = self.workspace([j[1] for j in jobs])
         ks_keyswitch_batch(self.handle, jobs, workspace, workspace_bytes, stream=stream)
+
+    def keyswitch_seeded(self, evk_b, a_seed, level, d, out=None, workspace=None, stream=None):
+        """Key switch with a compressed key: evk_b [dnum][L+1+K][N] plus the
+        seed of the a halves (Sec. IV-D)."""
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int32, device=d.device)
+        if workspace is None:
+            workspace = self.workspace([level], d.device)
+        ks_keyswitch_seeded(self.handle, evk_b, a_seed, level, d, out, workspace, stream=stream)
+        return out
+
+    def keyswitch_batch_seeded(self, jobs, workspace=None, stream=None, workspace_bytes=None):
+        if workspace is None:
+            workspace = self.workspace([j[2] for j in jobs])
+        ks_keyswitch_batch_seeded(self.handle, jobs, workspace, workspace_bytes, stream=stream)
+
+    def expand_seeded_a(self, a_seed, evk, stream=None):
+        ks_expand_seeded_a(self.handle, a_seed, evk, stream=stream)
 
     def ntt(self, data, g, inverse=False, stream=None):
         ks_ntt(self.handle, list(g), inverse, data, stream=stream)

@@ -148,9 +148,20 @@ ks_status_t run_dc(const Plan &pl, const uint32_t *evk, uint32_t level, const ui
   return KS_OK;
 }
 
+// One key switch of a call: a full key, or a compressed one (b halves plus
+// the seed of the a halves).
+struct Job {
+  const uint32_t *evk;
+  uint64_t a_seed;
+  uint32_t level;
+  const uint32_t *in;
+  uint32_t *out;
+};
+
 // ---------------------------------------------------------------- OC
-OcJob make_oc_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
-                  uint32_t *ws, uint32_t tt) {
+OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
+  const uint32_t *evk = jb.evk, *d = jb.in, level = jb.level;
+  uint32_t *out = jb.out;
   const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
   OcJob j{};
   j.d = d;
@@ -161,6 +172,7 @@ OcJob make_oc_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uin
   j.ycol = j.xt + (size_t)L1 * N;
   j.zp = j.ycol + (size_t)D * T * N;
   j.wcol = j.zp + (size_t)2 * K * N;
+  j.a_seed = jb.a_seed;
   j.ttu = j.ttd = tt;
   oc_tiles_host(pl, level, tt, j.tiles);
   return j;
@@ -168,20 +180,19 @@ OcJob make_oc_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uin
 
 uint32_t oc_tt(const Plan &pl) { return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1); }
 
-ks_status_t run_oc(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
-                   uint32_t *ws, hipStream_t st) {
+ks_status_t run_oc(const Plan &pl, const Job &jb, bool seeded, uint32_t *ws, hipStream_t st) {
   const uint32_t tt = oc_tt(pl);
-  const OcJob j = make_oc_job(pl, evk, level, d, out, ws, tt);
-  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, st));
+  const OcJob j = make_oc_job(pl, jb, ws, tt);
+  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, seeded, st));
 }
 
-ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint32_t level, const uint32_t *d,
-                    uint32_t *out, uint32_t *ws, hipStream_t st) {
+// Compressed keys are supported by the OC schedule only (callers check).
+ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const Job &jb, bool seeded, uint32_t *ws, hipStream_t st) {
   ks_status_t r;
   switch (sch) {
-    case KS_SCHED_MP: r = run_mp(pl, evk, level, d, out, ws, st); break;
-    case KS_SCHED_DC: r = run_dc(pl, evk, level, d, out, ws, st); break;
-    default: r = run_oc(pl, evk, level, d, out, ws, st); break;
+    case KS_SCHED_MP: r = run_mp(pl, jb.evk, jb.level, jb.in, jb.out, ws, st); break;
+    case KS_SCHED_DC: r = run_dc(pl, jb.evk, jb.level, jb.in, jb.out, ws, st); break;
+    default: r = run_oc(pl, jb, seeded, ws, st); break;
   }
   return r;
 }
@@ -190,6 +201,7 @@ ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const uint32_t *evk, uint
 // workspace, configuration); the job table is re-uploaded before each replay.
 struct GraphEntry {
   uint32_t count, mode, tt, spin, total;
+  bool seeded;
   std::vector<uint32_t> max_tiles;
   const void *ws;
   hipGraphExec_t exec;
@@ -200,14 +212,16 @@ struct GraphCache {
 };
 
 ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<uint32_t> &max_tiles, uint32_t total,
-                            char *ws, const BatchLayout &lay, uint32_t mode, uint32_t tt, uint32_t spin,
+                            char *ws, const BatchLayout &lay, uint32_t mode, uint32_t tt, uint32_t spin, bool seeded,
                             hipStream_t st) {
   const OcJob *djobs = (const OcJob *)(ws + lay.jobs);
+  if (mode == 2 && seeded) return KS_ERR_UNSUPPORTED;
   if (mode == 2)
     return dev_err(launch_oc_persistent(pl, djobs, (const OcSeg *)(ws + lay.segs), count * OC_NPHASE, total, count,
                                         (uint32_t *)(ws + lay.ctl), spin, st));
   const OcJob none{};
-  if (mode != 3 || count < 2) return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, st));
+  if (mode != 3 || count < 2)
+    return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, seeded, st));
   // Mode 3: the batch runs as two halves, the second on the plan's side stream:
   // the halves drift apart, so a bandwidth-bound phase of one overlaps a
   // compute-bound phase of the other.  (Each half launches with the batch's
@@ -218,14 +232,14 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
   TRY(hipEventRecord(f->fork, st));
   TRY(hipStreamWaitEvent(f->side, f->fork, 0));
   const uint32_t h = count / 2;
-  TRY(launch_oc_phases(pl, none, djobs, h, max_tiles.data(), tt, st));
-  TRY(launch_oc_phases(pl, none, djobs + h, count - h, max_tiles.data(), tt, f->side));
+  TRY(launch_oc_phases(pl, none, djobs, h, max_tiles.data(), tt, seeded, st));
+  TRY(launch_oc_phases(pl, none, djobs + h, count - h, max_tiles.data(), tt, seeded, f->side));
   TRY(hipEventRecord(f->join, f->side));
   TRY(hipStreamWaitEvent(st, f->join, 0));
   return KS_OK;
 }
 
-ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const BatchLayout &lay, char *ws,
+ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, bool seeded, const BatchLayout &lay, char *ws,
                          hipStream_t st) {
   const uint32_t mode = pl.cfg.batch_mode;
   const uint32_t tt = mode == 2 ? 1 : oc_tt(pl);
@@ -234,7 +248,7 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const B
   std::vector<OcJob> hj(count);
   std::vector<uint32_t> max_tiles(OC_NPHASE, 0);
   for (uint32_t i = 0; i < count; i++) {
-    hj[i] = make_oc_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)(ws + lay.region[i]), tt);
+    hj[i] = make_oc_job(pl, jobs[i], (uint32_t *)(ws + lay.region[i]), tt);
     for (uint32_t p = 0; p < OC_NPHASE; p++) max_tiles[p] = std::max(max_tiles[p], hj[i].tiles[p]);
   }
   std::vector<OcSeg> segs;
@@ -253,7 +267,7 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const B
   TRY(upload_async(pl, ws, blob.data(), blob.size(), st));
 
   const bool use_graph = pl.cfg.graph != 2 && !pl.trace.on;
-  if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, st);
+  if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, seeded, st);
 
   // graph keyed by (count, workspace, mode, tile, spin); the persistent launch
   // reads `total` from its arguments, so it is part of the key as well
@@ -266,13 +280,13 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const B
   hipGraphExec_t exec = nullptr;
   for (auto &e : gc->entries)
     if (e.count == count && e.ws == ws && e.mode == mode && e.tt == tt && e.spin == spin && e.total == total &&
-        e.max_tiles == max_tiles)
+        e.seeded == seeded && e.max_tiles == max_tiles)
       exec = e.exec;
   if (!exec) {
     if (!gc->capture && hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking) != hipSuccess)
       return KS_ERR_DEVICE;
     TRY(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
-    ks_status_t r = launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, gc->capture);
+    ks_status_t r = launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, seeded, gc->capture);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(gc->capture, &graph);
     if (r != KS_OK || e != hipSuccess) {
@@ -286,14 +300,15 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const ks_job_t *jobs, const B
       (void)hipGraphExecDestroy(gc->entries.front().exec);
       gc->entries.erase(gc->entries.begin());
     }
-    gc->entries.push_back(GraphEntry{count, mode, tt, spin, total, max_tiles, ws, exec});
+    gc->entries.push_back(GraphEntry{count, mode, tt, spin, total, seeded, max_tiles, ws, exec});
   }
   TRY(hipGraphLaunch(exec, st));
   return KS_OK;
 }
 
+// evk_halves: 2 for a full key, 1 for a compressed key (b halves only).
 ks_status_t check_job(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *in, const uint32_t *out,
-                      const void *ws, size_t ws_bytes, size_t need) {
+                      const void *ws, size_t ws_bytes, size_t need, uint32_t evk_halves = 2) {
   if (!evk || !in || !out || !ws) return KS_ERR_INVALID_ARG;
   if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
   if (((uintptr_t)evk | (uintptr_t)in | (uintptr_t)out) & 15) return KS_ERR_INVALID_ARG;
@@ -301,7 +316,7 @@ ks_status_t check_job(const Plan &pl, const uint32_t *evk, uint32_t level, const
   if (ws_bytes < need) return KS_ERR_BUDGET;
   const size_t lb = limb_bytes(pl);
   const size_t out_b = 2 * (size_t)(level + 1) * lb, in_b = (size_t)(level + 1) * lb;
-  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb;
+  const size_t evk_b = (size_t)pl.dnum * evk_halves * pl.ntot * lb;
   if (overlaps(out, out_b, in, in_b) || overlaps(out, out_b, evk, evk_b) || overlaps(out, out_b, ws, ws_bytes))
     return KS_ERR_INVALID_ARG;
   if (overlaps(ws, ws_bytes, in, in_b) || overlaps(ws, ws_bytes, evk, evk_b)) return KS_ERR_INVALID_ARG;
@@ -451,20 +466,6 @@ ks_status_t ks_workspace_size(ks_plan_t plan, uint32_t count, const uint32_t *le
   return KS_OK;
 }
 
-ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in, uint32_t *out,
-                         void *workspace, size_t workspace_bytes, void *stream) {
-  if (!plan) return KS_ERR_INVALID_ARG;
-  const Plan &pl = plan->p;
-  const ks_schedule_t sch = effective(pl);
-  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
-  const size_t need = ws_limbs(pl, sch, level) * limb_bytes(pl);
-  ks_status_t st = check_job(pl, evk, level, in, out, workspace, workspace_bytes, need);
-  if (st != KS_OK) return st;
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
-  return run_one(pl, sch, evk, level, in, out, (uint32_t *)workspace, (hipStream_t)stream);
-}
-
 // Failure-handling tests: KS_FAULT_INJECT=<n> makes the n-th call (1-based)
 // of ks_keyswitch_batch after the variable took its current value report
 // KS_ERR_DEVICE without enqueuing anything.
@@ -483,12 +484,31 @@ static bool injected_fault() {
   return ++calls == std::strtoull(now.c_str(), nullptr, 10);
 }
 
-ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
-                               size_t workspace_bytes, void *stream) {
-  if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
-  if (injected_fault()) return KS_ERR_DEVICE;
+}  // extern "C"
+
+namespace {
+
+ks_status_t keyswitch_one(ks_plan_t plan, const Job &jb, bool seeded, void *workspace, size_t workspace_bytes,
+                          void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  const ks_schedule_t sch = effective(pl);
+  if (seeded && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
+  if (jb.level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  const size_t need = ws_limbs(pl, sch, jb.level) * limb_bytes(pl);
+  ks_status_t st = check_job(pl, jb.evk, jb.level, jb.in, jb.out, workspace, workspace_bytes, need, seeded ? 1 : 2);
+  if (st != KS_OK) return st;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  return run_one(pl, sch, jb, seeded, (uint32_t *)workspace, (hipStream_t)stream);
+}
+
+ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, bool seeded, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+  const uint32_t count = (uint32_t)jobs.size();
   Plan &pl = plan->p;
   const ks_schedule_t sch = effective(pl);
+  if (seeded && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (!count) return KS_OK;
   std::vector<uint32_t> levels(count);
   for (uint32_t i = 0; i < count; i++) {
@@ -505,7 +525,7 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
   }
   for (uint32_t i = 0; i < count; i++) {
     ks_status_t st = check_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, workspace,
-                               workspace_bytes, need);
+                               workspace_bytes, need, seeded ? 1 : 2);
     if (st != KS_OK) return st;
     // no job's output may overlap another job's output or input (either order)
     const size_t ob = 2 * (size_t)(jobs[i].level + 1) * limb_bytes(pl);
@@ -523,12 +543,53 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
   hipStream_t st = (hipStream_t)stream;
   if (!together) {
     for (uint32_t i = 0; i < count; i++) {
-      ks_status_t r = run_one(pl, sch, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, (uint32_t *)workspace, st);
+      ks_status_t r = run_one(pl, sch, jobs[i], seeded, (uint32_t *)workspace, st);
       if (r != KS_OK) return r;
     }
     return KS_OK;
   }
-  return run_oc_batch(pl, count, jobs, lay, (char *)workspace, st);
+  return run_oc_batch(pl, count, jobs.data(), seeded, lay, (char *)workspace, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in, uint32_t *out,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+  return keyswitch_one(plan, Job{evk, 0, level, in, out}, false, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_keyswitch_seeded(ks_plan_t plan, const uint32_t *evk_b, uint64_t a_seed, uint32_t level,
+                                const uint32_t *in, uint32_t *out, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+  return keyswitch_one(plan, Job{evk_b, a_seed, level, in, out}, true, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+  if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
+  if (injected_fault()) return KS_ERR_DEVICE;
+  std::vector<Job> jb(count);
+  for (uint32_t i = 0; i < count; i++) jb[i] = Job{jobs[i].evk, 0, jobs[i].level, jobs[i].in, jobs[i].out};
+  return keyswitch_batch(plan, jb, false, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_seeded_job_t *jobs, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+  if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
+  if (injected_fault()) return KS_ERR_DEVICE;
+  std::vector<Job> jb(count);
+  for (uint32_t i = 0; i < count; i++) jb[i] = Job{jobs[i].evk_b, jobs[i].a_seed, jobs[i].level, jobs[i].in, jobs[i].out};
+  return keyswitch_batch(plan, jb, true, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_expand_seeded_a(ks_plan_t plan, uint64_t a_seed, uint32_t *evk, void *stream) {
+  if (!plan || !evk || ((uintptr_t)evk & 15)) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  return dev_err(launch_expand_a(pl, a_seed, evk, (hipStream_t)stream));
 }
 
 ks_status_t ks_batch_status(ks_plan_t plan, const void *workspace, void *stream, uint32_t *error_flag) {

@@ -47,6 +47,10 @@ hipError_t launch_bconv_down(const Plan &pl, uint32_t level, const uint32_t *xp,
 hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *acc, const uint32_t *what,
                                 uint32_t *out, hipStream_t st);
 
+// Compressed keys: writes the a half of every pair of the full-layout key evk
+// [dnum][2][L+1+K][N] from the seed (the b halves are left as they are).
+hipError_t launch_expand_a(const Plan &pl, uint64_t seed, uint32_t *evk, hipStream_t st);
+
 // ------------------------------------------------------------ Output-Centric
 // Phases in issue order (see oc_kernels.h).
 enum OcPhase : uint32_t {
@@ -56,16 +60,23 @@ enum OcPhase : uint32_t {
 // first).  Both depend only on INTT_COL, so one launch fills the device with
 // both instead of running them one after the other.
 constexpr uint32_t OC_UP_PQ = OC_NPHASE;
+// Launch-only phases: ROW_P / ROW_Q for compressed keys (Sec. IV-D), which
+// read only the b halves and regenerate the a halves from the job's seed.
+constexpr uint32_t OC_ROW_P_SEEDED = OC_NPHASE + 1;
+constexpr uint32_t OC_ROW_Q_SEEDED = OC_NPHASE + 2;
 
 // One key switch as the OC kernels see it (device-visible, by value or in a
 // job table).  Workspace regions: xt [l+1][N] ModUp P1 output, ycol
 // [ndig][T][N] column-pass output of ModUp P2/P3, zp [2][K][N] ModDown P1,
-// wcol [2][l+1][N] column-pass output of ModDown P2/P3.
+// wcol [2][l+1][N] column-pass output of ModDown P2/P3.  evk is the full key
+// [dnum][2][L+1+K][N], or for a compressed key its b halves [dnum][L+1+K][N]
+// with a_seed regenerating the a halves (the seeded row phases).
 struct OcJob {
   const uint32_t *d;
   const uint32_t *evk;
   uint32_t *out;
   uint32_t *xt, *ycol, *zp, *wcol;
+  uint64_t a_seed;
   uint32_t level, ttu, ttd, pad;
   uint32_t tiles[OC_NPHASE];  // tile count of every phase for this job
 };
@@ -108,16 +119,17 @@ __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint3
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want);
 // Tile counts of every phase (host).
 void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles);
-// One launch per phase; jobs == nullptr runs `one` alone.
+// One launch per phase; jobs == nullptr runs `one` alone.  seeded: every
+// job's key is compressed (b halves plus a_seed).
 hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                            const uint32_t *max_tiles, uint32_t tt, hipStream_t st);
+                            const uint32_t *max_tiles, uint32_t tt, bool seeded, hipStream_t st);
 // Persistent work-queue launch (tiles of one target per conversion tile).
 hipError_t launch_oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs,
                                 uint32_t total, uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);
 
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
-                     uint32_t tt, hipStream_t st);
+                     uint32_t tt, bool seeded, hipStream_t st);
 template <int A>
 hipError_t oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs, uint32_t total,
                          uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);

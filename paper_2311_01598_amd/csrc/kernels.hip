@@ -376,6 +376,24 @@ hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ compressed keys
+// grid (N/1024, ntot, dnum): the a half of digit j, row g (evk order), four
+// consecutive words per thread, written into a full-layout key.
+__global__ __launch_bounds__(256) void k_expand_a(DevPlan P, uint64_t seed, uint32_t *__restrict__ evk) {
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t g = blockIdx.y, j = blockIdx.z;
+  const uint32_t k = (blockIdx.x * 256 + threadIdx.x) * 4;
+  const ModQ m = P.mods[g];
+  uint32_t a[4];
+  seeded_a4(a, seed, (uint32_t)(((size_t)j * P.ntot + g) * N + k), m);
+  stg4(evk + (((size_t)2 * j + 1) * P.ntot + g) * N + k, make_uint4(a[0], a[1], a[2], a[3]));
+}
+
+hipError_t launch_expand_a(const Plan &pl, uint64_t seed, uint32_t *evk, hipStream_t st) {
+  KS_LAUNCH(pl, "expand_a", k_expand_a, dim3(pl.n / 1024, pl.ntot, pl.dnum), dim3(256), 0, st, pl.dev, seed, evk);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ OC entry
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want) {
   // two targets per tile keep 2 x 16 accumulators per thread; columns of
@@ -396,14 +414,14 @@ void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles)
 }
 
 hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                            const uint32_t *max_tiles, uint32_t tt, hipStream_t st) {
+                            const uint32_t *max_tiles, uint32_t tt, bool seeded, hipStream_t st) {
   switch (pl.dev.loga) {
-    case 4: return oc_phases<4>(pl, one, jobs, count, max_tiles, tt, st);
-    case 5: return oc_phases<5>(pl, one, jobs, count, max_tiles, tt, st);
-    case 6: return oc_phases<6>(pl, one, jobs, count, max_tiles, tt, st);
-    case 7: return oc_phases<7>(pl, one, jobs, count, max_tiles, tt, st);
-    case 8: return oc_phases<8>(pl, one, jobs, count, max_tiles, tt, st);
-    case 9: return oc_phases<9>(pl, one, jobs, count, max_tiles, tt, st);
+    case 4: return oc_phases<4>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 5: return oc_phases<5>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 6: return oc_phases<6>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 7: return oc_phases<7>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 8: return oc_phases<8>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 9: return oc_phases<9>(pl, one, jobs, count, max_tiles, tt, seeded, st);
   }
   return hipErrorInvalidValue;
 }

@@ -152,6 +152,27 @@ __device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
   return csub(r, m.q);
 }
 
+// Compressed keys (Sec. IV-D): the a half of a key pair is regenerated where
+// it is consumed instead of read.  The generator is SplitMix64 (Steele, Lea
+// and Flood 2014) evaluated at a counter: output t of seed s mixes
+// s + (t + 1) gamma.  Word k of row g of digit j's a half uses the counter
+// t = (j (L+1+K) + g) N + k, which is the word's position in the b halves;
+// the word is x 2^-32 mod m_g (one REDC of the 64-bit output, canonical).
+// Four consecutive counters from t.
+__device__ __forceinline__ void seeded_a4(uint32_t (&a)[4], uint64_t seed, uint32_t t, const ModQ &m) {
+  constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+  uint64_t z = seed + ((uint64_t)t + 1) * kGamma;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    uint64_t x = z;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    a[i] = redc64(x, m);
+    z += kGamma;
+  }
+}
+
 // Harvey forward (Cooley-Tukey) butterfly, inputs and outputs in [0, 4q).
 // The forward twiddle tables hold (-w mod 2^32, w') so that the Shoup
 // product comes out negated: nt = h q + y (-w) = -(y w - h q) = -t mod 2^32

@@ -576,7 +576,7 @@ __device__ __forceinline__ void ld4_nt(uint32_t (&v)[4], const uint32_t *p) {
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
-template <bool IS_P>
+template <bool IS_P, bool SEEDED>
 __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
@@ -593,8 +593,13 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;  // digit holding tower t (bypassed)
   uint2 *twl = row_tw(lds);
   const uint2 *twr = twl + r * kRowTwS;
-  const uint32_t *evk_t = J.evk + (size_t)g * N + roff + k0;  // + (2 digit + poly) ntot N
+  // key row of digit j: full key, half h at (2 j + h) ntot N; compressed
+  // key, b half at j ntot N (that offset is also the a half's counter)
+  const uint32_t *evk_t = J.evk + (size_t)g * N + roff + k0;
   const size_t evk_step = (size_t)P.ntot * N;
+  constexpr uint32_t kHalves = SEEDED ? 1 : 2;
+  const uint32_t ctr0 = (uint32_t)((size_t)g * N + roff + k0);
+  auto gen_a = [&](uint32_t (&a)[4], uint32_t j) { seeded_a4(a, J.a_seed, ctr0 + j * (uint32_t)evk_step, m); };
 
   // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the
   // foreign digits.  Job jb of a round runs in slot jb % 4.
@@ -627,8 +632,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       const uint32_t jb2 = base + s2;
       uint32_t d2 = jb2 < njobs ? job_digit(jb2) : 0xffffffffu;
       d2 = d2 == 0xffffffffu ? dummy : d2;
-      ld4_nt(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
-      ld4_nt(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
+      ld4_nt(ek[s2][0], evk_t + (kHalves * d2 + 0) * evk_step);
+      if (!SEEDED) ld4_nt(ek[s2][1], evk_t + (kHalves * d2 + 1) * evk_step);
     }
   };
 
@@ -643,8 +648,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   uint32_t yo[4], eo0[4], eo1[4];
   if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
     ld4(yo, J.d + (size_t)t * N + roff + k0);
-    ld4_nt(eo0, evk_t + (2 * own + 0) * evk_step);
-    ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
+    ld4_nt(eo0, evk_t + (kHalves * own + 0) * evk_step);
+    if (!SEEDED) ld4_nt(eo1, evk_t + (kHalves * own + 1) * evk_step);
   }
   load_keys(0);
   // ROW_P: the inverse twiddles of its ModDown P1 pass are loaded now, so
@@ -675,6 +680,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
 #pragma unroll
         for (int i = 0; i < 4; i++) (jb2 == 0 ? w0 : w1)[i] = y[i];
       } else {
+        if (SEEDED) gen_a(ek[s2][1], job_digit(jb2));
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           acc0[i] = mad64(y[i], ek[s2][0][i], acc0[i]);
@@ -685,6 +691,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     __syncthreads();  // LDS rows are rewritten by the next round
   }
   if (!IS_P) {
+    if (SEEDED) gen_a(eo1, own);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       acc0[i] = mad64(yo[i], eo0[i], acc0[i]);
@@ -747,11 +754,11 @@ __device__ __forceinline__ void oc_tile(const DevPlan &P, const OcJob &J, uint32
     case OC_INTT_ROW: tile_intt_row(P, J, tile, lds); break;
     case OC_INTT_COL: tile_intt_col<A>(P, J, tile, false, lds); break;
     case OC_UP_P: tile_up<A, TTU>(P, J, tile, true, J.ttu, lds); break;
-    case OC_ROW_P: tile_row<true>(P, J, tile, lds); break;
+    case OC_ROW_P: tile_row<true, false>(P, J, tile, lds); break;
     case OC_UP_Q: tile_up<A, TTU>(P, J, tile, false, J.ttu, lds); break;
     case OC_INTT_COL_DN: tile_intt_col<A>(P, J, tile, true, lds); break;
     case OC_DN: tile_dn<A, TTD>(P, J, tile, J.ttd, lds); break;
-    case OC_ROW_Q: tile_row<false>(P, J, tile, lds); break;
+    case OC_ROW_Q: tile_row<false, false>(P, J, tile, lds); break;
   }
 }
 
@@ -760,7 +767,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // LDS words of one phase's tiles, and of any phase (persistent kernel)
 template <int A, int PHASE, int TT>
 constexpr int oc_phase_lds_words() {
-  return (PHASE == OC_ROW_P || PHASE == OC_ROW_Q) ? kRowTileLds
+  return (PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED)
+             ? kRowTileLds
          : PHASE == OC_INTT_ROW                   ? kRowLds
          : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS + 2 * (1 << A)
                                                            : TT * (ColGeom<A>::LDS + 2 * (1 << A));
@@ -804,7 +812,11 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
     for (int i = 0; i < (int)(sizeof(OcJob) / 4); i++) dst[i] = src[i];
   }
   constexpr bool COL = PHASE != OC_INTT_ROW && PHASE != OC_ROW_P && PHASE != OC_ROW_Q;
-  if constexpr (PHASE == OC_UP_PQ) {
+  if constexpr (PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED) {
+    constexpr bool IS_P = PHASE == OC_ROW_P_SEEDED;
+    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row<IS_P, true>(P, J, blockIdx.x, lds);
+  } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
     const uint32_t b = special ? blockIdx.x : blockIdx.x - np;
@@ -817,9 +829,9 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   }
 }
 
-static const char *const kOcPhaseName[OC_NPHASE + 1] = {
+static const char *const kOcPhaseName[OC_NPHASE + 3] = {
     "oc.intt_row", "oc.intt_col.up", "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
-    "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q", "oc.bconv_col.up"};
+    "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q", "oc.bconv_col.up", "oc.row.p.seeded", "oc.row.q.seeded"};
 
 template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
@@ -831,22 +843,24 @@ static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, ui
 
 template <int A, int TT>
 static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                             const uint32_t *max_tiles, hipStream_t st) {
+                             const uint32_t *max_tiles, bool seeded, hipStream_t st) {
   launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
   launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
   // a job's merged grid needs at most its own UP_P + UP_Q tiles
   launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
-  launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
+  if (seeded) launch_phase<A, OC_ROW_P_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
+  else launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
-  launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
+  if (seeded) launch_phase<A, OC_ROW_Q_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
+  else launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
 }
 
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
-                     uint32_t tt, hipStream_t st) {
-  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, st);
-  else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, st);
+                     uint32_t tt, bool seeded, hipStream_t st) {
+  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, seeded, st);
+  else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, seeded, st);
   return hipGetLastError();
 }
 

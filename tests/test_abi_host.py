@@ -70,3 +70,40 @@ def test_plan_rejects_bad_params_before_device_work(shape, status):
 def test_status_strings():
     for s in range(6):
         assert ks.ks_status_string(s)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The Python binding's job and parameter structs have the header's
+    sizes and field offsets (compiled here with the host C compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no host C compiler")
+    checks = {
+        "ks_job_t": ["evk", "level", "in", "out"],
+        "ks_seeded_job_t": ["evk_b", "a_seed", "level", "in", "out"],
+        "ks_config_t": ["schedule", "tile_towers", "batch_mode", "spin_limit"],
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ks.h"', "int main(void) {"]
+    for t, fields in checks.items():
+        lines.append(f'  printf("{t} %zu\\n", sizeof({t}));')
+        for f in fields:
+            lines.append(f'  printf("{t}.{f} %zu\\n", offsetof({t}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("header needs the HIP toolchain: " + r.stderr[-300:])
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    pyname = {"in": "in_"}
+    for t, fields in checks.items():
+        cls = getattr(ks, t)
+        assert int(got[t]) == ctypes.sizeof(cls), t
+        for f in fields:
+            assert int(got[f"{t}.{f}"]) == getattr(cls, pyname.get(f, f)).offset, (t, f)
