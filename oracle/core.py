@@ -50,6 +50,15 @@ def lib():
             "oracle_keygen_seeded": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, ctypes.c_uint64, _I8P, _I8P, _U32P]),
             "oracle_splitmix_at": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
             "oracle_seeded_a": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, _U32P]),
+            "oracle_automorphism_coeff": (ctypes.c_int, [_U32P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                                         _U32P]),
+            "oracle_automorphism_eval": (ctypes.c_int, [_U32P, ctypes.c_uint32, ctypes.c_uint32, _U32P]),
+            "oracle_keygen_rotation": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, ctypes.c_uint32, _I8P, _I8P, _U32P]),
+            "oracle_keygen_relin": (ctypes.c_int, [P, _U32P, ctypes.c_uint64, _I8P, _U32P]),
+            "oracle_rotate_hoisted": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, ctypes.c_uint32, _U32P,
+                                                     _U32P, _U32P]),
+            "oracle_rotate": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, ctypes.c_uint32, _U32P, _U32P]),
+            "oracle_mult_relin": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, _U32P, _U32P, _U32P, _U32P]),
             "oracle_set_fault": (None, [ctypes.c_int]),
             "oracle_evk_words": (ctypes.c_uint64, [ctypes.c_uint32] * 4),
         }
@@ -219,6 +228,102 @@ def keygen_seeded(p, mods, seed, a_seed):
     if h < 0:
         raise ValueError("oracle_keygen_seeded rejected its arguments")
     return s, s2, evk, h
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return a, a.ctypes.data_as(_U32P)
+
+
+def automorphism_coeff(a, log_n, galois, q):
+    """a(X^k) of a coefficient-domain limb."""
+    a, ap = _arr(a)
+    out = np.zeros(1 << log_n, np.uint32)
+    if lib().oracle_automorphism_coeff(ap, log_n, int(galois), int(q), out.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("bad Galois element")
+    return out
+
+
+def automorphism_eval(a, log_n, galois):
+    """a(X^k) of an evaluation-domain limb (a permutation of the slots);
+    a may be [..., N], each limb permuted."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    flat = a.reshape(-1, 1 << log_n)
+    out = np.zeros_like(flat)
+    for i in range(flat.shape[0]):
+        if lib().oracle_automorphism_eval(flat[i].ctypes.data_as(_U32P), log_n, int(galois),
+                                          out[i].ctypes.data_as(_U32P)) != 0:
+            raise ValueError("bad Galois element")
+    return out.reshape(a.shape)
+
+
+def galois_rotation(log_n, r):
+    """Galois element of a rotation by r slots: 5^r mod 2N (r may be negative)."""
+    two_n = 2 << log_n
+    return pow(5, r % (two_n // 4), two_n)
+
+
+def keygen_rotation(p, mods, seed, galois):
+    """(s, s_k, evk, h): evk switches from s_k = s(X^k) to s."""
+    mods, mp_ = _u32(mods)
+    s = np.zeros(p.n, np.int8)
+    s2 = np.zeros(p.n, np.int8)
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint32)
+    h = lib().oracle_keygen_rotation(ctypes.byref(p.c()), mp_, int(seed), int(galois), s.ctypes.data_as(_I8P),
+                                     s2.ctypes.data_as(_I8P), evk.ctypes.data_as(_U32P))
+    if h < 0:
+        raise ValueError("oracle_keygen_rotation rejected its arguments")
+    return s, s2, evk, h
+
+
+def keygen_relin(p, mods, seed):
+    """(s, evk, h): evk switches from s^2 to s."""
+    mods, mp_ = _u32(mods)
+    s = np.zeros(p.n, np.int8)
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint32)
+    h = lib().oracle_keygen_relin(ctypes.byref(p.c()), mp_, int(seed), s.ctypes.data_as(_I8P),
+                                  evk.ctypes.data_as(_U32P))
+    if h < 0:
+        raise ValueError("oracle_keygen_relin rejected its arguments")
+    return s, evk, h
+
+
+def rotate_hoisted(p, mods, level, c0, c1, galois, evks):
+    """Rotations of (c0, c1) by each Galois element, one shared ModUp;
+    returns [count][2][level+1][N]."""
+    mods, mp_ = _u32(mods)
+    c0, c0p = _arr(c0)
+    c1, c1p = _arr(c1)
+    g, gp_ = _arr(list(galois))
+    ev, evp = _arr(np.stack(list(evks)))
+    outs = np.zeros((len(g), 2, level + 1, p.n), np.uint32)
+    if lib().oracle_rotate_hoisted(ctypes.byref(p.c()), mp_, int(level), c0p, c1p, len(g), gp_, evp,
+                                   outs.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("oracle_rotate_hoisted rejected its arguments")
+    return outs
+
+
+def rotate(p, mods, level, c0, c1, galois, evk):
+    mods, mp_ = _u32(mods)
+    c0, c0p = _arr(c0)
+    c1, c1p = _arr(c1)
+    ev, evp = _arr(evk)
+    out = np.zeros((2, level + 1, p.n), np.uint32)
+    if lib().oracle_rotate(ctypes.byref(p.c()), mp_, int(level), c0p, c1p, int(galois), evp,
+                           out.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("oracle_rotate rejected its arguments")
+    return out
+
+
+def mult_relin(p, mods, level, a0, a1, b0, b1, evk):
+    mods, mp_ = _u32(mods)
+    bufs = [_arr(x) for x in (a0, a1, b0, b1)]
+    ev, evp = _arr(evk)
+    out = np.zeros((2, level + 1, p.n), np.uint32)
+    if lib().oracle_mult_relin(ctypes.byref(p.c()), mp_, int(level), *[b[1] for b in bufs], evp,
+                               out.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("oracle_mult_relin rejected its arguments")
+    return out
 
 
 def set_fault(k):

@@ -29,7 +29,8 @@ void oracle_set_fault(int fault) { g_fault = fault; }
  *  1: ModUp P5 drops the last digit's contribution
  *  2: ModDown P4 adds w_hat instead of subtracting it
  *  3: ModUp P2 uses the wrong target constant (index off by one)
- *  4: ModUp P3 bypass takes the limb from the neighbouring digit */
+ *  4: ModUp P3 bypass takes the limb from the neighbouring digit
+ *  5: hoisted rotation permutes the digits with the inverse map */
 
 /* ------------------------------------------------------------------ */
 /* integers                                                             */
@@ -296,23 +297,15 @@ static void moddown(const ks_ctx *c, const uint32_t *acc, uint32_t *out) {
   free(w);
 }
 
-int oracle_keyswitch(const oracle_params *p, const uint32_t *moduli, uint32_t level,
-                     const uint32_t *evk, const uint32_t *d, uint32_t *out) {
-  ks_ctx c;
-  if (ctx_init(&c, p, moduli, level) != 0) return -1;
-  const uint32_t n = c.n, l1 = level + 1, T = c.ntow, D = c.ndig, EL = c.L1 + c.K;
-  /* ModUp P1: INTT of every input tower */
-  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
-  /* ModUp P2/P3 output, one [T][N] block per digit: y[j][t] */
-  uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)D * T * n);
-  uint32_t *acc = (uint32_t *)calloc((size_t)2 * T * n, sizeof(uint32_t));
-  uint32_t *tgt = (uint32_t *)malloc(sizeof(uint32_t) * T * n);
-  uint32_t *tq = (uint32_t *)malloc(sizeof(uint32_t) * T);
-  if (!x || !y || !acc || !tgt || !tq) { free(x); free(y); free(acc); free(tgt); free(tq); return -1; }
-
+/* ModUp P1-P3 (Sec. III-B) of d [level+1][N]: x receives the INTT of
+ * every input tower, y[j][t] ([D][T][N], evaluation domain) digit j
+ * extended to every tower of D_l, the digit's own towers copied from d.
+ * tgt [T][N] and tq [T] are scratch. */
+static void modup(const ks_ctx *cc, const uint32_t *d, uint32_t *x, uint32_t *y, uint32_t *tgt, uint32_t *tq) {
+  const ks_ctx c = *cc;
+  const uint32_t n = c.n, l1 = c.level + 1, T = c.ntow, D = c.ndig;
   memcpy(x, d, sizeof(uint32_t) * (size_t)l1 * n);
   for (uint32_t i = 0; i < l1; i++) oracle_intt(LIMB(x, i, n), c.log_n, c.q[i], c.psi[i]);
-
   for (uint32_t j = 0; j < D; j++) {
     uint32_t lo, hi;
     digit_range(&c, j, &lo, &hi);
@@ -336,6 +329,23 @@ int oracle_keyswitch(const oracle_params *p, const uint32_t *moduli, uint32_t le
       }
     }
   }
+}
+
+int oracle_keyswitch(const oracle_params *p, const uint32_t *moduli, uint32_t level,
+                     const uint32_t *evk, const uint32_t *d, uint32_t *out) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, level) != 0) return -1;
+  const uint32_t n = c.n, l1 = level + 1, T = c.ntow, D = c.ndig, EL = c.L1 + c.K;
+  /* ModUp P1: INTT of every input tower */
+  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  /* ModUp P2/P3 output, one [T][N] block per digit: y[j][t] */
+  uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)D * T * n);
+  uint32_t *acc = (uint32_t *)calloc((size_t)2 * T * n, sizeof(uint32_t));
+  uint32_t *tgt = (uint32_t *)malloc(sizeof(uint32_t) * T * n);
+  uint32_t *tq = (uint32_t *)malloc(sizeof(uint32_t) * T);
+  if (!x || !y || !acc || !tgt || !tq) { free(x); free(y); free(acc); free(tgt); free(tq); return -1; }
+
+  modup(&c, d, x, y, tgt, tq);
   /* P4: apply the key, P5: sum over digits */
   for (uint32_t j = 0; j < D; j++) {
     if (g_fault == 1 && j == D - 1 && D > 1) continue;
@@ -352,7 +362,6 @@ int oracle_keyswitch(const oracle_params *p, const uint32_t *moduli, uint32_t le
   free(x); free(y); free(acc); free(tgt); free(tq);
   return 0;
 }
-
 /* Output-Centric order (Sec. IV-C): INTT outputs kept, then one output tower
  * at a time.  Section 2 (the P towers, every digit extended) comes first so
  * their INTT (ModDown P1) is available; then each Q tower takes the other
@@ -474,23 +483,188 @@ int oracle_seeded_a(const oracle_params *p, const uint32_t *moduli, uint64_t a_s
   return 0;
 }
 
-static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, uint64_t a_seed,
-                       int8_t *s, int8_t *s2, uint32_t *evk);
+/* s2 of a key: KG_RANDOM a fresh ternary secret, KG_ROTATE sigma_k(s) (the
+ * key of a rotation), KG_RELIN s^2 (the key of a multiplication). */
+enum { KG_RANDOM = 0, KG_ROTATE = 1, KG_RELIN = 2 };
+static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, int mode,
+                       uint32_t galois, int8_t *s, int8_t *s2, uint32_t *evk);
 
 int oracle_keygen(const oracle_params *p, const uint32_t *moduli, uint64_t seed,
                   int8_t *s, int8_t *s2, uint32_t *evk) {
-  return keygen_impl(p, moduli, seed, 0, 0, s, s2, evk);
+  return keygen_impl(p, moduli, seed, 0, KG_RANDOM, 0, s, s2, evk);
+}
+
+int oracle_keygen_rotation(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint32_t galois,
+                           int8_t *s, int8_t *s2, uint32_t *evk) {
+  const uint32_t two_n = 2u << p->log_n;
+  if ((galois & 1u) == 0 || galois >= two_n) return -1;
+  return keygen_impl(p, moduli, seed, 0, KG_ROTATE, galois, s, s2, evk);
+}
+
+int oracle_keygen_relin(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int8_t *s, uint32_t *evk) {
+  int8_t *s2 = (int8_t *)malloc((size_t)1 << p->log_n);
+  if (!s2) return -1;
+  const int h = keygen_impl(p, moduli, seed, 0, KG_RELIN, 0, s, s2, evk);
+  free(s2);
+  return h;
 }
 
 int oracle_keygen_seeded(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint64_t a_seed,
                          int8_t *s, int8_t *s2, uint32_t *evk) {
   if (oracle_seeded_a(p, moduli, a_seed, evk) != 0) return -1;
-  return keygen_impl(p, moduli, seed, 1, a_seed, s, s2, evk);
+  return keygen_impl(p, moduli, seed, 1, KG_RANDOM, 0, s, s2, evk);
 }
 
-static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, uint64_t a_seed,
-                       int8_t *s, int8_t *s2, uint32_t *evk) {
-  (void)a_seed;
+/* ------------------------------------------------------------------ */
+/* callers of the key switch: rotation and multiplication (Sec. II)     */
+/* ------------------------------------------------------------------ */
+
+/* The CKKS automorphism a(X) -> a(X^k), k odd (rotation by r slots uses
+ * k = 5^r mod 2N, conjugation k = 2N - 1; Cheon, Kim, Kim and Song 2017).
+ * Coefficient domain: X^i maps to X^(i k mod 2N) = -X^(i k mod 2N - N)
+ * past N, since X^N = -1. */
+int oracle_automorphism_coeff(const uint32_t *a, uint32_t log_n, uint32_t galois, uint32_t q, uint32_t *out) {
+  const uint32_t n = 1u << log_n, two_n = 2 * n;
+  if ((galois & 1u) == 0 || galois >= two_n) return -1;
+  for (uint32_t i = 0; i < n; i++) {
+    const uint32_t e = (uint32_t)(((uint64_t)i * galois) % two_n);
+    if (e < n) out[e] = a[i];
+    else out[e - n] = a[i] ? q - a[i] : 0;
+  }
+  return 0;
+}
+
+/* Evaluation domain: slot j holds a(psi^(2 brv(j) + 1)), so the slot of
+ * a(X^k) at that point holds a at psi^(k (2 brv(j) + 1)), i.e. slot j' with
+ * 2 brv(j') + 1 = k (2 brv(j) + 1) mod 2N: a permutation, the same for
+ * every modulus. */
+int oracle_automorphism_eval(const uint32_t *a, uint32_t log_n, uint32_t galois, uint32_t *out) {
+  const uint32_t n = 1u << log_n, two_n = 2 * n;
+  if ((galois & 1u) == 0 || galois >= two_n) return -1;
+  for (uint32_t j = 0; j < n; j++) {
+    const uint32_t e = 2 * oracle_bitrev(j, log_n) + 1;
+    const uint32_t e2 = (uint32_t)(((uint64_t)galois * e) % two_n);
+    out[j] = a[oracle_bitrev((e2 - 1) / 2, log_n)];
+  }
+  return 0;
+}
+
+/* Rotations of one ciphertext (c0, c1) at `level` (evaluation domain) by
+ * `count` Galois elements, sharing one ModUp (hoisting: the automorphism is
+ * a permutation of the evaluation domain that commutes with the key
+ * product, so the extended digits of c1 are computed once and permuted per
+ * rotation; double hoisting is named in Sec. VII).  Rotation r:
+ *   acc_s = sum_j sigma_r(y_j) * evk_r[j][s]   (ModUp P4/P5 on permuted digits)
+ *   out_r = (ModDown(acc_0) + sigma_r(c0), ModDown(acc_1))
+ * where y_j are the ModUp P1-P3 outputs of c1.  evk_r switches from
+ * sigma_r(s) to s.  evks: count keys one after the other; outs: count
+ * outputs [2][level+1][N]. */
+int oracle_rotate_hoisted(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                          const uint32_t *c1, uint32_t count, const uint32_t *galois, const uint32_t *evks,
+                          uint32_t *outs) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, level) != 0) return -1;
+  const uint32_t n = c.n, l1 = level + 1, T = c.ntow, D = c.ndig, EL = c.L1 + c.K;
+  const size_t evk_words = (size_t)p->dnum * 2 * EL * n;
+  for (uint32_t r = 0; r < count; r++)
+    if ((galois[r] & 1u) == 0 || galois[r] >= 2 * n) return -1;
+  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)D * T * n);
+  uint32_t *acc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)2 * T * n);
+  uint32_t *tgt = (uint32_t *)malloc(sizeof(uint32_t) * T * n);
+  uint32_t *tq = (uint32_t *)malloc(sizeof(uint32_t) * T);
+  uint32_t *perm = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  if (!x || !y || !acc || !tgt || !tq || !perm) {
+    free(x); free(y); free(acc); free(tgt); free(tq); free(perm);
+    return -1;
+  }
+  modup(&c, c1, x, y, tgt, tq);
+  for (uint32_t r = 0; r < count; r++) {
+    const uint32_t *evk = evks + r * evk_words;
+    uint32_t *out = outs + (size_t)r * 2 * l1 * n;
+    memset(acc, 0, sizeof(uint32_t) * (size_t)2 * T * n);
+    for (uint32_t j = 0; j < D; j++)
+      for (uint32_t t = 0; t < T; t++) {
+        if (g_fault == 1 && j == D - 1 && D > 1) continue;
+        oracle_automorphism_eval(LIMB(y, (size_t)j * T + t, n), c.log_n, galois[r], perm);
+        if (g_fault == 5) { /* the inverse permutation: scatter where a gather belongs */
+          for (uint32_t z = 0; z < n; z++) perm[z] = 0;
+          for (uint32_t z = 0; z < n; z++) {
+            const uint32_t e2 = (uint32_t)(((uint64_t)galois[r] * (2 * oracle_bitrev(z, c.log_n) + 1)) % (2 * n));
+            perm[oracle_bitrev((e2 - 1) / 2, c.log_n)] = LIMB(y, (size_t)j * T + t, n)[z];
+          }
+        }
+        for (uint32_t s = 0; s < 2; s++) {
+          const uint32_t *ek = evk + (((size_t)j * 2 + s) * EL + c.evk_limb[t]) * n;
+          uint32_t *aa = LIMB(acc, (size_t)s * T + t, n);
+          for (uint32_t z = 0; z < n; z++) aa[z] = addmod(aa[z], mulmod(perm[z], ek[z], c.q[t]), c.q[t]);
+        }
+      }
+    for (uint32_t s = 0; s < 2; s++) moddown(&c, LIMB(acc, (size_t)s * T, n), LIMB(out, (size_t)s * l1, n));
+    for (uint32_t i = 0; i < l1; i++) {
+      oracle_automorphism_eval(LIMB(c0, i, n), c.log_n, galois[r], perm);
+      for (uint32_t z = 0; z < n; z++) LIMB(out, i, n)[z] = addmod(LIMB(out, i, n)[z], perm[z], c.q[i]);
+    }
+  }
+  free(x); free(y); free(acc); free(tgt); free(tq); free(perm);
+  return 0;
+}
+
+/* One rotation without hoisting: permute c0 and c1, key-switch sigma(c1),
+ * add sigma(c0).  A different, equally valid result (the ModUp of sigma(c1)
+ * differs from sigma of the ModUp of c1 by multiples of Q_j). */
+int oracle_rotate(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                  const uint32_t *c1, uint32_t galois, const uint32_t *evk, uint32_t *out) {
+  const uint32_t n = 1u << p->log_n, l1 = level + 1;
+  if ((galois & 1u) == 0 || galois >= 2 * n || level >= p->num_q) return -1;
+  uint32_t *sc1 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  uint32_t *sc0 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  if (!sc1 || !sc0) { free(sc1); free(sc0); return -1; }
+  int rc = 0;
+  for (uint32_t i = 0; i < l1; i++) {
+    rc |= oracle_automorphism_eval(LIMB(c1, i, n), p->log_n, galois, LIMB(sc1, i, n));
+    rc |= oracle_automorphism_eval(LIMB(c0, i, n), p->log_n, galois, LIMB(sc0, i, n));
+  }
+  if (rc == 0) rc = oracle_keyswitch(p, moduli, level, evk, sc1, out);
+  for (uint32_t i = 0; rc == 0 && i < l1; i++)
+    for (uint32_t z = 0; z < n; z++) LIMB(out, i, n)[z] = addmod(LIMB(out, i, n)[z], LIMB(sc0, i, n)[z], moduli[i]);
+  free(sc1); free(sc0);
+  return rc;
+}
+
+/* Multiplication with relinearisation: the tensor product of (a0, a1) and
+ * (b0, b1) (pointwise in the evaluation domain) is d0 = a0 b0,
+ * d1 = a0 b1 + a1 b0, d2 = a1 b1, decryptable with (1, s, s^2); the key
+ * switch of d2 with a key from s^2 to s brings it back:
+ * out = (d0 + KS(d2)_0, d1 + KS(d2)_1). */
+int oracle_mult_relin(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *a0,
+                      const uint32_t *a1, const uint32_t *b0, const uint32_t *b1, const uint32_t *evk, uint32_t *out) {
+  const uint32_t n = 1u << p->log_n, l1 = level + 1;
+  if (level >= p->num_q) return -1;
+  uint32_t *d = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)3 * l1 * n);
+  if (!d) return -1;
+  for (uint32_t i = 0; i < l1; i++) {
+    const uint32_t q = moduli[i];
+    for (uint32_t z = 0; z < n; z++) {
+      const size_t w = (size_t)i * n + z;
+      d[w] = mulmod(a0[w], b0[w], q);
+      d[(size_t)l1 * n + w] = addmod(mulmod(a0[w], b1[w], q), mulmod(a1[w], b0[w], q), q);
+      d[(size_t)2 * l1 * n + w] = mulmod(a1[w], b1[w], q);
+    }
+  }
+  int rc = oracle_keyswitch(p, moduli, level, evk, d + (size_t)2 * l1 * n, out);
+  for (uint32_t h = 0; rc == 0 && h < 2; h++)
+    for (uint32_t i = 0; i < l1; i++)
+      for (uint32_t z = 0; z < n; z++) {
+        const size_t w = ((size_t)h * l1 + i) * n + z;
+        out[w] = addmod(out[w], d[w], moduli[i]);
+      }
+  free(d);
+  return rc;
+}
+
+static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int seeded, int mode,
+                       uint32_t galois, int8_t *s, int8_t *s2, uint32_t *evk) {
   ks_ctx c;
   if (ctx_init(&c, p, moduli, p->num_q - 1) != 0) return -1;
   const uint32_t n = c.n, EL = c.L1 + c.K;
@@ -499,6 +673,13 @@ static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t 
   int h = 0;
   for (uint32_t z = 0; z < n; z++) { s[z] = (int8_t)((int)rng_below(&r, 3) - 1); h += s[z] != 0; }
   for (uint32_t z = 0; z < n; z++) s2[z] = (int8_t)((int)rng_below(&r, 3) - 1);
+  if (mode == KG_ROTATE) { /* s2 = s(X^k): coefficient i moves to i k mod 2N, negated past N */
+    const uint32_t two_n = 2 * n;
+    for (uint32_t i = 0; i < n; i++) {
+      const uint32_t e = (uint32_t)(((uint64_t)i * galois) % two_n);
+      if (e < n) s2[e] = s[i]; else s2[e - n] = (int8_t)-s[i];
+    }
+  }
   uint32_t *sh = (uint32_t *)malloc(sizeof(uint32_t) * n), *s2h = (uint32_t *)malloc(sizeof(uint32_t) * n);
   uint32_t *eh = (uint32_t *)malloc(sizeof(uint32_t) * n);
   int32_t *e = (int32_t *)malloc(sizeof(int32_t) * n);
@@ -511,6 +692,8 @@ static int keygen_impl(const oracle_params *p, const uint32_t *moduli, uint64_t 
       for (uint32_t z = 0; z < n; z++) { sh[z] = signed_mod(s[z], m); s2h[z] = signed_mod(s2[z], m); eh[z] = signed_mod(e[z], m); }
       oracle_ntt(sh, c.log_n, m, c.psi[g]);
       oracle_ntt(s2h, c.log_n, m, c.psi[g]);
+      if (mode == KG_RELIN) /* s^2 in the evaluation domain is the pointwise square */
+        for (uint32_t z = 0; z < n; z++) s2h[z] = mulmod(sh[z], sh[z], m);
       oracle_ntt(eh, c.log_n, m, c.psi[g]);
       uint32_t gad = 0; /* [P]_m on digit j's own q-limbs */
       if (g >= lo && g < hi) {

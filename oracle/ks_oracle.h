@@ -97,6 +97,31 @@ int oracle_seeded_a(const oracle_params *p, const uint32_t *moduli, uint64_t a_s
 int oracle_keygen_seeded(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint64_t a_seed,
                          int8_t *s, int8_t *s2, uint32_t *evk);
 
+/* Callers of the key switch (Sec. II: rotations and multiplications need
+ * it).  Galois element k: odd, below 2N.
+ * oracle_automorphism_coeff: a(X^k) of a coefficient-domain limb.
+ * oracle_automorphism_eval: the same map on an evaluation-domain limb, a
+ * permutation of the slots (modulus-independent).
+ * oracle_keygen_rotation: key switching from s(X^k) to s (s2 returns s(X^k)).
+ * oracle_keygen_relin: key switching from s^2 to s.
+ * oracle_rotate_hoisted: count rotations of (c0, c1) sharing one ModUp of
+ * c1; evks [count][dnum][2][L+1+K][N], outs [count][2][level+1][N].
+ * oracle_rotate: one rotation, permute then key-switch (cross-check).
+ * oracle_mult_relin: tensor product then key switch of d2, out [2][l+1][N].
+ * All return 0 (keygen: the Hamming weight of s) or -1 on bad arguments. */
+int oracle_automorphism_coeff(const uint32_t *a, uint32_t log_n, uint32_t galois, uint32_t q, uint32_t *out);
+int oracle_automorphism_eval(const uint32_t *a, uint32_t log_n, uint32_t galois, uint32_t *out);
+int oracle_keygen_rotation(const oracle_params *p, const uint32_t *moduli, uint64_t seed, uint32_t galois,
+                           int8_t *s, int8_t *s2, uint32_t *evk);
+int oracle_keygen_relin(const oracle_params *p, const uint32_t *moduli, uint64_t seed, int8_t *s, uint32_t *evk);
+int oracle_rotate_hoisted(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                          const uint32_t *c1, uint32_t count, const uint32_t *galois, const uint32_t *evks,
+                          uint32_t *outs);
+int oracle_rotate(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                  const uint32_t *c1, uint32_t galois, const uint32_t *evk, uint32_t *out);
+int oracle_mult_relin(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *a0,
+                      const uint32_t *a1, const uint32_t *b0, const uint32_t *b1, const uint32_t *evk, uint32_t *out);
+
 /* Test hook: plant a deliberate mistake in the oracle's key switch so tests
  * can show their checks catch it.  0 = none; see ks_oracle.c for the list. */
 void oracle_set_fault(int fault);
