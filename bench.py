@@ -185,6 +185,60 @@ def seeded_rate(ks, plan, evks, d, steps, warmup, count, np, torch, synth):
     return res
 
 
+def rotation_rate(ks, plan, evks, steps, np, torch, synth):
+    """Hoisted rotations of one ciphertext of the bench workload: m rotations
+    sharing one ModUp of c1 (keys rotating over the full-key copies) against
+    the same m rotations one call each, and multiplication with
+    relinearisation; rotations/s and multiplications/s."""
+    n, l1 = plan.n, LEVEL + 1
+    mods = plan.moduli
+    c0 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 400)).view(np.int32)).cuda()
+    c1 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 401)).view(np.int32)).cuda()
+    plan.configure("oc", tile_towers=1, batch_mode=1)
+    res = {"hoisted": {}, "one_at_a_time": {}}
+    for m in (1, 4, 8):
+        gal = [ks.galois_rotation(LOG_N, r + 1) for r in range(m)]
+        rots = [(evks[i % len(evks)], g) for i, g in enumerate(gal)]
+        ws = plan._ws(ks.ks_rotate_workspace_size(plan.handle, LEVEL, m), "cuda")
+        wsm = plan._ws(ks.ks_rotate_workspace_size(plan.handle, LEVEL, 1), "cuda")
+        outs = [torch.empty((2, l1, n), dtype=torch.int32, device="cuda") for _ in range(m)]
+        reps = max(5, steps // (4 * m))
+        for name, hoist in (("hoisted", True), ("one_at_a_time", False)):
+            def once():
+                if hoist:
+                    ks.ks_rotate_hoisted(plan.handle, LEVEL, c0, c1, [(e, g, o) for (e, g), o in zip(rots, outs)], ws)
+                else:
+                    for (e, g), o in zip(rots, outs):
+                        ks.ks_rotate_hoisted(plan.handle, LEVEL, c0, c1, [(e, g, o)], wsm)
+            once()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                once()
+            b.record()
+            torch.cuda.synchronize()
+            res[name][f"m{m}"] = round(m * reps / (a.elapsed_time(b) / 1e3), 1)
+    res["hoisting_gain_m8"] = round(res["hoisted"]["m8"] / res["one_at_a_time"]["m8"], 3)
+    a0, a1 = c0, c1
+    b0 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 402)).view(np.int32)).cuda()
+    b1 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 403)).view(np.int32)).cuda()
+    out = torch.empty((2, l1, n), dtype=torch.int32, device="cuda")
+    wsr = plan._ws(ks.ks_mult_workspace_size(plan.handle, LEVEL), "cuda")
+    reps = max(10, steps // 2)
+    for i in range(5):
+        plan.mult_relin(evks[i % len(evks)], LEVEL, a0, a1, b0, b1, out=out, workspace=wsr)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(reps):
+        plan.mult_relin(evks[i % len(evks)], LEVEL, a0, a1, b0, b1, out=out, workspace=wsr)
+    b.record()
+    torch.cuda.synchronize()
+    res["mult_relin_per_s"] = round(reps / (a.elapsed_time(b) / 1e3), 1)
+    return res
+
+
 def mixed_rate(ks, dnum, reps, np, torch, synth):
     """64 ciphertexts at levels with l+1 ~ U[8, 24], N=2^16, K = alpha, one
     shared key: OC batched vs the same 64 switched one at a time with MP."""
@@ -298,6 +352,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=16,
                     help="ciphertexts per call in the batched measurement of the same workload (0 = skip)")
     ap.add_argument("--seeded", type=int, default=1, help="also time compressed keys (0: skip)")
+    ap.add_argument("--rotations", type=int, default=1, help="also time hoisted rotations and HMult (0: skip)")
     ap.add_argument("--mixed", action="store_true",
                     help="also time 64-ciphertext batches at levels l+1 ~ U[8,24] for dnum 2, 3, 4")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -432,6 +487,8 @@ def main():
     res["stages"] = stages
     if args.batch:
         res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)
+    if args.rotations:
+        res["rotations"] = rotation_rate(ks, plan, evks, args.steps, np, torch, synth)
     if args.seeded:
         res["key_compression"] = seeded_rate(ks, plan, evks, d, args.steps, args.warmup, args.batch or 16, np,
                                              torch, synth)

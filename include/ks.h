@@ -194,6 +194,62 @@ ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_s
  * computed from a) and for schedules that take full keys only. */
 ks_status_t ks_expand_seeded_a(ks_plan_t plan, uint64_t a_seed, uint32_t *evk, void *stream);
 
+/* ----------------------------------------------------------------------
+ * Callers of the key switch (Sec. II: rotations and multiplications are
+ * what need it).  Galois element k of the automorphism X -> X^k: odd and
+ * below 2N (rotation by r slots: k = 5^r mod 2N; conjugation: 2N - 1).
+ * In the evaluation domain (slot j holds the value at psi^(2 brv(j) + 1))
+ * the automorphism is the permutation out[j] = in[pi(j)] with
+ * 2 brv(pi(j)) + 1 = k (2 brv(j) + 1) mod 2N, the same for every modulus.
+ * ---------------------------------------------------------------------- */
+
+/* out[c] = automorphism of in[c] for `count` limbs [count][N] (device,
+ * 4-byte aligned, out not overlapping in). */
+ks_status_t ks_automorphism(ks_plan_t plan, uint32_t galois, uint32_t count, const uint32_t *in,
+                            uint32_t *out, void *stream);
+
+/* One rotation of a hoisted group: its key evk [dnum][2][L+1+K][N] switches
+ * from s(X^galois) to s; out [2][level+1][N] receives the rotated ciphertext
+ * (device pointers). */
+typedef struct {
+  const uint32_t *evk;
+  uint32_t galois;
+  uint32_t *out;
+} ks_rotation_t;
+
+/* Bytes of workspace ks_rotate_hoisted needs for `count` rotations at
+ * `level` (0 for count 0). */
+ks_status_t ks_rotate_workspace_size(ks_plan_t plan, uint32_t level, uint32_t count, size_t *bytes);
+
+/* Hoisted rotations of the ciphertext (c0, c1) [level+1][N] each (device,
+ * evaluation domain): ModUp of c1 (Sec. III-B P1-P3) runs once and every
+ * rotation r reuses it (hoisting; double hoisting is named in Sec. VII):
+ *   acc = sum_j sigma_r(ModUp_j(c1)) * evk_r[j]      (P4, P5)
+ *   out_r = (ModDown(acc_0) + sigma_r(c0), ModDown(acc_1))
+ * where sigma_r is the evaluation-domain automorphism.  The permutation is
+ * applied inside the row stages of the Output-Centric order (a row of 256
+ * slots maps onto one row), so nothing is permuted in memory.  OC schedule
+ * only (KS_ERR_UNSUPPORTED otherwise).  Outputs must not overlap each
+ * other, c0, c1, any key or the workspace; the workspace (>=
+ * ks_rotate_workspace_size, 256-byte aligned) must not overlap c0, c1 or a
+ * key. */
+ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                              uint32_t count, const ks_rotation_t *rots, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/* Bytes of workspace ks_mult_relin needs at `level`. */
+ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes);
+
+/* Multiplication with relinearisation (Sec. II): the tensor product of
+ * (a0, a1) and (b0, b1) ([level+1][N] each, device, evaluation domain),
+ * d = (a0 b0, a0 b1 + a1 b0, a1 b1), then out = (d0, d1) + KS(d2) with evk
+ * [dnum][2][L+1+K][N] switching from s^2 to s; the additions are fused into
+ * the key switch's last stage.  out [2][level+1][N] must not overlap an
+ * input, the key or the workspace.  OC schedule only. */
+ks_status_t ks_mult_relin(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *a0,
+                          const uint32_t *a1, const uint32_t *b0, const uint32_t *b1, uint32_t *out,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
 /* After a batch: waits for `stream`, then sets *error_flag to 1 if a
  * dependency wait of the persistent launch exceeded its spin limit (the
  * outputs of that batch are then invalid), else 0. */

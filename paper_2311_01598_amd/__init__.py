@@ -47,6 +47,10 @@ class ks_seeded_job_t(ctypes.Structure):
                 ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class ks_rotation_t(ctypes.Structure):
+    _fields_ = [("evk", ctypes.c_void_p), ("galois", ctypes.c_uint32), ("out", ctypes.c_void_p)]
+
+
 _U32P = ctypes.POINTER(ctypes.c_uint32)
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -66,6 +70,14 @@ _SIGS = {
     "ks_keyswitch_batch_seeded": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_seeded_job_t), _VP,
                                                  ctypes.c_size_t, _VP]),
     "ks_expand_seeded_a": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
+    "ks_automorphism": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP]),
+    "ks_rotate_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "ks_rotate_hoisted": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
+                                         ctypes.POINTER(ks_rotation_t), _VP, ctypes.c_size_t, _VP]),
+    "ks_mult_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ks_mult_relin": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                     _VP]),
     "ks_batch_status": (ctypes.c_int, [_VP, _VP, _VP, _U32P]),
     "ks_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
     "ks_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -251,6 +263,47 @@ def ks_expand_seeded_a(plan, a_seed, evk, stream=None):
            "ks_expand_seeded_a")
 
 
+def ks_automorphism(plan, galois, count, inp, out, stream=None):
+    _check(_lib.ks_automorphism(plan, int(galois), int(count), _ptr(inp), _ptr(out), _stream(stream)),
+           "ks_automorphism")
+
+
+def ks_rotate_workspace_size(plan, level, count):
+    n = ctypes.c_size_t(0)
+    _check(_lib.ks_rotate_workspace_size(plan, int(level), int(count), ctypes.byref(n)), "ks_rotate_workspace_size")
+    return n.value
+
+
+def ks_rotate_hoisted(plan, level, c0, c1, rots, workspace, workspace_bytes=None, stream=None):
+    """rots: list of (evk, galois, out)."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_rotation_t * max(len(rots), 1))()
+    for i, (evk, galois, out) in enumerate(rots):
+        arr[i] = ks_rotation_t(_ptr(evk), int(galois), _ptr(out))
+    _check(_lib.ks_rotate_hoisted(plan, int(level), _ptr(c0), _ptr(c1), len(rots), arr, _ptr(workspace),
+                                  int(workspace_bytes), _stream(stream)), "ks_rotate_hoisted")
+
+
+def ks_mult_workspace_size(plan, level):
+    n = ctypes.c_size_t(0)
+    _check(_lib.ks_mult_workspace_size(plan, int(level), ctypes.byref(n)), "ks_mult_workspace_size")
+    return n.value
+
+
+def ks_mult_relin(plan, evk, level, a0, a1, b0, b1, out, workspace, workspace_bytes=None, stream=None):
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.ks_mult_relin(plan, _ptr(evk), int(level), _ptr(a0), _ptr(a1), _ptr(b0), _ptr(b1), _ptr(out),
+                              _ptr(workspace), int(workspace_bytes), _stream(stream)), "ks_mult_relin")
+
+
+def galois_rotation(log_n, r):
+    """Galois element of a rotation by r slots: 5^r mod 2N."""
+    two_n = 2 << log_n
+    return pow(5, r % (two_n // 4), two_n)
+
+
 def ks_ntt(plan, g, inverse, data, stream=None):
     arr = _u32_array(g)
     _check(_lib.ks_ntt(plan, len(g), arr, int(bool(inverse)), _ptr(data), _stream(stream)), "ks_ntt")
@@ -362,6 +415,41 @@ class Plan:
 
     def expand_seeded_a(self, a_seed, evk, stream=None):
         ks_expand_seeded_a(self.handle, a_seed, evk, stream=stream)
+
+    def _ws(self, nbytes, device):
+        import torch
+        return torch.empty((max(nbytes, 256) + 3) // 4, dtype=torch.int32, device=device)
+
+    def automorphism(self, x, galois, out=None, stream=None):
+        """Evaluation-domain automorphism X -> X^galois of every limb of x."""
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        ks_automorphism(self.handle, galois, x.numel() // self.n, x, out, stream=stream)
+        return out
+
+    def rotate_hoisted(self, level, c0, c1, rots, workspace=None, stream=None):
+        """rots: list of (evk, galois); returns the rotated ciphertexts
+        [2][level+1][N], one per rotation, sharing one ModUp of c1."""
+        import torch
+        outs = [torch.empty((2, level + 1, self.n), dtype=torch.int32, device=c1.device) for _ in rots]
+        if workspace is None:
+            workspace = self._ws(ks_rotate_workspace_size(self.handle, level, len(rots)), c1.device)
+        ks_rotate_hoisted(self.handle, level, c0, c1, [(e, g, o) for (e, g), o in zip(rots, outs)], workspace,
+                          stream=stream)
+        return outs
+
+    def rotate(self, evk, galois, level, c0, c1, workspace=None, stream=None):
+        return self.rotate_hoisted(level, c0, c1, [(evk, galois)], workspace, stream)[0]
+
+    def mult_relin(self, evk, level, a0, a1, b0, b1, out=None, workspace=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int32, device=a0.device)
+        if workspace is None:
+            workspace = self._ws(ks_mult_workspace_size(self.handle, level), a0.device)
+        ks_mult_relin(self.handle, evk, level, a0, a1, b0, b1, out, workspace, stream=stream)
+        return out
 
     def ntt(self, data, g, inverse=False, stream=None):
         ks_ntt(self.handle, list(g), inverse, data, stream=stream)

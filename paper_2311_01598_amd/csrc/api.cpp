@@ -57,6 +57,30 @@ BatchLayout batch_layout(const Plan &pl, uint32_t count, const uint32_t *levels)
   return b;
 }
 
+// Hoisted rotations: job table, the shared ModUp output (xt, ycol), then
+// the ModDown regions (zp, wcol) of every rotation.
+struct RotLayout {
+  size_t xt, ycol, rot0, per_rot, total;
+};
+RotLayout rot_layout(const Plan &pl, uint32_t level, uint32_t count) {
+  const size_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), lb = limb_bytes(pl);
+  RotLayout r;
+  r.xt = align256((size_t)count * sizeof(OcJob));
+  r.ycol = r.xt + align256(L1 * lb);
+  r.rot0 = r.ycol + align256(D * T * lb);
+  r.per_rot = align256((2 * K + 2 * L1) * lb);
+  r.total = count ? r.rot0 + (size_t)count * r.per_rot : 0;
+  return r;
+}
+
+// Multiplication: the tensor product d [3][l+1][N], then one OC region.
+size_t mult_tensor_bytes(const Plan &pl, uint32_t level) { return align256((size_t)3 * (level + 1) * limb_bytes(pl)); }
+size_t mult_bytes(const Plan &pl, uint32_t level) {
+  return mult_tensor_bytes(pl, level) + ws_limbs(pl, KS_SCHED_OC, level) * limb_bytes(pl);
+}
+
+bool galois_ok(const Plan &pl, uint32_t k) { return (k & 1u) && k < 2u * pl.n; }
+
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
   const char *x = (const char *)a, *y = (const char *)b;
   return x < y + nb && y < x + na;
@@ -173,6 +197,7 @@ OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
   j.zp = j.ycol + (size_t)D * T * N;
   j.wcol = j.zp + (size_t)2 * K * N;
   j.a_seed = jb.a_seed;
+  j.galois = 1;
   j.ttu = j.ttd = tt;
   oc_tiles_host(pl, level, tt, j.tiles);
   return j;
@@ -183,7 +208,8 @@ uint32_t oc_tt(const Plan &pl) { return oc_effective_tt(pl.dev.loga, pl.cfg.tile
 ks_status_t run_oc(const Plan &pl, const Job &jb, bool seeded, uint32_t *ws, hipStream_t st) {
   const uint32_t tt = oc_tt(pl);
   const OcJob j = make_oc_job(pl, jb, ws, tt);
-  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, seeded, st));
+  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, seeded ? OC_ROWS_SEEDED : OC_ROWS_PLAIN,
+                                  OC_PART_ALL, st));
 }
 
 // Compressed keys are supported by the OC schedule only (callers check).
@@ -220,8 +246,9 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
     return dev_err(launch_oc_persistent(pl, djobs, (const OcSeg *)(ws + lay.segs), count * OC_NPHASE, total, count,
                                         (uint32_t *)(ws + lay.ctl), spin, st));
   const OcJob none{};
+  const OcRowVariant rows = seeded ? OC_ROWS_SEEDED : OC_ROWS_PLAIN;
   if (mode != 3 || count < 2)
-    return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, seeded, st));
+    return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, rows, OC_PART_ALL, st));
   // Mode 3: the batch runs as two halves, the second on the plan's side stream:
   // the halves drift apart, so a bandwidth-bound phase of one overlaps a
   // compute-bound phase of the other.  (Each half launches with the batch's
@@ -232,8 +259,8 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
   TRY(hipEventRecord(f->fork, st));
   TRY(hipStreamWaitEvent(f->side, f->fork, 0));
   const uint32_t h = count / 2;
-  TRY(launch_oc_phases(pl, none, djobs, h, max_tiles.data(), tt, seeded, st));
-  TRY(launch_oc_phases(pl, none, djobs + h, count - h, max_tiles.data(), tt, seeded, f->side));
+  TRY(launch_oc_phases(pl, none, djobs, h, max_tiles.data(), tt, rows, OC_PART_ALL, st));
+  TRY(launch_oc_phases(pl, none, djobs + h, count - h, max_tiles.data(), tt, rows, OC_PART_ALL, f->side));
   TRY(hipEventRecord(f->join, f->side));
   TRY(hipStreamWaitEvent(st, f->join, 0));
   return KS_OK;
@@ -582,6 +609,114 @@ ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_s
   std::vector<Job> jb(count);
   for (uint32_t i = 0; i < count; i++) jb[i] = Job{jobs[i].evk_b, jobs[i].a_seed, jobs[i].level, jobs[i].in, jobs[i].out};
   return keyswitch_batch(plan, jb, true, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_automorphism(ks_plan_t plan, uint32_t galois, uint32_t count, const uint32_t *in, uint32_t *out,
+                            void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  if (!galois_ok(pl, galois)) return KS_ERR_INVALID_ARG;
+  if (!count) return KS_OK;
+  if (!in || !out || (((uintptr_t)in | (uintptr_t)out) & 3)) return KS_ERR_INVALID_ARG;
+  const size_t b = (size_t)count * limb_bytes(pl);
+  if (overlaps(in, b, out, b)) return KS_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  return dev_err(launch_automorphism(pl, galois, count, in, out, (hipStream_t)stream));
+}
+
+ks_status_t ks_rotate_workspace_size(ks_plan_t plan, uint32_t level, uint32_t count, size_t *bytes) {
+  if (!plan || !bytes || level >= plan->p.num_q) return KS_ERR_INVALID_ARG;
+  *bytes = rot_layout(plan->p, level, count).total;
+  return KS_OK;
+}
+
+ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1, uint32_t count,
+                              const ks_rotation_t *rots, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  Plan &pl = plan->p;
+  if (effective(pl) != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
+  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  if (!count) return KS_OK;
+  if (!rots || !c0 || !c1 || !workspace) return KS_ERR_INVALID_ARG;
+  if ((((uintptr_t)c0 | (uintptr_t)c1) & 15) || ((uintptr_t)workspace & 255)) return KS_ERR_INVALID_ARG;
+  const RotLayout lay = rot_layout(pl, level, count);
+  if (workspace_bytes < lay.total) return KS_ERR_BUDGET;
+  const size_t lb = limb_bytes(pl), in_b = (size_t)(level + 1) * lb, out_b = 2 * in_b;
+  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb;
+  if (overlaps(workspace, workspace_bytes, c0, in_b) || overlaps(workspace, workspace_bytes, c1, in_b))
+    return KS_ERR_INVALID_ARG;
+  for (uint32_t r = 0; r < count; r++) {
+    const ks_rotation_t &x = rots[r];
+    if (!x.evk || !x.out || (((uintptr_t)x.evk | (uintptr_t)x.out) & 15) || !galois_ok(pl, x.galois))
+      return KS_ERR_INVALID_ARG;
+    if (overlaps(x.out, out_b, c0, in_b) || overlaps(x.out, out_b, c1, in_b) ||
+        overlaps(x.out, out_b, workspace, workspace_bytes) || overlaps(workspace, workspace_bytes, x.evk, evk_b))
+      return KS_ERR_INVALID_ARG;
+    for (uint32_t u = 0; u < count; u++)
+      if (overlaps(x.out, out_b, rots[u].evk, evk_b) || (u != r && overlaps(x.out, out_b, rots[u].out, out_b)))
+        return KS_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  const uint32_t tt = oc_tt(pl);
+  std::vector<OcJob> hj(count);
+  for (uint32_t r = 0; r < count; r++) {
+    OcJob &j = hj[r];
+    j = make_oc_job(pl, Job{rots[r].evk, 0, level, c1, rots[r].out}, (uint32_t *)(ws + lay.xt), tt);
+    j.xt = (uint32_t *)(ws + lay.xt);  // shared: one ModUp for every rotation
+    j.ycol = (uint32_t *)(ws + lay.ycol);
+    j.zp = (uint32_t *)(ws + lay.rot0 + r * lay.per_rot);
+    j.wcol = j.zp + (size_t)2 * pl.num_p * pl.n;
+    j.galois = rots[r].galois;
+    j.add0 = c0;
+  }
+  TRY(upload_async(pl, ws, hj.data(), hj.size() * sizeof(OcJob), st));
+  const OcJob none{};
+  const OcJob *djobs = (const OcJob *)ws;
+  TRY(launch_oc_phases(pl, none, djobs, 1, hj[0].tiles, tt, OC_ROWS_EXT, OC_PART_MODUP, st));
+  return dev_err(launch_oc_phases(pl, none, djobs, count, hj[0].tiles, tt, OC_ROWS_EXT, OC_PART_REST, st));
+}
+
+ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes) {
+  if (!plan || !bytes || level >= plan->p.num_q) return KS_ERR_INVALID_ARG;
+  *bytes = mult_bytes(plan->p, level);
+  return KS_OK;
+}
+
+ks_status_t ks_mult_relin(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *a0, const uint32_t *a1,
+                          const uint32_t *b0, const uint32_t *b1, uint32_t *out, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  if (effective(pl) != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
+  if (level >= pl.num_q || !evk || !a0 || !a1 || !b0 || !b1 || !out || !workspace) return KS_ERR_INVALID_ARG;
+  if ((((uintptr_t)evk | (uintptr_t)a0 | (uintptr_t)a1 | (uintptr_t)b0 | (uintptr_t)b1 | (uintptr_t)out) & 15) ||
+      ((uintptr_t)workspace & 255))
+    return KS_ERR_INVALID_ARG;
+  if (workspace_bytes < mult_bytes(pl, level)) return KS_ERR_BUDGET;
+  const size_t lb = limb_bytes(pl), in_b = (size_t)(level + 1) * lb, out_b = 2 * in_b;
+  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb;
+  const void *ins[4] = {a0, a1, b0, b1};
+  for (const void *x : ins)
+    if (overlaps(out, out_b, x, in_b) || overlaps(workspace, workspace_bytes, x, in_b)) return KS_ERR_INVALID_ARG;
+  if (overlaps(out, out_b, evk, evk_b) || overlaps(out, out_b, workspace, workspace_bytes) ||
+      overlaps(workspace, workspace_bytes, evk, evk_b))
+    return KS_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t *d = (uint32_t *)workspace;
+  const size_t limbs = (size_t)(level + 1) * pl.n;
+  TRY(launch_tensor(pl, level, a0, a1, b0, b1, d, st));
+  const uint32_t tt = oc_tt(pl);
+  OcJob j = make_oc_job(pl, Job{evk, 0, level, d + 2 * limbs, out},
+                        (uint32_t *)((char *)workspace + mult_tensor_bytes(pl, level)), tt);
+  j.add0 = d;
+  j.add1 = d + limbs;
+  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, OC_ROWS_EXT, OC_PART_ALL, st));
 }
 
 ks_status_t ks_expand_seeded_a(ks_plan_t plan, uint64_t a_seed, uint32_t *evk, void *stream) {

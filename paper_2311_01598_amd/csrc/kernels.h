@@ -50,6 +50,14 @@ hipError_t launch_moddown_final(const Plan &pl, uint32_t level, const uint32_t *
 // Compressed keys: writes the a half of every pair of the full-layout key evk
 // [dnum][2][L+1+K][N] from the seed (the b halves are left as they are).
 hipError_t launch_expand_a(const Plan &pl, uint64_t seed, uint32_t *evk, hipStream_t st);
+// out[c][j] = in[c][pi(j)] for `count` limbs [count][N]: the automorphism
+// X -> X^galois in the evaluation domain.
+hipError_t launch_automorphism(const Plan &pl, uint32_t galois, uint32_t count, const uint32_t *in, uint32_t *out,
+                               hipStream_t st);
+// Tensor product of (a0, a1) and (b0, b1) at `level`: d [3][l+1][N] =
+// (a0 b0, a0 b1 + a1 b0, a1 b1), pointwise, canonical.
+hipError_t launch_tensor(const Plan &pl, uint32_t level, const uint32_t *a0, const uint32_t *a1, const uint32_t *b0,
+                         const uint32_t *b1, uint32_t *d, hipStream_t st);
 
 // ------------------------------------------------------------ Output-Centric
 // Phases in issue order (see oc_kernels.h).
@@ -64,20 +72,35 @@ constexpr uint32_t OC_UP_PQ = OC_NPHASE;
 // read only the b halves and regenerate the a halves from the job's seed.
 constexpr uint32_t OC_ROW_P_SEEDED = OC_NPHASE + 1;
 constexpr uint32_t OC_ROW_Q_SEEDED = OC_NPHASE + 2;
+// Launch-only phases: ROW_P / ROW_Q for the callers of the key switch
+// (rotation, multiplication): the digits are read through the job's
+// automorphism and ROW_Q adds the job's addends to its output.
+constexpr uint32_t OC_ROW_P_EXT = OC_NPHASE + 3;
+constexpr uint32_t OC_ROW_Q_EXT = OC_NPHASE + 4;
+
+// Which row-stage kernels a launch uses.
+enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT };
+// Which phases a launch sequence runs: all, ModUp only (INTT_ROW .. UP_PQ),
+// or the rest (ROW_P .. ROW_Q) on the ModUp output of an earlier launch.
+enum OcPart : uint32_t { OC_PART_ALL = 0, OC_PART_MODUP, OC_PART_REST };
 
 // One key switch as the OC kernels see it (device-visible, by value or in a
 // job table).  Workspace regions: xt [l+1][N] ModUp P1 output, ycol
 // [ndig][T][N] column-pass output of ModUp P2/P3, zp [2][K][N] ModDown P1,
 // wcol [2][l+1][N] column-pass output of ModDown P2/P3.  evk is the full key
 // [dnum][2][L+1+K][N], or for a compressed key its b halves [dnum][L+1+K][N]
-// with a_seed regenerating the a halves (the seeded row phases).
+// with a_seed regenerating the a halves (the seeded row phases).  The
+// extended row phases read digit word j of a row at the automorphism's
+// pi(j) (galois = k of X -> X^k, 1 = none) and add add0[t][pi(j)] and
+// add1[t][pi(j)] ([l+1][N] each, either may be null) to the two outputs.
 struct OcJob {
   const uint32_t *d;
   const uint32_t *evk;
   uint32_t *out;
   uint32_t *xt, *ycol, *zp, *wcol;
+  const uint32_t *add0, *add1;
   uint64_t a_seed;
-  uint32_t level, ttu, ttd, pad;
+  uint32_t level, ttu, ttd, galois;
   uint32_t tiles[OC_NPHASE];  // tile count of every phase for this job
 };
 
@@ -119,17 +142,19 @@ __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint3
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want);
 // Tile counts of every phase (host).
 void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles);
-// One launch per phase; jobs == nullptr runs `one` alone.  seeded: every
-// job's key is compressed (b halves plus a_seed).
+// One launch per phase; jobs == nullptr runs `one` alone.  rows: the
+// row-stage kernels (plain, compressed keys, or extended); part: which
+// phases run.
 hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                            const uint32_t *max_tiles, uint32_t tt, bool seeded, hipStream_t st);
+                            const uint32_t *max_tiles, uint32_t tt, OcRowVariant rows, OcPart part,
+                            hipStream_t st);
 // Persistent work-queue launch (tiles of one target per conversion tile).
 hipError_t launch_oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs,
                                 uint32_t total, uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);
 
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
-                     uint32_t tt, bool seeded, hipStream_t st);
+                     uint32_t tt, OcRowVariant rows, OcPart part, hipStream_t st);
 template <int A>
 hipError_t oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs, uint32_t total,
                          uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);

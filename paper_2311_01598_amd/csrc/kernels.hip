@@ -394,6 +394,46 @@ hipError_t launch_expand_a(const Plan &pl, uint64_t seed, uint32_t *evk, hipStre
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ automorphism, tensor
+// grid (N/256, count)
+__global__ __launch_bounds__(256) void k_automorphism(DevPlan P, uint32_t galois, const uint32_t *__restrict__ in,
+                                                      uint32_t *__restrict__ out) {
+  const size_t N = (size_t)1 << P.log_n, c = blockIdx.y;
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  out[c * N + j] = in[c * N + galois_perm(j, galois, P.log_n)];
+}
+
+hipError_t launch_automorphism(const Plan &pl, uint32_t galois, uint32_t count, const uint32_t *in, uint32_t *out,
+                               hipStream_t st) {
+  if (!count) return hipSuccess;
+  KS_LAUNCH(pl, "automorphism", k_automorphism, dim3(pl.n / 256, count), dim3(256), 0, st, pl.dev, galois, in, out);
+  return hipGetLastError();
+}
+
+// grid (N/256, l+1); a b mod q as REDC(a b) = a b 2^-32, then times 2^32
+// mod q with a Shoup product
+__global__ __launch_bounds__(256) void k_tensor(DevPlan P, uint32_t level, const uint32_t *__restrict__ a0,
+                                                const uint32_t *__restrict__ a1, const uint32_t *__restrict__ b0,
+                                                const uint32_t *__restrict__ b1, uint32_t *__restrict__ d) {
+  const size_t N = (size_t)1 << P.log_n, l1 = level + 1;
+  const uint32_t i = blockIdx.y;
+  const size_t w = i * N + blockIdx.x * 256 + threadIdx.x;
+  const ModQ m = P.mods[i];
+  const uint32_t r32 = (0u - m.q) % m.q;  // 2^32 mod q
+  const uint32_t r32p = shoup_companion(r32, m.q, P.qrecip[i]);
+  const uint32_t x0 = a0[w], x1 = a1[w], y0 = b0[w], y1 = b1[w];
+  auto fin = [&](uint64_t t) { return csub(mul_shoup(redc64(t, m), r32, r32p, m.q), m.q); };
+  d[w] = fin((uint64_t)x0 * y0);
+  d[l1 * N + w] = fin((uint64_t)x0 * y1 + (uint64_t)x1 * y0);
+  d[2 * l1 * N + w] = fin((uint64_t)x1 * y1);
+}
+
+hipError_t launch_tensor(const Plan &pl, uint32_t level, const uint32_t *a0, const uint32_t *a1, const uint32_t *b0,
+                         const uint32_t *b1, uint32_t *d, hipStream_t st) {
+  KS_LAUNCH(pl, "tensor", k_tensor, dim3(pl.n / 256, level + 1), dim3(256), 0, st, pl.dev, level, a0, a1, b0, b1, d);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ OC entry
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want) {
   // two targets per tile keep 2 x 16 accumulators per thread; columns of
@@ -414,14 +454,15 @@ void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles)
 }
 
 hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                            const uint32_t *max_tiles, uint32_t tt, bool seeded, hipStream_t st) {
+                            const uint32_t *max_tiles, uint32_t tt, OcRowVariant rows, OcPart part,
+                            hipStream_t st) {
   switch (pl.dev.loga) {
-    case 4: return oc_phases<4>(pl, one, jobs, count, max_tiles, tt, seeded, st);
-    case 5: return oc_phases<5>(pl, one, jobs, count, max_tiles, tt, seeded, st);
-    case 6: return oc_phases<6>(pl, one, jobs, count, max_tiles, tt, seeded, st);
-    case 7: return oc_phases<7>(pl, one, jobs, count, max_tiles, tt, seeded, st);
-    case 8: return oc_phases<8>(pl, one, jobs, count, max_tiles, tt, seeded, st);
-    case 9: return oc_phases<9>(pl, one, jobs, count, max_tiles, tt, seeded, st);
+    case 4: return oc_phases<4>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
+    case 5: return oc_phases<5>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
+    case 6: return oc_phases<6>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
+    case 7: return oc_phases<7>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
+    case 8: return oc_phases<8>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
+    case 9: return oc_phases<9>(pl, one, jobs, count, max_tiles, tt, rows, part, st);
   }
   return hipErrorInvalidValue;
 }

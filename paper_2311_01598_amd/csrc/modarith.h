@@ -173,6 +173,17 @@ __device__ __forceinline__ void seeded_a4(uint32_t (&a)[4], uint64_t seed, uint3
   }
 }
 
+// The automorphism X -> X^k (k odd) in the evaluation domain: slot j holds
+// the value at psi^(2 brv(j) + 1), so the slot of a(X^k) takes a's slot
+// pi(j) with 2 brv(pi(j)) + 1 = k (2 brv(j) + 1) mod 2N.  (The product is
+// only needed modulo 2N, a power of two, so 32-bit wrap-around is exact.)
+// pi maps every aligned block of 2^b slots onto one aligned block.
+__device__ __forceinline__ uint32_t galois_perm(uint32_t j, uint32_t k, uint32_t log_n) {
+  const uint32_t e = 2u * (__brev(j) >> (32 - log_n)) + 1u;
+  const uint32_t e2 = (k * e) & ((2u << log_n) - 1u);
+  return __brev((e2 - 1u) >> 1) >> (32 - log_n);
+}
+
 // Harvey forward (Cooley-Tukey) butterfly, inputs and outputs in [0, 4q).
 // The forward twiddle tables hold (-w mod 2^32, w') so that the Shoup
 // product comes out negated: nt = h q + y (-w) = -(y w - h q) = -t mod 2^32

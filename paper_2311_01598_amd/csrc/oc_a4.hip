@@ -3,7 +3,7 @@
 
 namespace ks {
 template hipError_t oc_phases<4>(const Plan &, const OcJob &, const OcJob *, uint32_t, const uint32_t *, uint32_t,
-                                  bool, hipStream_t);
+                                  OcRowVariant, OcPart, hipStream_t);
 template hipError_t oc_persistent<4>(const Plan &, const OcJob *, const OcSeg *, uint32_t, uint32_t, uint32_t,
                                       uint32_t *, uint32_t, hipStream_t);
 }  // namespace ks

@@ -477,6 +477,7 @@ __device__ __forceinline__ uint32_t *row_buf(uint32_t *lds, int b, int r) { retu
 constexpr int kRowTw = 256;    // heap entries per row
 constexpr int kRowTwS = 260;   // LDS stride between rows (uint2)
 constexpr int kRowTileLds = kRowBufs * kPad + 2 * kRB4 * kRowTwS;
+constexpr int kRowTileLdsExt = kRowTileLds + 2 * kRB4 * kRowTwS;  // + the permuted rows' twiddles
 __device__ __forceinline__ uint2 *row_tw(uint32_t *lds) { return reinterpret_cast<uint2 *>(lds + kRowBufs * kPad); }
 __device__ __forceinline__ int row_tw_slot(int i) {  // LDS position of heap entry i in its row
   const int lvl = 31 - __clz(i | 1);
@@ -576,7 +577,7 @@ __device__ __forceinline__ void ld4_nt(uint32_t (&v)[4], const uint32_t *p) {
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
-template <bool IS_P, bool SEEDED>
+template <bool IS_P, bool SEEDED, bool EXT>
 __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
@@ -589,10 +590,25 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   const int k0 = 4 * (threadIdx.x & 63);  // element-wise part: words k0..k0+3 of the row
   const uint32_t row0 = blk * kRB4, m0 = (1u << P.loga) + row0;
   const size_t roff = (size_t)(row0 + r) * 256;
+  // EXT: digit word j of this row is read at pi(j) of the automorphism; pi
+  // maps the whole row onto row roff_s / 256, word k0 + i onto pofs[i]
+  // and the tile's 4 rows onto an aligned block of 4 rows from row rs0; a
+  // permuted row is transformed with its own row twiddles (second table)
+  size_t roff_s = roff;
+  uint32_t pofs[4] = {(uint32_t)k0, (uint32_t)k0 + 1, (uint32_t)k0 + 2, (uint32_t)k0 + 3};
+  uint32_t rs0 = 0;
+  if (EXT) {
+    roff_s = galois_perm((uint32_t)roff, J.galois, P.log_n) & ~255u;
+#pragma unroll
+    for (int i = 0; i < 4; i++) pofs[i] = galois_perm((uint32_t)roff + k0 + i, J.galois, P.log_n) & 255u;
+    rs0 = (galois_perm(row0 * 256u, J.galois, P.log_n) >> 8) & ~(uint32_t)(kRB4 - 1);
+  }
   const uint32_t ndig = cdiv(L1, P.alpha);
   const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;  // digit holding tower t (bypassed)
   uint2 *twl = row_tw(lds);
   const uint2 *twr = twl + r * kRowTwS;
+  uint2 *twl_s = twl + kRB4 * kRowTwS;  // EXT: twiddles of the permuted rows
+  const uint2 *twr_s = EXT ? twl_s + (uint32_t)((roff_s >> 8) - rs0) * kRowTwS : twr;
   // key row of digit j: full key, half h at (2 j + h) ntot N; compressed
   // key, b half at j ntot N (that offset is also the a half's counter)
   const uint32_t *evk_t = J.evk + (size_t)g * N + roff + k0;
@@ -613,7 +629,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   auto job_src = [&](uint32_t jb) -> const uint32_t * {
     const uint32_t j = job_digit(jb);
     if (j == 0xffffffffu) return J.wcol + ((size_t)jb * L1 + t) * N + roff;
-    return J.ycol + ((size_t)j * T + t) * N + roff;
+    return J.ycol + ((size_t)j * T + t) * N + roff_s;
   };
   // Loads are unconditional (an idle slot re-reads the round's last row, a
   // job without a key reads a key row the tile reads anyway) so that the
@@ -642,12 +658,19 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // first round's key words.
   uint32_t tw4[kRB4 * kRowTw / kOcThreads];
   row_tw_issue(tw4, P.tw_fwd32 + (size_t)g * N, m0);
+  uint32_t tws4[EXT ? kRB4 * kRowTw / kOcThreads : 1];
+  if constexpr (EXT) row_tw_issue(tws4, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + rs0);
   const double qr = ldcd(P.qrecip + g);
   uint32_t x[16];
   load_src(x, 0);
   uint32_t yo[4], eo0[4], eo1[4];
   if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
-    ld4(yo, J.d + (size_t)t * N + roff + k0);
+    if (EXT) {
+#pragma unroll
+      for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + roff_s + pofs[i]];
+    } else {
+      ld4(yo, J.d + (size_t)t * N + roff + k0);
+    }
     ld4_nt(eo0, evk_t + (kHalves * own + 0) * evk_step);
     if (!SEEDED) ld4_nt(eo1, evk_t + (kHalves * own + 1) * evk_step);
   }
@@ -657,6 +680,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   uint32_t twi4[kRB4 * kRowTw / kOcThreads];
   if (IS_P) row_tw_issue(twi4, P.tw_inv32 + (size_t)g * N, m0);
   row_tw_store(twl, tw4, q, qr, true);
+  if constexpr (EXT) row_tw_store(twl_s, tws4, q, qr, true);
   __syncthreads();
 
   // at most 16 digits (checked at plan creation): one REDC per sum
@@ -667,13 +691,20 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       load_src(x, base);
       load_keys(base);
     }
-    row_round_fwd(x, base + slot < njobs, row_buf(lds, slot, r), tig, twr, q);
+    // a ModDown term is a natural row; a digit row is permuted under EXT
+    const bool perm_row = EXT && base + slot < njobs && job_digit(base + slot) != 0xffffffffu;
+    row_round_fwd(x, base + slot < njobs, row_buf(lds, slot, r), tig, perm_row ? twr_s : twr, q);
 #pragma unroll
     for (int s2 = 0; s2 < kSlots; s2++) {
       const uint32_t jb2 = base + s2;
       if (jb2 >= njobs) break;
       uint32_t y[4];
-      lds4(y, row_buf(lds, s2, r), k0);
+      if (EXT && job_digit(jb2) != 0xffffffffu) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) y[i] = row_buf(lds, s2, r)[rl(pofs[i])];
+      } else {
+        lds4(y, row_buf(lds, s2, r), k0);
+      }
 #pragma unroll
       for (int i = 0; i < 4; i++) y[i] = canon4(y[i], q);
       if (job_digit(jb2) == 0xffffffffu) {
@@ -740,6 +771,16 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       o0[i] = csub(mul_shoup(r0[i] + q - w0[i], f.x, f.y, q), q);
       o1[i] = csub(mul_shoup(r1[i] + q - w1[i], f.x, f.y, q), q);
     }
+    if (EXT) {  // the caller's addends, read through the same automorphism
+      if (J.add0) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) o0[i] = csub(o0[i] + gp(J.add0)[(size_t)t * N + roff_s + pofs[i]], q);
+      }
+      if (J.add1) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) o1[i] = csub(o1[i] + gp(J.add1)[(size_t)t * N + roff_s + pofs[i]], q);
+      }
+    }
     stg4_nt(J.out + ((size_t)0 * L1 + t) * N + roff + k0, make_uint4(o0[0], o0[1], o0[2], o0[3]));
     stg4_nt(J.out + ((size_t)1 * L1 + t) * N + roff + k0, make_uint4(o1[0], o1[1], o1[2], o1[3]));
   }
@@ -754,11 +795,11 @@ __device__ __forceinline__ void oc_tile(const DevPlan &P, const OcJob &J, uint32
     case OC_INTT_ROW: tile_intt_row(P, J, tile, lds); break;
     case OC_INTT_COL: tile_intt_col<A>(P, J, tile, false, lds); break;
     case OC_UP_P: tile_up<A, TTU>(P, J, tile, true, J.ttu, lds); break;
-    case OC_ROW_P: tile_row<true, false>(P, J, tile, lds); break;
+    case OC_ROW_P: tile_row<true, false, false>(P, J, tile, lds); break;
     case OC_UP_Q: tile_up<A, TTU>(P, J, tile, false, J.ttu, lds); break;
     case OC_INTT_COL_DN: tile_intt_col<A>(P, J, tile, true, lds); break;
     case OC_DN: tile_dn<A, TTD>(P, J, tile, J.ttd, lds); break;
-    case OC_ROW_Q: tile_row<false, false>(P, J, tile, lds); break;
+    case OC_ROW_Q: tile_row<false, false, false>(P, J, tile, lds); break;
   }
 }
 
@@ -767,7 +808,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // LDS words of one phase's tiles, and of any phase (persistent kernel)
 template <int A, int PHASE, int TT>
 constexpr int oc_phase_lds_words() {
-  return (PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED)
+  return (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT) ? kRowTileLdsExt
+         : (PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED)
              ? kRowTileLds
          : PHASE == OC_INTT_ROW                   ? kRowLds
          : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS + 2 * (1 << A)
@@ -815,7 +857,11 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   if constexpr (PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SEEDED;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, true>(P, J, blockIdx.x, lds);
+    tile_row<IS_P, true, false>(P, J, blockIdx.x, lds);
+  } else if constexpr (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT) {
+    constexpr bool IS_P = PHASE == OC_ROW_P_EXT;
+    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row<IS_P, false, true>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -829,9 +875,10 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   }
 }
 
-static const char *const kOcPhaseName[OC_NPHASE + 3] = {
-    "oc.intt_row", "oc.intt_col.up", "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
-    "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q", "oc.bconv_col.up", "oc.row.p.seeded", "oc.row.q.seeded"};
+static const char *const kOcPhaseName[OC_NPHASE + 5] = {
+    "oc.intt_row",      "oc.intt_col.up",    "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
+    "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q",          "oc.bconv_col.up", "oc.row.p.seeded",
+    "oc.row.q.seeded",  "oc.row.p.ext",      "oc.row.q.ext"};
 
 template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
@@ -843,24 +890,33 @@ static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, ui
 
 template <int A, int TT>
 static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
-                             const uint32_t *max_tiles, bool seeded, hipStream_t st) {
-  launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
-  launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
-  // a job's merged grid needs at most its own UP_P + UP_Q tiles
-  launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
-  if (seeded) launch_phase<A, OC_ROW_P_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
-  else launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
+                             const uint32_t *max_tiles, OcRowVariant rows, OcPart part, hipStream_t st) {
+  if (part != OC_PART_REST) {
+    launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
+    launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
+    // a job's merged grid needs at most its own UP_P + UP_Q tiles
+    launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
+  }
+  if (part == OC_PART_MODUP) return;
+  switch (rows) {
+    case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_P_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
+    case OC_ROWS_EXT: launch_phase<A, OC_ROW_P_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
+    default: launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
+  }
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
-  if (seeded) launch_phase<A, OC_ROW_Q_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
-  else launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
+  switch (rows) {
+    case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_Q_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
+    case OC_ROWS_EXT: launch_phase<A, OC_ROW_Q_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
+    default: launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
+  }
 }
 
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
-                     uint32_t tt, bool seeded, hipStream_t st) {
-  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, seeded, st);
-  else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, seeded, st);
+                     uint32_t tt, OcRowVariant rows, OcPart part, hipStream_t st) {
+  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, rows, part, st);
+  else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, rows, part, st);
   return hipGetLastError();
 }
 

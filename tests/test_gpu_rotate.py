@@ -1,0 +1,201 @@
+"""GPU parity of the callers of the key switch (Sec. II): the automorphism,
+hoisted rotations (one ModUp of c1 shared by every rotation key) and
+multiplication with relinearisation, bit for bit against the oracle.
+
+Cases: the N=2^12 / 4-tower / dnum 2 workload with real rotation and
+relinearisation keys (outputs also decrypt), the N=2^16 / 24-tower / dnum 3
+workload at full size (every element), partial last digits, dnum = 1,
+K != alpha, alpha = 1, level 0, both conversion tile widths, conjugation
+and the identity element; rejections of bad arguments.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import core
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_01598_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("log_n", [12, 16])
+def test_automorphism_matches_oracle(ks, log_n):
+    plan = ks.Plan(log_n, 3, 1, 1)
+    a = synth.uniform_limbs(plan.moduli[:3], plan.n, synth.seed_for(20, log_n))
+    for k in (5, core.galois_rotation(log_n, -7), (2 << log_n) - 1, 1):
+        say(f"[auto] log_n={log_n} k={k}")
+        got = host(plan.automorphism(dev(a), k))
+        assert np.array_equal(got, core.automorphism_eval(a, log_n, k)), k
+    plan.close()
+
+
+def _sub(a, b, mods):
+    return np.stack([((a[i].astype(np.int64) - b[i]) % int(mods[i])) for i in range(len(a))]).astype(np.uint32)
+
+
+@pytest.mark.parametrize("tt", [1, 2])
+def test_hoisted_plain_workload_decrypts(ks, tt):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    level = 3
+    c0 = synth.uniform_limbs(mods[:4], p.n, synth.seed_for(21, 0))
+    c1 = synth.uniform_limbs(mods[:4], p.n, synth.seed_for(21, 1))
+    gal = [core.galois_rotation(12, r) for r in (1, 5, -3)] + [(2 << 12) - 1, 1]
+    keys = [core.keygen_rotation(p, mods, 60 + i, k) for i, k in enumerate(gal)]
+    want = core.rotate_hoisted(p, mods, level, c0, c1, gal, [k[2] for k in keys])
+    plan = ks.Plan(12, 4, 2, 2)
+    plan.configure("oc", tile_towers=tt)
+    say(f"[rot plain] tt={tt}")
+    outs = plan.rotate_hoisted(level, dev(c0), dev(c1), [(dev(k[2]), g) for k, g in zip(keys, gal)])
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        assert np.array_equal(host(o), w), (i, gal[i], np.argwhere(host(o) != w)[:5])
+    s, sk, _, h = keys[0]
+    got = host(outs[0])
+    sc0 = core.automorphism_eval(c0, 12, gal[0])
+    sc1 = core.automorphism_eval(c1, 12, gal[0])
+    r = oracle.decrypt_residual(p, mods, level, sc1, np.stack([_sub(got[0], sc0, mods), got[1]]), s, sk)
+    assert max(abs(v) for v in r) <= oracle.noise_bound(p, mods, level, h)
+    # identity element: the key switch of c1 plus (c0, 0), from the plain entry point
+    ks1 = host(plan.keyswitch(dev(keys[-1][2]), level, dev(c1)))
+    ident = host(outs[-1])
+    assert np.array_equal(ident[1], ks1[1])
+    assert np.array_equal(ident[0], np.stack([(ks1[0][i].astype(np.uint64) + c0[i]) % int(mods[i])
+                                              for i in range(4)]).astype(np.uint32))
+    plan.close()
+
+
+def test_hoisted_full_size_n16_l24_dnum3(ks):
+    p = oracle.Params(16, 24, 3, 8)
+    mods = oracle.moduli(p)
+    c0 = synth.uniform_limbs(mods[:24], p.n, synth.seed_for(22, 0))
+    c1 = synth.uniform_limbs(mods[:24], p.n, synth.seed_for(22, 1))
+    gal = [core.galois_rotation(16, r) for r in (1, 2, -1)]
+    keys = [synth.uniform_evk(mods, 3, p.n, synth.seed_for(22, 10 + i)) for i in range(3)]
+    want = core.rotate_hoisted(p, mods, 23, c0, c1, gal, keys)
+    plan = ks.Plan(16, 24, 3, 8)
+    for tt in (1, 2):
+        say(f"[rot n16] tt={tt}")
+        plan.configure("oc", tile_towers=tt)
+        outs = plan.rotate_hoisted(23, dev(c0), dev(c1), [(dev(k), g) for k, g in zip(keys, gal)])
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(outs, want)):
+            bad = np.argwhere(host(o) != w)
+            assert bad.size == 0, (tt, i, bad[:5], len(bad))
+    plan.close()
+
+
+SHAPES = [
+    (12, 5, 2, 0, [4, 0]),     # partial last digit; level 0
+    (12, 4, 1, 0, [3]),        # dnum = 1
+    (13, 9, 3, 2, [8, 4]),     # K != alpha
+    (12, 7, 7, 1, [6, 2]),     # alpha = 1
+]
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,levels", SHAPES)
+def test_hoisted_shapes(ks, log_n, num_q, dnum, num_p, levels):
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    gal = [core.galois_rotation(log_n, 3), (2 << log_n) - 1]
+    keys = [synth.uniform_evk(mods, dnum, p.n, synth.seed_for(23, 10 * num_q + i)) for i in range(2)]
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    for level in levels:
+        say(f"[rot shape] {log_n},{num_q},{dnum},{num_p} level={level}")
+        c0 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(23, 100 + level))
+        c1 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(23, 200 + level))
+        want = core.rotate_hoisted(p, mods, level, c0, c1, gal, keys)
+        outs = plan.rotate_hoisted(level, dev(c0), dev(c1), [(dev(k), g) for k, g in zip(keys, gal)])
+        torch.cuda.synchronize()
+        for o, w in zip(outs, want):
+            assert np.array_equal(host(o), w), (level, np.argwhere(host(o) != w)[:5])
+    plan.close()
+
+
+def test_mult_relin_plain_workload_decrypts(ks):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    s, evk, h = core.keygen_relin(p, mods, 31)
+    plan = ks.Plan(12, 4, 2, 2)
+    for level in (3, 1, 0):
+        a0, a1, b0, b1 = [synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(24, 10 * level + i))
+                          for i in range(4)]
+        want = core.mult_relin(p, mods, level, a0, a1, b0, b1, evk)
+        for tt in (1, 2):
+            say(f"[relin plain] level={level} tt={tt}")
+            plan.configure("oc", tile_towers=tt)
+            got = host(plan.mult_relin(dev(evk), level, dev(a0), dev(a1), dev(b0), dev(b1)))
+            assert np.array_equal(got, want), (level, tt, np.argwhere(got != want)[:5])
+    plan.close()
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", [(16, 24, 3, 8, 23), (13, 9, 3, 2, 6), (12, 7, 7, 1, 6)])
+def test_mult_relin_shapes(ks, log_n, num_q, dnum, num_p, level):
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, dnum, p.n, synth.seed_for(25, num_q))
+    a0, a1, b0, b1 = [synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(25, 100 + i)) for i in range(4)]
+    want = core.mult_relin(p, mods, level, a0, a1, b0, b1, evk)
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    say(f"[relin] {log_n},{num_q},{dnum},{num_p} level={level}")
+    got = host(plan.mult_relin(dev(evk), level, dev(a0), dev(a1), dev(b0), dev(b1)))
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (bad[:5], len(bad))
+    plan.close()
+
+
+def test_rotation_rejections(ks):
+    plan = ks.Plan(12, 4, 2, 2)
+    mods = plan.moduli
+    c0 = dev(synth.uniform_limbs(mods[:4], plan.n, 1))
+    c1 = dev(synth.uniform_limbs(mods[:4], plan.n, 2))
+    evk = dev(synth.uniform_evk(mods, 2, plan.n, 3))
+    out = torch.empty((2, 4, plan.n), dtype=torch.int32, device="cuda")
+    ws = plan._ws(ks.ks_rotate_workspace_size(plan.handle, 3, 1), "cuda")
+
+    def call(**kw):
+        args = dict(c0=c0, c1=c1, rots=[(evk, 5, out)], ws=ws)
+        args.update(kw)
+        with pytest.raises(ks.KsError) as e:
+            ks.ks_rotate_hoisted(plan.handle, 3, args["c0"], args["c1"], args["rots"], args["ws"])
+        return e.value.status
+    assert call(rots=[(evk, 4, out)]) == ks.KS_ERR_INVALID_ARG           # even element
+    assert call(rots=[(evk, 2 * plan.n + 1, out)]) == ks.KS_ERR_INVALID_ARG
+    big = torch.empty((4, 4, plan.n), dtype=torch.int32, device="cuda")
+    # an output over c0 (both inside one buffer, so in bounds either way)
+    assert call(c0=big[0], rots=[(evk, 5, big[0:2])]) == ks.KS_ERR_INVALID_ARG
+    assert call(ws=ws[: ws.numel() // 2]) == ks.KS_ERR_BUDGET
+    plan.configure("mp")
+    assert call() == ks.KS_ERR_UNSUPPORTED
+    with pytest.raises(ks.KsError) as e:
+        plan.mult_relin(evk, 3, c0, c1, c0, c1)
+    assert e.value.status == ks.KS_ERR_UNSUPPORTED
+    plan.configure("oc")
+    with pytest.raises(ks.KsError) as e:
+        plan.automorphism(c0, 6)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    plan.close()
