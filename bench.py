@@ -239,6 +239,44 @@ def rotation_rate(ks, plan, evks, steps, np, torch, synth):
     return res
 
 
+BTS_SETS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+
+
+def bts_rate(ks, steps, np, torch, synth):
+    """Key switches per second at the bootstrapping-scale parameter sets of
+    Table III (N = 2^17, 30-bit towers), one ciphertext at the top level per
+    call, keys rotating over 4 copies; OC and MP."""
+    res = {}
+    for name, (log_n, num_q, dnum, num_p) in BTS_SETS.items():
+        plan = ks.Plan(log_n, num_q, dnum, num_p)
+        n, mods, level = plan.n, plan.moduli, num_q - 1
+        evks = [torch.from_numpy(synth.uniform_evk(mods, dnum, n, synth.seed_for(31, c)).view(np.int32)).cuda()
+                for c in range(4)]
+        d = torch.from_numpy(synth.uniform_limbs(mods[:num_q], n, synth.seed_for(31, 9)).view(np.int32)).cuda()
+        out = torch.empty((2, num_q, n), dtype=torch.int32, device="cuda")
+        cur = {"evk_mib": round(evks[0].numel() * 4 / 2**20, 1)}
+        for sched in ("oc", "mp"):
+            plan.configure(sched)
+            ws = plan.workspace([level])
+            for i in range(5):
+                plan.keyswitch(evks[i % 4], level, d, out=out, workspace=ws)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for i in range(steps):
+                plan.keyswitch(evks[i % 4], level, d, out=out, workspace=ws)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            cur[sched] = {"ks_per_s": round(1e3 / ms, 1), "us_per_ks": round(ms * 1e3, 2)}
+            del ws
+        cur["oc_over_mp"] = round(cur["oc"]["ks_per_s"] / cur["mp"]["ks_per_s"], 3)
+        res[name] = cur
+        del evks
+        plan.close()
+    return res
+
+
 def mixed_rate(ks, dnum, reps, np, torch, synth):
     """64 ciphertexts at levels with l+1 ~ U[8, 24], N=2^16, K = alpha, one
     shared key: OC batched vs the same 64 switched one at a time with MP."""
@@ -353,6 +391,7 @@ def parse():
                     help="ciphertexts per call in the batched measurement of the same workload (0 = skip)")
     ap.add_argument("--seeded", type=int, default=1, help="also time compressed keys (0: skip)")
     ap.add_argument("--rotations", type=int, default=1, help="also time hoisted rotations and HMult (0: skip)")
+    ap.add_argument("--bts", type=int, default=1, help="also time the N=2^17 bootstrapping-scale sets (0: skip)")
     ap.add_argument("--mixed", action="store_true",
                     help="also time 64-ciphertext batches at levels l+1 ~ U[8,24] for dnum 2, 3, 4")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -487,6 +526,8 @@ def main():
     res["stages"] = stages
     if args.batch:
         res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)
+    if args.bts:
+        res["bts_scale"] = bts_rate(ks, max(20, args.steps // 4), np, torch, synth)
     if args.rotations:
         res["rotations"] = rotation_rate(ks, plan, evks, args.steps, np, torch, synth)
     if args.seeded:

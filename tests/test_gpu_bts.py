@@ -1,0 +1,67 @@
+"""GPU parity at bootstrapping scale: the BTS1 / BTS2 / BTS3 parameter sets
+of Table III (N = 2^17; 28+28 towers with dnum 1, 40+20 with dnum 2, 45+15
+with dnum 3), 30-bit towers, at full size with every output element
+compared against the oracle.  These stress the 2^17 two-pass transform
+(512 x 256), conversions with more than 16 source towers (alpha 28 and 20,
+and K = 28 / 20 for ModDown, accumulated in chunks of 16 products), and
+the single-digit case where ModUp has no Q target.  BTS3 also runs with a
+compressed key, BTS2 also with the Max-Parallel schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import core
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_01598_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("name", ["bts1", "bts2", "bts3"])
+def test_bts_full_size(ks, name):
+    log_n, num_q, dnum, num_p = BTS[name]
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    level = num_q - 1
+    evk = synth.uniform_evk(mods, dnum, p.n, synth.seed_for(30, num_q))
+    a_seed = synth.seed_for(30, 500 + num_q)
+    if name == "bts3":  # the a halves regenerated from a seed
+        evk[:, 1] = core.seeded_a(p, mods, a_seed)[:, 1]
+    d = synth.uniform_limbs(mods[:num_q], p.n, synth.seed_for(30, 100 + num_q))
+    print(f"[{name}] oracle", flush=True)
+    want = oracle.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    runs = [("oc", None)] + ([("mp", None)] if name == "bts2" else []) + ([("oc", "seeded")] if name == "bts3" else [])
+    for sched, kind in runs:
+        print(f"[{name}] {sched} {kind or ''}", flush=True)
+        sys.stdout.flush()
+        plan.configure(sched)
+        if kind == "seeded":
+            out = plan.keyswitch_seeded(dev(np.ascontiguousarray(evk[:, 0])), a_seed, level, dev(d))
+        else:
+            out = plan.keyswitch(dev(evk), level, dev(d))
+        torch.cuda.synchronize()
+        bad = np.argwhere(host(out) != want)
+        assert bad.size == 0, (name, sched, kind, bad[:5], len(bad))
+    plan.close()
