@@ -220,6 +220,23 @@ def rotation_rate(ks, plan, evks, steps, np, torch, synth):
             torch.cuda.synchronize()
             res[name][f"m{m}"] = round(m * reps / (a.elapsed_time(b) / 1e3), 1)
     res["hoisting_gain_m8"] = round(res["hoisted"]["m8"] / res["one_at_a_time"]["m8"], 3)
+    # the same 8 rotations with compressed keys (b halves plus a seed)
+    keys_b = [e[:, 0].contiguous() for e in evks]
+    gal = [ks.galois_rotation(LOG_N, r + 1) for r in range(8)]
+    ws = plan._ws(ks.ks_rotate_workspace_size(plan.handle, LEVEL, 8), "cuda")
+    outs = [torch.empty((2, l1, n), dtype=torch.int32, device="cuda") for _ in range(8)]
+    rots = [(keys_b[i % len(keys_b)], 1000 + i, g, o) for i, (g, o) in enumerate(zip(gal, outs))]
+    ks.ks_rotate_hoisted_seeded(plan.handle, LEVEL, c0, c1, rots, ws)
+    torch.cuda.synchronize()
+    reps = max(5, steps // 32)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        ks.ks_rotate_hoisted_seeded(plan.handle, LEVEL, c0, c1, rots, ws)
+    b.record()
+    torch.cuda.synchronize()
+    res["hoisted_compressed_keys"] = {"m8": round(8 * reps / (a.elapsed_time(b) / 1e3), 1)}
+    del keys_b
     a0, a1 = c0, c1
     b0 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 402)).view(np.int32)).cuda()
     b1 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 403)).view(np.int32)).cuda()
@@ -271,6 +288,22 @@ def bts_rate(ks, steps, np, torch, synth):
             cur[sched] = {"ks_per_s": round(1e3 / ms, 1), "us_per_ks": round(ms * 1e3, 2)}
             del ws
         cur["oc_over_mp"] = round(cur["oc"]["ks_per_s"] / cur["mp"]["ks_per_s"], 3)
+        # compressed keys (b halves of the same keys plus a seed)
+        keys_b = [e[:, 0].contiguous() for e in evks]
+        plan.configure("oc")
+        ws = plan.workspace([level])
+        for i in range(5):
+            plan.keyswitch_seeded(keys_b[i % 4], 77 + i % 4, level, d, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(steps):
+            plan.keyswitch_seeded(keys_b[i % 4], 77 + i % 4, level, d, out=out, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        cur["oc_compressed_keys"] = {"ks_per_s": round(1e3 / ms, 1), "us_per_ks": round(ms * 1e3, 2)}
+        del ws, keys_b
         res[name] = cur
         del evks
         plan.close()

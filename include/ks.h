@@ -237,6 +237,24 @@ ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0
                               uint32_t count, const ks_rotation_t *rots, void *workspace,
                               size_t workspace_bytes, void *stream);
 
+/* One rotation of a hoisted group with a compressed key: the b halves
+ * evk_b [dnum][L+1+K][N] (device) and the seed of the a halves, as for
+ * ks_keyswitch_seeded. */
+typedef struct {
+  const uint32_t *evk_b;
+  uint64_t a_seed;
+  uint32_t galois;
+  uint32_t *out;
+} ks_seeded_rotation_t;
+
+/* ks_rotate_hoisted with compressed rotation keys (Sec. IV-D key
+ * compression applied to the keys of a hoisted group): results equal
+ * ks_rotate_hoisted with the expanded keys.  Same rules; a key counts as
+ * dnum (L+1+K) N words for the overlap checks. */
+ks_status_t ks_rotate_hoisted_seeded(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                                     uint32_t count, const ks_seeded_rotation_t *rots, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+
 /* Bytes of workspace ks_mult_relin needs at `level`. */
 ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes);
 

@@ -51,6 +51,11 @@ class ks_rotation_t(ctypes.Structure):
     _fields_ = [("evk", ctypes.c_void_p), ("galois", ctypes.c_uint32), ("out", ctypes.c_void_p)]
 
 
+class ks_seeded_rotation_t(ctypes.Structure):
+    _fields_ = [("evk_b", ctypes.c_void_p), ("a_seed", ctypes.c_uint64), ("galois", ctypes.c_uint32),
+                ("out", ctypes.c_void_p)]
+
+
 _U32P = ctypes.POINTER(ctypes.c_uint32)
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -75,6 +80,8 @@ _SIGS = {
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "ks_rotate_hoisted": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
                                          ctypes.POINTER(ks_rotation_t), _VP, ctypes.c_size_t, _VP]),
+    "ks_rotate_hoisted_seeded": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
+                                                ctypes.POINTER(ks_seeded_rotation_t), _VP, ctypes.c_size_t, _VP]),
     "ks_mult_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "ks_mult_relin": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                      _VP]),
@@ -285,6 +292,17 @@ def ks_rotate_hoisted(plan, level, c0, c1, rots, workspace, workspace_bytes=None
                                   int(workspace_bytes), _stream(stream)), "ks_rotate_hoisted")
 
 
+def ks_rotate_hoisted_seeded(plan, level, c0, c1, rots, workspace, workspace_bytes=None, stream=None):
+    """rots: list of (evk_b, a_seed, galois, out)."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_seeded_rotation_t * max(len(rots), 1))()
+    for i, (evk_b, a_seed, galois, out) in enumerate(rots):
+        arr[i] = ks_seeded_rotation_t(_ptr(evk_b), int(a_seed) & (2**64 - 1), int(galois), _ptr(out))
+    _check(_lib.ks_rotate_hoisted_seeded(plan, int(level), _ptr(c0), _ptr(c1), len(rots), arr, _ptr(workspace),
+                                         int(workspace_bytes), _stream(stream)), "ks_rotate_hoisted_seeded")
+
+
 def ks_mult_workspace_size(plan, level):
     n = ctypes.c_size_t(0)
     _check(_lib.ks_mult_workspace_size(plan, int(level), ctypes.byref(n)), "ks_mult_workspace_size")
@@ -437,6 +455,16 @@ class Plan:
             workspace = self._ws(ks_rotate_workspace_size(self.handle, level, len(rots)), c1.device)
         ks_rotate_hoisted(self.handle, level, c0, c1, [(e, g, o) for (e, g), o in zip(rots, outs)], workspace,
                           stream=stream)
+        return outs
+
+    def rotate_hoisted_seeded(self, level, c0, c1, rots, workspace=None, stream=None):
+        """rots: list of (evk_b, a_seed, galois) with compressed keys."""
+        import torch
+        outs = [torch.empty((2, level + 1, self.n), dtype=torch.int32, device=c1.device) for _ in rots]
+        if workspace is None:
+            workspace = self._ws(ks_rotate_workspace_size(self.handle, level, len(rots)), c1.device)
+        ks_rotate_hoisted_seeded(self.handle, level, c0, c1, [(e, a, g, o) for (e, a, g), o in zip(rots, outs)],
+                                 workspace, stream=stream)
         return outs
 
     def rotate(self, evk, galois, level, c0, c1, workspace=None, stream=None):

@@ -631,23 +631,37 @@ ks_status_t ks_rotate_workspace_size(ks_plan_t plan, uint32_t level, uint32_t co
   return KS_OK;
 }
 
-ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1, uint32_t count,
-                              const ks_rotation_t *rots, void *workspace, size_t workspace_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// One rotation of a hoisted group: full key (a_seed unused) or compressed key.
+struct Rot {
+  const uint32_t *evk;
+  uint64_t a_seed;
+  uint32_t galois;
+  uint32_t *out;
+};
+
+ks_status_t rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                           const std::vector<Rot> &rots, bool seeded, void *workspace, size_t workspace_bytes,
+                           void *stream) {
   if (!plan) return KS_ERR_INVALID_ARG;
   Plan &pl = plan->p;
   if (effective(pl) != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  const uint32_t count = (uint32_t)rots.size();
   if (!count) return KS_OK;
-  if (!rots || !c0 || !c1 || !workspace) return KS_ERR_INVALID_ARG;
+  if (!c0 || !c1 || !workspace) return KS_ERR_INVALID_ARG;
   if ((((uintptr_t)c0 | (uintptr_t)c1) & 15) || ((uintptr_t)workspace & 255)) return KS_ERR_INVALID_ARG;
   const RotLayout lay = rot_layout(pl, level, count);
   if (workspace_bytes < lay.total) return KS_ERR_BUDGET;
   const size_t lb = limb_bytes(pl), in_b = (size_t)(level + 1) * lb, out_b = 2 * in_b;
-  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb;
+  const size_t evk_b = (size_t)pl.dnum * (seeded ? 1 : 2) * pl.ntot * lb;
   if (overlaps(workspace, workspace_bytes, c0, in_b) || overlaps(workspace, workspace_bytes, c1, in_b))
     return KS_ERR_INVALID_ARG;
   for (uint32_t r = 0; r < count; r++) {
-    const ks_rotation_t &x = rots[r];
+    const Rot &x = rots[r];
     if (!x.evk || !x.out || (((uintptr_t)x.evk | (uintptr_t)x.out) & 15) || !galois_ok(pl, x.galois))
       return KS_ERR_INVALID_ARG;
     if (overlaps(x.out, out_b, c0, in_b) || overlaps(x.out, out_b, c1, in_b) ||
@@ -665,7 +679,7 @@ ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0
   std::vector<OcJob> hj(count);
   for (uint32_t r = 0; r < count; r++) {
     OcJob &j = hj[r];
-    j = make_oc_job(pl, Job{rots[r].evk, 0, level, c1, rots[r].out}, (uint32_t *)(ws + lay.xt), tt);
+    j = make_oc_job(pl, Job{rots[r].evk, rots[r].a_seed, level, c1, rots[r].out}, (uint32_t *)(ws + lay.xt), tt);
     j.xt = (uint32_t *)(ws + lay.xt);  // shared: one ModUp for every rotation
     j.ycol = (uint32_t *)(ws + lay.ycol);
     j.zp = (uint32_t *)(ws + lay.rot0 + r * lay.per_rot);
@@ -676,8 +690,30 @@ ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0
   TRY(upload_async(pl, ws, hj.data(), hj.size() * sizeof(OcJob), st));
   const OcJob none{};
   const OcJob *djobs = (const OcJob *)ws;
-  TRY(launch_oc_phases(pl, none, djobs, 1, hj[0].tiles, tt, OC_ROWS_EXT, OC_PART_MODUP, st));
-  return dev_err(launch_oc_phases(pl, none, djobs, count, hj[0].tiles, tt, OC_ROWS_EXT, OC_PART_REST, st));
+  const OcRowVariant rows = seeded ? OC_ROWS_SEEDED_EXT : OC_ROWS_EXT;
+  TRY(launch_oc_phases(pl, none, djobs, 1, hj[0].tiles, tt, rows, OC_PART_MODUP, st));
+  return dev_err(launch_oc_phases(pl, none, djobs, count, hj[0].tiles, tt, rows, OC_PART_REST, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+ks_status_t ks_rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1, uint32_t count,
+                              const ks_rotation_t *rots, void *workspace, size_t workspace_bytes, void *stream) {
+  if (count && !rots) return KS_ERR_INVALID_ARG;
+  std::vector<Rot> r(count);
+  for (uint32_t i = 0; i < count; i++) r[i] = Rot{rots[i].evk, 0, rots[i].galois, rots[i].out};
+  return rotate_hoisted(plan, level, c0, c1, r, false, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_rotate_hoisted_seeded(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                                     uint32_t count, const ks_seeded_rotation_t *rots, void *workspace,
+                                     size_t workspace_bytes, void *stream) {
+  if (count && !rots) return KS_ERR_INVALID_ARG;
+  std::vector<Rot> r(count);
+  for (uint32_t i = 0; i < count; i++) r[i] = Rot{rots[i].evk_b, rots[i].a_seed, rots[i].galois, rots[i].out};
+  return rotate_hoisted(plan, level, c0, c1, r, true, workspace, workspace_bytes, stream);
 }
 
 ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes) {

@@ -77,9 +77,13 @@ constexpr uint32_t OC_ROW_Q_SEEDED = OC_NPHASE + 2;
 // automorphism and ROW_Q adds the job's addends to its output.
 constexpr uint32_t OC_ROW_P_EXT = OC_NPHASE + 3;
 constexpr uint32_t OC_ROW_Q_EXT = OC_NPHASE + 4;
+// Both: extended row stages with compressed keys (rotation keys stored as
+// their b halves and a seed).
+constexpr uint32_t OC_ROW_P_SEEDED_EXT = OC_NPHASE + 5;
+constexpr uint32_t OC_ROW_Q_SEEDED_EXT = OC_NPHASE + 6;
 
 // Which row-stage kernels a launch uses.
-enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT };
+enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT, OC_ROWS_SEEDED_EXT };
 // Which phases a launch sequence runs: all, ModUp only (INTT_ROW .. UP_PQ),
 // or the rest (ROW_P .. ROW_Q) on the ModUp output of an earlier launch.
 enum OcPart : uint32_t { OC_PART_ALL = 0, OC_PART_MODUP, OC_PART_REST };

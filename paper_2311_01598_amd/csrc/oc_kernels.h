@@ -808,7 +808,9 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // LDS words of one phase's tiles, and of any phase (persistent kernel)
 template <int A, int PHASE, int TT>
 constexpr int oc_phase_lds_words() {
-  return (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT) ? kRowTileLdsExt
+  return (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
+          PHASE == OC_ROW_Q_SEEDED_EXT)
+             ? kRowTileLdsExt
          : (PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED)
              ? kRowTileLds
          : PHASE == OC_INTT_ROW                   ? kRowLds
@@ -858,10 +860,12 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
     constexpr bool IS_P = PHASE == OC_ROW_P_SEEDED;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
     tile_row<IS_P, true, false>(P, J, blockIdx.x, lds);
-  } else if constexpr (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT) {
-    constexpr bool IS_P = PHASE == OC_ROW_P_EXT;
+  } else if constexpr (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
+                       PHASE == OC_ROW_Q_SEEDED_EXT) {
+    constexpr bool IS_P = PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_P_SEEDED_EXT;
+    constexpr bool SEEDED = PHASE == OC_ROW_P_SEEDED_EXT || PHASE == OC_ROW_Q_SEEDED_EXT;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, false, true>(P, J, blockIdx.x, lds);
+    tile_row<IS_P, SEEDED, true>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -875,10 +879,10 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   }
 }
 
-static const char *const kOcPhaseName[OC_NPHASE + 5] = {
+static const char *const kOcPhaseName[OC_NPHASE + 7] = {
     "oc.intt_row",      "oc.intt_col.up",    "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
     "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q",          "oc.bconv_col.up", "oc.row.p.seeded",
-    "oc.row.q.seeded",  "oc.row.p.ext",      "oc.row.q.ext"};
+    "oc.row.q.seeded",  "oc.row.p.ext",      "oc.row.q.ext",      "oc.row.p.seeded_ext", "oc.row.q.seeded_ext"};
 
 template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
@@ -901,6 +905,9 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   switch (rows) {
     case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_P_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
     case OC_ROWS_EXT: launch_phase<A, OC_ROW_P_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
+    case OC_ROWS_SEEDED_EXT:
+      launch_phase<A, OC_ROW_P_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
+      break;
     default: launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
   }
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
@@ -908,6 +915,9 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   switch (rows) {
     case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_Q_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
     case OC_ROWS_EXT: launch_phase<A, OC_ROW_Q_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
+    case OC_ROWS_SEEDED_EXT:
+      launch_phase<A, OC_ROW_Q_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
+      break;
     default: launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
   }
 }

@@ -86,6 +86,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "ks_seeded_job_t": ["evk_b", "a_seed", "level", "in", "out"],
         "ks_config_t": ["schedule", "tile_towers", "batch_mode", "spin_limit"],
         "ks_rotation_t": ["evk", "galois", "out"],
+        "ks_seeded_rotation_t": ["evk_b", "a_seed", "galois", "out"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ks.h"', "int main(void) {"]
     for t, fields in checks.items():

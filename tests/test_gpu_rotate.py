@@ -109,6 +109,34 @@ def test_hoisted_full_size_n16_l24_dnum3(ks):
     plan.close()
 
 
+@pytest.mark.parametrize("shape", [(12, 4, 2, 2, 3), (16, 24, 3, 8, 23), (13, 9, 3, 2, 4)])
+def test_hoisted_compressed_keys(ks, shape):
+    """Rotation keys stored as b halves plus a seed give the bits of the
+    expanded keys."""
+    log_n, num_q, dnum, num_p, level = shape
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    c0 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(26, 0))
+    c1 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(26, 1))
+    gal = [core.galois_rotation(log_n, r) for r in (1, 4)] + [(2 << log_n) - 1]
+    seeds = [synth.seed_for(26, 50 + i) for i in range(3)]
+    keys = []
+    for i, a_seed in enumerate(seeds):
+        full = synth.uniform_evk(mods, dnum, p.n, synth.seed_for(26, 10 + i))
+        full[:, 1] = core.seeded_a(p, mods, a_seed)[:, 1]
+        keys.append(full)
+    want = core.rotate_hoisted(p, mods, level, c0, c1, gal, keys)
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    print(f"[rot seeded] {shape}", flush=True)
+    outs = plan.rotate_hoisted_seeded(level, dev(c0), dev(c1), [(dev(np.ascontiguousarray(k[:, 0])), a, g)
+                                                                 for k, a, g in zip(keys, seeds, gal)])
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        bad = np.argwhere(host(o) != w)
+        assert bad.size == 0, (i, bad[:5], len(bad))
+    plan.close()
+
+
 SHAPES = [
     (12, 5, 2, 0, [4, 0]),     # partial last digit; level 0
     (12, 4, 1, 0, [3]),        # dnum = 1
