@@ -58,6 +58,8 @@ def lib():
             "oracle_rotate_hoisted": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, ctypes.c_uint32, _U32P,
                                                      _U32P, _U32P]),
             "oracle_rotate": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, ctypes.c_uint32, _U32P, _U32P]),
+            "oracle_rotate_sum_hoisted": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, ctypes.c_uint32,
+                                                         _U32P, _U32P, _U32P, _U32P]),
             "oracle_mult_relin": (ctypes.c_int, [P, _U32P, ctypes.c_uint32, _U32P, _U32P, _U32P, _U32P, _U32P, _U32P]),
             "oracle_set_fault": (None, [ctypes.c_int]),
             "oracle_evk_words": (ctypes.c_uint64, [ctypes.c_uint32] * 4),
@@ -301,6 +303,24 @@ def rotate_hoisted(p, mods, level, c0, c1, galois, evks):
                                    outs.ctypes.data_as(_U32P)) != 0:
         raise ValueError("oracle_rotate_hoisted rejected its arguments")
     return outs
+
+
+def rotate_sum_hoisted(p, mods, level, c0, c1, galois, evks, diags=None):
+    """sum_r p_r sigma_r((c0, c1)) with one ModUp and one ModDown (double
+    hoisting); diags None or [count][L+1+K][N]; returns [2][level+1][N]."""
+    mods, mp_ = _u32(mods)
+    c0, c0p = _arr(c0)
+    c1, c1p = _arr(c1)
+    g, gp_ = _arr(list(galois))
+    ev, evp = _arr(np.stack(list(evks)))
+    dg = None
+    if diags is not None:
+        dg, dgp = _arr(np.stack(list(diags)))
+    out = np.zeros((2, level + 1, p.n), np.uint32)
+    if lib().oracle_rotate_sum_hoisted(ctypes.byref(p.c()), mp_, int(level), c0p, c1p, len(g), gp_, evp,
+                                       dgp if dg is not None else None, out.ctypes.data_as(_U32P)) != 0:
+        raise ValueError("oracle_rotate_sum_hoisted rejected its arguments")
+    return out
 
 
 def rotate(p, mods, level, c0, c1, galois, evk):

@@ -30,7 +30,8 @@ void oracle_set_fault(int fault) { g_fault = fault; }
  *  2: ModDown P4 adds w_hat instead of subtracting it
  *  3: ModUp P2 uses the wrong target constant (index off by one)
  *  4: ModUp P3 bypass takes the limb from the neighbouring digit
- *  5: hoisted rotation permutes the digits with the inverse map */
+ *  5: hoisted rotations (single and summed) permute the digits with the
+ *     inverse map */
 
 /* ------------------------------------------------------------------ */
 /* integers                                                             */
@@ -610,6 +611,69 @@ int oracle_rotate_hoisted(const oracle_params *p, const uint32_t *moduli, uint32
   return 0;
 }
 
+/* Double hoisting (named in Sec. VII): a sum of rotations, each optionally
+ * times a plaintext diagonal p_r, with one ModUp of c1 and one ModDown for
+ * the whole sum:
+ *   ACC_s = sum_r p_r * sum_j sigma_r(y_j) * evk_r[j][s]   (extended basis)
+ *   out   = (ModDown(ACC_0) + sum_r p_r * sigma_r(c0), ModDown(ACC_1))
+ * diags: null (every p_r = 1) or [count][L+1+K][N] in key-row order
+ * (q_0..q_L, p_0..p_{K-1}; evaluation domain). */
+int oracle_rotate_sum_hoisted(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                              const uint32_t *c1, uint32_t count, const uint32_t *galois, const uint32_t *evks,
+                              const uint32_t *diags, uint32_t *out) {
+  ks_ctx c;
+  if (ctx_init(&c, p, moduli, level) != 0) return -1;
+  const uint32_t n = c.n, l1 = level + 1, T = c.ntow, D = c.ndig, EL = c.L1 + c.K;
+  const size_t evk_words = (size_t)p->dnum * 2 * EL * n, diag_words = (size_t)EL * n;
+  for (uint32_t r = 0; r < count; r++)
+    if ((galois[r] & 1u) == 0 || galois[r] >= 2 * n) return -1;
+  uint32_t *x = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)D * T * n);
+  uint32_t *acc = (uint32_t *)calloc((size_t)2 * T * n, sizeof(uint32_t));
+  uint32_t *tgt = (uint32_t *)malloc(sizeof(uint32_t) * T * n);
+  uint32_t *tq = (uint32_t *)malloc(sizeof(uint32_t) * T);
+  uint32_t *perm = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t *one = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  if (!x || !y || !acc || !tgt || !tq || !perm || !one) {
+    free(x); free(y); free(acc); free(tgt); free(tq); free(perm); free(one);
+    return -1;
+  }
+  modup(&c, c1, x, y, tgt, tq);
+  for (uint32_t r = 0; r < count; r++) {
+    const uint32_t *evk = evks + r * evk_words;
+    for (uint32_t t = 0; t < T; t++) {
+      const uint32_t m = c.q[t];
+      const uint32_t *pr = diags ? diags + r * diag_words + (size_t)c.evk_limb[t] * n : NULL;
+      for (uint32_t s = 0; s < 2; s++) {
+        memset(one, 0, sizeof(uint32_t) * n); /* this rotation's key product, tower t */
+        for (uint32_t j = 0; j < D; j++) {
+          if (g_fault == 1 && j == D - 1 && D > 1) continue;
+          oracle_automorphism_eval(LIMB(y, (size_t)j * T + t, n), c.log_n, galois[r], perm);
+          if (g_fault == 5) /* the inverse permutation: scatter where a gather belongs */
+            for (uint32_t z = 0; z < n; z++) {
+              const uint32_t e2 = (uint32_t)(((uint64_t)galois[r] * (2 * oracle_bitrev(z, c.log_n) + 1)) % (2 * n));
+              perm[oracle_bitrev((e2 - 1) / 2, c.log_n)] = LIMB(y, (size_t)j * T + t, n)[z];
+            }
+          const uint32_t *ek = evk + (((size_t)j * 2 + s) * EL + c.evk_limb[t]) * n;
+          for (uint32_t z = 0; z < n; z++) one[z] = addmod(one[z], mulmod(perm[z], ek[z], m), m);
+        }
+        uint32_t *aa = LIMB(acc, (size_t)s * T + t, n);
+        for (uint32_t z = 0; z < n; z++) aa[z] = addmod(aa[z], pr ? mulmod(pr[z], one[z], m) : one[z], m);
+      }
+    }
+  }
+  for (uint32_t s = 0; s < 2; s++) moddown(&c, LIMB(acc, (size_t)s * T, n), LIMB(out, (size_t)s * l1, n));
+  for (uint32_t r = 0; r < count; r++)
+    for (uint32_t i = 0; i < l1; i++) {
+      const uint32_t *pr = diags ? diags + r * diag_words + (size_t)i * n : NULL;
+      oracle_automorphism_eval(LIMB(c0, i, n), c.log_n, galois[r], perm);
+      for (uint32_t z = 0; z < n; z++)
+        LIMB(out, i, n)[z] = addmod(LIMB(out, i, n)[z], pr ? mulmod(pr[z], perm[z], c.q[i]) : perm[z], c.q[i]);
+    }
+  free(x); free(y); free(acc); free(tgt); free(tq); free(perm); free(one);
+  return 0;
+}
+
 /* One rotation without hoisting: permute c0 and c1, key-switch sigma(c1),
  * add sigma(c0).  A different, equally valid result (the ModUp of sigma(c1)
  * differs from sigma of the ModUp of c1 by multiples of Q_j). */
@@ -617,8 +681,8 @@ int oracle_rotate(const oracle_params *p, const uint32_t *moduli, uint32_t level
                   const uint32_t *c1, uint32_t galois, const uint32_t *evk, uint32_t *out) {
   const uint32_t n = 1u << p->log_n, l1 = level + 1;
   if ((galois & 1u) == 0 || galois >= 2 * n || level >= p->num_q) return -1;
-  uint32_t *sc1 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
-  uint32_t *sc0 = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)l1 * n);
+  uint32_t *sc1 = (uint32_t *)calloc((size_t)l1 * n, sizeof(uint32_t));
+  uint32_t *sc0 = (uint32_t *)calloc((size_t)l1 * n, sizeof(uint32_t));
   if (!sc1 || !sc0) { free(sc1); free(sc0); return -1; }
   int rc = 0;
   for (uint32_t i = 0; i < l1; i++) {

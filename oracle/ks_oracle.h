@@ -117,6 +117,12 @@ int oracle_keygen_relin(const oracle_params *p, const uint32_t *moduli, uint64_t
 int oracle_rotate_hoisted(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
                           const uint32_t *c1, uint32_t count, const uint32_t *galois, const uint32_t *evks,
                           uint32_t *outs);
+/* oracle_rotate_sum_hoisted: double hoisting, sum_r p_r sigma_r(c0, c1)
+ * with one ModUp and one ModDown; diags null (all p_r = 1) or
+ * [count][L+1+K][N] (key-row order, evaluation domain); out [2][l+1][N]. */
+int oracle_rotate_sum_hoisted(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
+                              const uint32_t *c1, uint32_t count, const uint32_t *galois, const uint32_t *evks,
+                              const uint32_t *diags, uint32_t *out);
 int oracle_rotate(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *c0,
                   const uint32_t *c1, uint32_t galois, const uint32_t *evk, uint32_t *out);
 int oracle_mult_relin(const oracle_params *p, const uint32_t *moduli, uint32_t level, const uint32_t *a0,

@@ -159,3 +159,86 @@ def test_planted_mistakes_break_the_rotation_bound(fault):
     sc1 = core.automorphism_eval(c1, 12, k)
     r = oracle.decrypt_residual(p, mods, 3, sc1, np.stack([_sub(out[0], sc0, mods), out[1]]), s, sk)
     assert max(abs(v) for v in r) > oracle.noise_bound(p, mods, 3, h)
+
+
+# ---------------------------------------------------------------- double hoisting
+
+def _small_diag(p, mods, seed, bound=2):
+    """A plaintext diagonal with coefficients in [-bound, bound], in the
+    evaluation domain of every key row (q_0..q_L, p_0..p_{K-1})."""
+    rng = np.random.default_rng(seed)
+    coef = rng.integers(-bound, bound + 1, p.n)
+    return np.stack([oracle.ntt(np.array([int(v) % int(m) for v in coef], np.uint32), int(m)) for m in mods]), coef
+
+
+def _sum_residual(p, mods, level, c0, c1, out, s, sks, gal, coefs):
+    """c0' + c1' s - sum_r p_r (sigma_r(c0) + sigma_r(c1) sigma_r(s)), centred."""
+    l1 = level + 1
+    r = np.zeros((l1, p.n), np.uint32)
+    for i in range(l1):
+        q = int(mods[i])
+        f = lambda v: oracle.ntt(np.array([int(x) % q for x in v], np.uint32), q).astype(object)
+        v = out[0, i].astype(object) + out[1, i].astype(object) * f(s)
+        for k, sk, cf in zip(gal, sks, coefs):
+            pr = f(cf) if cf is not None else 1
+            sc0 = core.automorphism_eval(c0[i], p.log_n, k).astype(object)
+            sc1 = core.automorphism_eval(c1[i], p.log_n, k).astype(object)
+            v = v - pr * (sc0 + sc1 * f(sk))
+        r[i] = oracle.intt(np.array([int(x) % q for x in v], np.uint32), q)
+    Q = oracle.prod(mods[:l1])
+    return [core.centre(v, Q) for v in core.crt(r, mods[:l1])]
+
+
+def test_sum_of_one_rotation_is_the_hoisted_rotation():
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    c0, c1 = _cipher(p, mods, 3, 31)
+    k = core.galois_rotation(12, 3)
+    _, _, evk, _ = core.keygen_rotation(p, mods, 32, k)
+    one = core.rotate_sum_hoisted(p, mods, 3, c0, c1, [k], [evk])
+    assert np.array_equal(one, core.rotate_hoisted(p, mods, 3, c0, c1, [k], [evk])[0])
+    ones = np.ones((1, p.num_q + p.num_p, p.n), np.uint32)
+    assert np.array_equal(core.rotate_sum_hoisted(p, mods, 3, c0, c1, [k], [evk], ones), one)
+
+
+@pytest.mark.parametrize("with_diag", [False, True])
+def test_rotation_sum_decrypts(with_diag):
+    p = oracle.Params(11, 5, 2, 3)
+    mods = oracle.moduli(p)
+    level = 4
+    c0, c1 = _cipher(p, mods, level, 41)
+    gal = [core.galois_rotation(11, r) for r in (0, 1, 2, 5)] + [(2 << 11) - 1]
+    keys = [core.keygen_rotation(p, mods, 42, k) for k in gal]  # one seed: one secret s for every key
+    s, h = keys[0][0], keys[0][3]
+    assert all(np.array_equal(kk[0], s) for kk in keys)
+    diags, coefs = None, [None] * len(gal)
+    if with_diag:
+        dd = [_small_diag(p, mods, 50 + i) for i in range(len(gal))]
+        diags, coefs = [d[0] for d in dd], [d[1] for d in dd]
+    out = core.rotate_sum_hoisted(p, mods, level, c0, c1, gal, [k[2] for k in keys], diags)
+    r = _sum_residual(p, mods, level, c0, c1, out, s, [k[1] for k in keys], gal, coefs)
+    # one ModDown for the sum: the key-switch error of every term, scaled by
+    # the diagonal (at most N * 2 per coefficient), then one rounding
+    E = oracle.noise_bound(p, mods, level, h) - (1 + h) * (1 + p.num_p)
+    scale = p.n * 2 if with_diag else 1
+    B = len(gal) * scale * (E + 1) + (1 + h) * (1 + p.num_p)
+    assert max(abs(v) for v in r) <= B
+    assert B < oracle.prod(mods[:level + 1]) // 4
+
+
+@pytest.mark.parametrize("fault", [1, 2, 5])
+def test_planted_mistakes_break_the_sum_bound(fault):
+    p = oracle.Params(11, 5, 2, 3)
+    mods = oracle.moduli(p)
+    c0, c1 = _cipher(p, mods, 4, 61)
+    gal = [core.galois_rotation(11, r) for r in (1, 3)]
+    keys = [core.keygen_rotation(p, mods, 62, k) for k in gal]
+    s, h = keys[0][0], keys[0][3]
+    oracle.set_fault(fault)
+    try:
+        out = core.rotate_sum_hoisted(p, mods, 4, c0, c1, gal, [k[2] for k in keys])
+    finally:
+        oracle.set_fault(0)
+    r = _sum_residual(p, mods, 4, c0, c1, out, s, [k[1] for k in keys], gal, [None, None])
+    E = oracle.noise_bound(p, mods, 4, h) - (1 + h) * (1 + p.num_p)
+    assert max(abs(v) for v in r) > len(gal) * (E + 1) + (1 + h) * (1 + p.num_p)
