@@ -237,6 +237,24 @@ def rotation_rate(ks, plan, evks, steps, np, torch, synth):
     torch.cuda.synchronize()
     res["hoisted_compressed_keys"] = {"m8": round(8 * reps / (a.elapsed_time(b) / 1e3), 1)}
     del keys_b
+    # double hoisting: the sum of the same 8 rotations, each times a plaintext
+    # diagonal, with one ModUp and one ModDown (Max-Parallel stages)
+    diags = [torch.from_numpy(synth.uniform_limbs(mods, n, synth.seed_for(2, 500 + i)).view(np.int32)).cuda()
+             for i in range(8)]
+    terms = [(evks[i % len(evks)], g, diags[i]) for i, g in enumerate(gal)]
+    ws = plan._ws(ks.ks_rotate_sum_workspace_size(plan.handle, LEVEL, 8), "cuda")
+    out = torch.empty((2, l1, n), dtype=torch.int32, device="cuda")
+    ks.ks_rotate_sum_hoisted(plan.handle, LEVEL, c0, c1, terms, out, ws)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        ks.ks_rotate_sum_hoisted(plan.handle, LEVEL, c0, c1, terms, out, ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    res["double_hoisted_sum_m8"] = {"sums_per_s": round(1e3 / ms, 1), "rotations_per_s": round(8e3 / ms, 1),
+                                    "us_per_sum": round(ms * 1e3, 2)}
+    del diags, ws
     a0, a1 = c0, c1
     b0 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 402)).view(np.int32)).cuda()
     b1 = torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 403)).view(np.int32)).cuda()

@@ -255,6 +255,33 @@ ks_status_t ks_rotate_hoisted_seeded(ks_plan_t plan, uint32_t level, const uint3
                                      uint32_t count, const ks_seeded_rotation_t *rots, void *workspace,
                                      size_t workspace_bytes, void *stream);
 
+/* One term of a double-hoisted rotation sum: the rotation's key evk
+ * [dnum][2][L+1+K][N] (from s(X^galois) to s) and an optional plaintext
+ * diagonal diag [L+1+K][N] (device, key-row order q_0..q_L, p_0..p_{K-1},
+ * evaluation domain, canonical), or NULL for the constant 1. */
+typedef struct {
+  const uint32_t *evk;
+  uint32_t galois;
+  const uint32_t *diag;
+} ks_rotation_term_t;
+
+/* Bytes of workspace ks_rotate_sum_hoisted needs (0 for count 0). */
+ks_status_t ks_rotate_sum_workspace_size(ks_plan_t plan, uint32_t level, uint32_t count, size_t *bytes);
+
+/* Double hoisting (named in Sec. VII): out = sum_r diag_r * sigma_r((c0, c1))
+ * with one ModUp of c1 and one ModDown for the whole sum:
+ *   ACC = sum_r diag_r * sum_j sigma_r(ModUp_j(c1)) * evk_r[j]  (extended basis)
+ *   out = (ModDown(ACC_0) + sum_r diag_r * sigma_r(c0), ModDown(ACC_1)).
+ * The building block of a linear transform's inner sum.  It runs the
+ * Max-Parallel stages (the sum needs every term's product before its one
+ * ModDown) whatever the plan's schedule.  c0, c1 [level+1][N], out
+ * [2][level+1][N] (device, 16-byte aligned); out must not overlap an input,
+ * a key, a diagonal or the workspace (>= ks_rotate_sum_workspace_size,
+ * 256-byte aligned). */
+ks_status_t ks_rotate_sum_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                                  uint32_t count, const ks_rotation_term_t *terms, uint32_t *out,
+                                  void *workspace, size_t workspace_bytes, void *stream);
+
 /* Bytes of workspace ks_mult_relin needs at `level`. */
 ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes);
 

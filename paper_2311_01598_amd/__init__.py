@@ -56,6 +56,10 @@ class ks_seeded_rotation_t(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class ks_rotation_term_t(ctypes.Structure):
+    _fields_ = [("evk", ctypes.c_void_p), ("galois", ctypes.c_uint32), ("diag", ctypes.c_void_p)]
+
+
 _U32P = ctypes.POINTER(ctypes.c_uint32)
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -82,6 +86,10 @@ _SIGS = {
                                          ctypes.POINTER(ks_rotation_t), _VP, ctypes.c_size_t, _VP]),
     "ks_rotate_hoisted_seeded": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
                                                 ctypes.POINTER(ks_seeded_rotation_t), _VP, ctypes.c_size_t, _VP]),
+    "ks_rotate_sum_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "ks_rotate_sum_hoisted": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
+                                             ctypes.POINTER(ks_rotation_term_t), _VP, _VP, ctypes.c_size_t, _VP]),
     "ks_mult_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "ks_mult_relin": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                      _VP]),
@@ -303,6 +311,24 @@ def ks_rotate_hoisted_seeded(plan, level, c0, c1, rots, workspace, workspace_byt
                                          int(workspace_bytes), _stream(stream)), "ks_rotate_hoisted_seeded")
 
 
+def ks_rotate_sum_workspace_size(plan, level, count):
+    n = ctypes.c_size_t(0)
+    _check(_lib.ks_rotate_sum_workspace_size(plan, int(level), int(count), ctypes.byref(n)),
+           "ks_rotate_sum_workspace_size")
+    return n.value
+
+
+def ks_rotate_sum_hoisted(plan, level, c0, c1, terms, out, workspace, workspace_bytes=None, stream=None):
+    """terms: list of (evk, galois, diag or None)."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_rotation_term_t * max(len(terms), 1))()
+    for i, (evk, galois, diag) in enumerate(terms):
+        arr[i] = ks_rotation_term_t(_ptr(evk), int(galois), _ptr(diag) if diag is not None else None)
+    _check(_lib.ks_rotate_sum_hoisted(plan, int(level), _ptr(c0), _ptr(c1), len(terms), arr, _ptr(out),
+                                      _ptr(workspace), int(workspace_bytes), _stream(stream)), "ks_rotate_sum_hoisted")
+
+
 def ks_mult_workspace_size(plan, level):
     n = ctypes.c_size_t(0)
     _check(_lib.ks_mult_workspace_size(plan, int(level), ctypes.byref(n)), "ks_mult_workspace_size")
@@ -466,6 +492,17 @@ class Plan:
         ks_rotate_hoisted_seeded(self.handle, level, c0, c1, [(e, a, g, o) for (e, a, g), o in zip(rots, outs)],
                                  workspace, stream=stream)
         return outs
+
+    def rotate_sum_hoisted(self, level, c0, c1, terms, out=None, workspace=None, stream=None):
+        """terms: list of (evk, galois, diag or None); returns
+        sum_r diag_r * sigma_r((c0, c1)) with one ModUp and one ModDown."""
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int32, device=c1.device)
+        if workspace is None:
+            workspace = self._ws(ks_rotate_sum_workspace_size(self.handle, level, len(terms)), c1.device)
+        ks_rotate_sum_hoisted(self.handle, level, c0, c1, terms, out, workspace, stream=stream)
+        return out
 
     def rotate(self, evk, galois, level, c0, c1, workspace=None, stream=None):
         return self.rotate_hoisted(level, c0, c1, [(evk, galois)], workspace, stream)[0]

@@ -81,6 +81,24 @@ size_t mult_bytes(const Plan &pl, uint32_t level) {
 
 bool galois_ok(const Plan &pl, uint32_t k) { return (k & 1u) && k < 2u * pl.n; }
 
+// Double hoisting: term table, then the MP ModUp output X [l+1], Y [d'][T],
+// the summed accumulator ACC [2][T] and the ModDown buffers XP [2][K],
+// W [2][l+1].
+struct SumLayout {
+  size_t x, y, acc, xp, w, total;
+};
+SumLayout sum_layout(const Plan &pl, uint32_t level, uint32_t count) {
+  const size_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), lb = limb_bytes(pl);
+  SumLayout r;
+  r.x = align256((size_t)count * sizeof(RotTerm));
+  r.y = r.x + align256(L1 * lb);
+  r.acc = r.y + align256(D * T * lb);
+  r.xp = r.acc + align256(2 * T * lb);
+  r.w = r.xp + align256(2 * K * lb);
+  r.total = count ? r.w + align256(2 * L1 * lb) : 0;
+  return r;
+}
+
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
   const char *x = (const char *)a, *y = (const char *)b;
   return x < y + nb && y < x + na;
@@ -94,13 +112,18 @@ ks_status_t dev_err(hipError_t e) { return e == hipSuccess ? KS_OK : KS_ERR_DEVI
     if (_e != hipSuccess) return KS_ERR_DEVICE;    \
   } while (0)
 
+#define TRYK(expr)                    \
+  do {                                \
+    const ks_status_t _s = (expr);    \
+    if (_s != KS_OK) return _s;       \
+  } while (0)
+
 // ---------------------------------------------------------------- MP
 // Sec. IV-A: every stage over all towers, every stage output in HBM.
-ks_status_t run_mp(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
-                   uint32_t *ws, hipStream_t st) {
-  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
-  uint32_t *X = ws, *Y = X + (size_t)L1 * N, *Z = Y + (size_t)D * T * N, *ACC = Z + (size_t)D * 2 * T * N;
-  uint32_t *XP = ACC + (size_t)2 * T * N, *W = XP + (size_t)2 * K * N;
+// ModUp P1-P3 in the MP order: X [l+1] (INTT of d), Y [d'][T] (every digit
+// extended, evaluation domain; a digit's own towers are left to d).
+ks_status_t mp_modup(const Plan &pl, uint32_t level, const uint32_t *d, uint32_t *X, uint32_t *Y, hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level);
   std::vector<uint32_t> so, dof, g;
   // ModUp P1: INTT of all towers
   for (uint32_t i = 0; i < L1; i++) { so.push_back(i); dof.push_back(i); g.push_back(i); }
@@ -118,11 +141,15 @@ ks_status_t run_mp(const Plan &pl, const uint32_t *evk, uint32_t level, const ui
     }
   }
   TRY(launch_ntt(pl, false, Y, Y, so, dof, g, st));
-  // P4: apply key, P5: sum over digits
-  TRY(launch_keymul(pl, level, d, Y, evk, Z, st));
-  TRY(launch_reduce_digits(pl, level, Z, ACC, st));
+  return KS_OK;
+}
+
+// ModDown P1-P4 in the MP order from ACC [2][T] (carrying 2^-32) to out.
+ks_status_t mp_moddown(const Plan &pl, uint32_t level, const uint32_t *ACC, uint32_t *XP, uint32_t *W, uint32_t *out,
+                       hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K;
+  std::vector<uint32_t> so, dof, g;
   // ModDown P1: INTT of the K special towers of both polynomials
-  so.clear(); dof.clear(); g.clear();
   for (uint32_t s = 0; s < 2; s++)
     for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl.num_q + k); }
   TRY(launch_ntt(pl, true, ACC, XP, so, dof, g, st));
@@ -134,6 +161,18 @@ ks_status_t run_mp(const Plan &pl, const uint32_t *evk, uint32_t level, const ui
   TRY(launch_ntt(pl, false, W, W, so, dof, g, st));
   TRY(launch_moddown_final(pl, level, ACC, W, out, st));
   return KS_OK;
+}
+
+ks_status_t run_mp(const Plan &pl, const uint32_t *evk, uint32_t level, const uint32_t *d, uint32_t *out,
+                   uint32_t *ws, hipStream_t st) {
+  const uint32_t L1 = level + 1, K = pl.num_p, T = L1 + K, D = num_digits(pl, level), N = pl.n;
+  uint32_t *X = ws, *Y = X + (size_t)L1 * N, *Z = Y + (size_t)D * T * N, *ACC = Z + (size_t)D * 2 * T * N;
+  uint32_t *XP = ACC + (size_t)2 * T * N, *W = XP + (size_t)2 * K * N;
+  TRYK(mp_modup(pl, level, d, X, Y, st));
+  // P4: apply key, P5: sum over digits
+  TRY(launch_keymul(pl, level, d, Y, evk, Z, st));
+  TRY(launch_reduce_digits(pl, level, Z, ACC, st));
+  return mp_moddown(pl, level, ACC, XP, W, out, st);
 }
 
 // ---------------------------------------------------------------- DC
@@ -714,6 +753,55 @@ ks_status_t ks_rotate_hoisted_seeded(ks_plan_t plan, uint32_t level, const uint3
   std::vector<Rot> r(count);
   for (uint32_t i = 0; i < count; i++) r[i] = Rot{rots[i].evk_b, rots[i].a_seed, rots[i].galois, rots[i].out};
   return rotate_hoisted(plan, level, c0, c1, r, true, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_rotate_sum_workspace_size(ks_plan_t plan, uint32_t level, uint32_t count, size_t *bytes) {
+  if (!plan || !bytes || level >= plan->p.num_q) return KS_ERR_INVALID_ARG;
+  *bytes = sum_layout(plan->p, level, count).total;
+  return KS_OK;
+}
+
+ks_status_t ks_rotate_sum_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, const uint32_t *c1,
+                                  uint32_t count, const ks_rotation_term_t *terms, uint32_t *out, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  if (!count) return KS_OK;
+  if (!terms || !c0 || !c1 || !out || !workspace) return KS_ERR_INVALID_ARG;
+  if ((((uintptr_t)c0 | (uintptr_t)c1 | (uintptr_t)out) & 15) || ((uintptr_t)workspace & 255))
+    return KS_ERR_INVALID_ARG;
+  const SumLayout lay = sum_layout(pl, level, count);
+  if (workspace_bytes < lay.total) return KS_ERR_BUDGET;
+  const size_t lb = limb_bytes(pl), in_b = (size_t)(level + 1) * lb, out_b = 2 * in_b;
+  const size_t evk_b = (size_t)pl.dnum * 2 * pl.ntot * lb, diag_b = (size_t)pl.ntot * lb;
+  if (overlaps(out, out_b, c0, in_b) || overlaps(out, out_b, c1, in_b) ||
+      overlaps(out, out_b, workspace, workspace_bytes) || overlaps(workspace, workspace_bytes, c0, in_b) ||
+      overlaps(workspace, workspace_bytes, c1, in_b))
+    return KS_ERR_INVALID_ARG;
+  std::vector<RotTerm> ht(count);
+  for (uint32_t r = 0; r < count; r++) {
+    const ks_rotation_term_t &x = terms[r];
+    if (!x.evk || ((uintptr_t)x.evk & 15) || ((uintptr_t)x.diag & 3) || !galois_ok(pl, x.galois))
+      return KS_ERR_INVALID_ARG;
+    if (overlaps(out, out_b, x.evk, evk_b) || overlaps(workspace, workspace_bytes, x.evk, evk_b))
+      return KS_ERR_INVALID_ARG;
+    if (x.diag && (overlaps(out, out_b, x.diag, diag_b) || overlaps(workspace, workspace_bytes, x.diag, diag_b)))
+      return KS_ERR_INVALID_ARG;
+    ht[r] = RotTerm{x.evk, x.diag, x.galois, 0};
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  uint32_t *X = (uint32_t *)(ws + lay.x), *Y = (uint32_t *)(ws + lay.y), *ACC = (uint32_t *)(ws + lay.acc);
+  uint32_t *XP = (uint32_t *)(ws + lay.xp), *W = (uint32_t *)(ws + lay.w);
+  const RotTerm *dterms = (const RotTerm *)ws;
+  TRY(upload_async(pl, ws, ht.data(), ht.size() * sizeof(RotTerm), st));
+  TRYK(mp_modup(pl, level, c1, X, Y, st));
+  TRY(launch_rotsum_keymul(pl, level, c1, Y, dterms, count, ACC, st));
+  TRYK(mp_moddown(pl, level, ACC, XP, W, out, st));
+  return dev_err(launch_rotsum_c0(pl, level, c0, dterms, count, out, st));
 }
 
 ks_status_t ks_mult_workspace_size(ks_plan_t plan, uint32_t level, size_t *bytes) {

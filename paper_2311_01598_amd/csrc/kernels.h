@@ -54,6 +54,22 @@ hipError_t launch_expand_a(const Plan &pl, uint64_t seed, uint32_t *evk, hipStre
 // X -> X^galois in the evaluation domain.
 hipError_t launch_automorphism(const Plan &pl, uint32_t galois, uint32_t count, const uint32_t *in, uint32_t *out,
                                hipStream_t st);
+// One term of a double-hoisted rotation sum: the rotation's key (full
+// layout), its plaintext diagonal ([L+1+K][N] in key-row order, or null for
+// 1) and its Galois element.
+struct RotTerm {
+  const uint32_t *evk;
+  const uint32_t *diag;
+  uint32_t galois, pad;
+};
+// ACC [2][T] (carrying 2^-32, as the MP ModDown expects) = sum over the terms
+// of diag * sum_j sigma(yhat_j) * evk[j]; yhat_j is Y's digit j with the
+// digit's own towers read from d.
+hipError_t launch_rotsum_keymul(const Plan &pl, uint32_t level, const uint32_t *d, const uint32_t *y,
+                                const RotTerm *terms, uint32_t nterm, uint32_t *acc, hipStream_t st);
+// out[0][i] += sum over the terms of diag * sigma(c0[i]).
+hipError_t launch_rotsum_c0(const Plan &pl, uint32_t level, const uint32_t *c0, const RotTerm *terms, uint32_t nterm,
+                            uint32_t *out, hipStream_t st);
 // Tensor product of (a0, a1) and (b0, b1) at `level`: d [3][l+1][N] =
 // (a0 b0, a0 b1 + a1 b0, a1 b1), pointwise, canonical.
 hipError_t launch_tensor(const Plan &pl, uint32_t level, const uint32_t *a0, const uint32_t *a1, const uint32_t *b0,

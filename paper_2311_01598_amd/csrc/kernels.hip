@@ -434,6 +434,83 @@ hipError_t launch_tensor(const Plan &pl, uint32_t level, const uint32_t *a0, con
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ double hoisting
+// exact a b mod q: REDC(a b) = a b 2^-32, then a Shoup product by 2^32 mod q
+__device__ __forceinline__ uint32_t mulmod_exact(uint32_t a, uint32_t b, const ModQ &m, uint32_t r32,
+                                                 uint32_t r32p) {
+  return csub(mul_shoup(redc64((uint64_t)a * b, m), r32, r32p, m.q), m.q);
+}
+
+// grid (N/256, T): both polynomials per thread, so each gathered digit word
+// is read once for the two key halves
+__global__ __launch_bounds__(256) void k_rotsum_keymul(DevPlan P, uint32_t level, const uint32_t *__restrict__ d,
+                                                       const uint32_t *__restrict__ y,
+                                                       const RotTerm *__restrict__ terms, uint32_t nterm,
+                                                       uint32_t *__restrict__ acc) {
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x, t = blockIdx.y;
+  const uint32_t L1 = level + 1, T = L1 + P.num_p, g = gidx(P, level, t), ndig = (L1 + P.alpha - 1) / P.alpha;
+  const ModQ m = P.mods[g];
+  const uint32_t r32 = (0u - m.q) % m.q;
+  const uint32_t r32p = shoup_companion(r32, m.q, P.qrecip[g]);
+  const size_t half = (size_t)P.ntot * N;  // from a key row of half 0 to the same row of half 1
+  uint32_t total0 = 0, total1 = 0;
+  for (uint32_t r = 0; r < nterm; r++) {
+    const RotTerm rt = terms[r];
+    const size_t src = galois_perm(c, rt.galois, P.log_n);
+    uint64_t a0 = 0, a1 = 0;  // at most 16 digits: no overflow
+    for (uint32_t j = 0; j < ndig; j++) {
+      const uint32_t yv = yhat_at(P, level, j, t, d, y + (size_t)j * T * N, N, src, m.q);
+      const uint32_t *e = rt.evk + ((size_t)j * 2 * P.ntot + g) * N + c;
+      a0 += (uint64_t)yv * e[0];
+      a1 += (uint64_t)yv * e[half];
+    }
+    uint32_t v0 = redc64(a0, m), v1 = redc64(a1, m);
+    if (rt.diag) {
+      const uint32_t pv = rt.diag[(size_t)g * N + c];
+      v0 = mulmod_exact(v0, pv, m, r32, r32p);
+      v1 = mulmod_exact(v1, pv, m, r32, r32p);
+    }
+    total0 = csub(total0 + v0, m.q);
+    total1 = csub(total1 + v1, m.q);
+  }
+  acc[(size_t)t * N + c] = total0;
+  acc[((size_t)T + t) * N + c] = total1;
+}
+
+hipError_t launch_rotsum_keymul(const Plan &pl, uint32_t level, const uint32_t *d, const uint32_t *y,
+                                const RotTerm *terms, uint32_t nterm, uint32_t *acc, hipStream_t st) {
+  const uint32_t T = level + 1 + pl.num_p;
+  KS_LAUNCH(pl, "rotsum_keymul", k_rotsum_keymul, dim3(pl.n / 256, T), dim3(256), 0, st, pl.dev, level, d, y, terms,
+            nterm, acc);
+  return hipGetLastError();
+}
+
+// grid (N/256, l+1); out[0][i] is canonical, so is the result
+__global__ __launch_bounds__(256) void k_rotsum_c0(DevPlan P, const uint32_t *__restrict__ c0,
+                                                   const RotTerm *__restrict__ terms, uint32_t nterm,
+                                                   uint32_t *__restrict__ out) {
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  const ModQ m = P.mods[i];
+  const uint32_t r32 = (0u - m.q) % m.q;
+  const uint32_t r32p = shoup_companion(r32, m.q, P.qrecip[i]);
+  uint32_t v = out[(size_t)i * N + c];
+  for (uint32_t r = 0; r < nterm; r++) {
+    const RotTerm rt = terms[r];
+    uint32_t x = c0[(size_t)i * N + galois_perm(c, rt.galois, P.log_n)];
+    if (rt.diag) x = mulmod_exact(x, rt.diag[(size_t)i * N + c], m, r32, r32p);
+    v = csub(v + x, m.q);
+  }
+  out[(size_t)i * N + c] = v;
+}
+
+hipError_t launch_rotsum_c0(const Plan &pl, uint32_t level, const uint32_t *c0, const RotTerm *terms, uint32_t nterm,
+                            uint32_t *out, hipStream_t st) {
+  KS_LAUNCH(pl, "rotsum_c0", k_rotsum_c0, dim3(pl.n / 256, level + 1), dim3(256), 0, st, pl.dev, c0, terms, nterm, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ OC entry
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want) {
   // two targets per tile keep 2 x 16 accumulators per thread; columns of

@@ -87,6 +87,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "ks_config_t": ["schedule", "tile_towers", "batch_mode", "spin_limit"],
         "ks_rotation_t": ["evk", "galois", "out"],
         "ks_seeded_rotation_t": ["evk_b", "a_seed", "galois", "out"],
+        "ks_rotation_term_t": ["evk", "galois", "diag"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ks.h"', "int main(void) {"]
     for t, fields in checks.items():

@@ -137,6 +137,66 @@ def test_hoisted_compressed_keys(ks, shape):
     plan.close()
 
 
+def _diag(mods, n, seed):
+    """A plaintext diagonal in every key row: uniform residues (any value is
+    a valid operand of the exact product)."""
+    return synth.uniform_limbs(mods, n, seed)
+
+
+@pytest.mark.parametrize("shape,with_diag", [((12, 4, 2, 2, 3), False), ((12, 4, 2, 2, 2), True),
+                                             ((16, 24, 3, 8, 23), True), ((13, 9, 3, 2, 5), True),
+                                             ((12, 7, 7, 1, 6), False)])
+def test_double_hoisted_sum(ks, shape, with_diag):
+    log_n, num_q, dnum, num_p, level = shape
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = oracle.moduli(p)
+    c0 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(27, 0))
+    c1 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(27, 1))
+    gal = [core.galois_rotation(log_n, r) for r in (0, 1, 3)] + [(2 << log_n) - 1]
+    keys = [synth.uniform_evk(mods, dnum, p.n, synth.seed_for(27, 10 + i)) for i in range(len(gal))]
+    diags = [_diag(mods, p.n, synth.seed_for(27, 30 + i)) for i in range(len(gal))] if with_diag else None
+    want = core.rotate_sum_hoisted(p, mods, level, c0, c1, gal, keys, diags)
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    print(f"[rot sum] {shape} diag={with_diag}", flush=True)
+    terms = [(dev(k), g, dev(diags[i]) if with_diag else None) for i, (k, g) in enumerate(zip(keys, gal))]
+    for sched in ("oc", "mp"):  # the sum runs the same stages under any schedule
+        plan.configure(sched)
+        got = host(plan.rotate_sum_hoisted(level, dev(c0), dev(c1), terms))
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, (sched, bad[:5], len(bad))
+    plan.close()
+
+
+def test_double_hoisted_sum_decrypts(ks):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = oracle.moduli(p)
+    level = 3
+    c0 = synth.uniform_limbs(mods[:4], p.n, synth.seed_for(28, 0))
+    c1 = synth.uniform_limbs(mods[:4], p.n, synth.seed_for(28, 1))
+    gal = [core.galois_rotation(12, r) for r in (1, 2, 7)]
+    keys = [core.keygen_rotation(p, mods, 71, k) for k in gal]  # one seed: one secret
+    plan = ks.Plan(12, 4, 2, 2)
+    got = host(plan.rotate_sum_hoisted(level, dev(c0), dev(c1), [(dev(k[2]), g, None) for k, g in zip(keys, gal)]))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, core.rotate_sum_hoisted(p, mods, level, c0, c1, gal, [k[2] for k in keys]))
+    # r = c0' + c1' s - sum_r sigma_r(c0 + c1 s), assembled from the oracle's
+    # residual helper (linear modulo Q before centring), is within the summed
+    # key-switch error plus one ModDown rounding
+    s, h = keys[0][0], keys[0][3]
+    Q = oracle.prod(mods[:4])
+    sc0 = sum(core.automorphism_eval(c0, 12, k).astype(np.int64) for k in gal)
+    out0 = np.stack([(got[0][i].astype(np.int64) - sc0[i]) % int(mods[i]) for i in range(4)]).astype(np.uint32)
+    zero = np.zeros((4, p.n), np.uint32)
+    r = oracle.decrypt_residual(p, mods, level, zero, np.stack([out0, got[1]]), s, s)  # c0'' + c1' s
+    for k, (_, sk, _, _) in zip(gal, keys):  # - sigma_r(c1) sigma_r(s)
+        sc1 = core.automorphism_eval(c1, 12, k)
+        r = [a + b for a, b in zip(r, oracle.decrypt_residual(p, mods, level, sc1, np.stack([zero, zero]), s, sk))]
+    worst = max(abs(core.centre(v % Q, Q)) for v in r)
+    E = oracle.noise_bound(p, mods, level, h) - (1 + h) * (1 + p.num_p)
+    assert worst <= len(gal) * (E + 1) + (1 + h) * (1 + p.num_p)
+    plan.close()
+
+
 SHAPES = [
     (12, 5, 2, 0, [4, 0]),     # partial last digit; level 0
     (12, 4, 1, 0, [3]),        # dnum = 1
