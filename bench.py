@@ -408,6 +408,16 @@ def serving_rate(ks, count, np, torch, synth, seed=5):
     res["poisson"] = {"offered_per_s": round(rate, 1), "ks_per_s": round(st["ks_per_s"], 1),
                       "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "batches": st["batches"],
                       "high_water_gib": round(st["high_water_bytes"] / 2**30, 3)}
+    # the same requests with every key compressed (b halves plus a seed):
+    # half the resident key bytes
+    ckeys = {k: [(e.view(3, 2, -1)[:, 0].contiguous(), 900 + i) for i, e in enumerate(v)] for k, v in keys.items()}
+    srv = Server(plans, ckeys, budget, streams=2, max_batch=16)
+    st = srv.run([(0.0, r) for r in requests()])
+    res["saturation_compressed_keys"] = {"ks_per_s": round(st["ks_per_s"], 1), "batches": st["batches"]}
+    res["resident_key_gib"] = {"full": round(sum(e.numel() * 4 for v in keys.values() for e in v) / 2**30, 2),
+                               "compressed": round(sum(b.numel() * 4 for v in ckeys.values() for b, _ in v) / 2**30,
+                                                   2)}
+    del ckeys
     # the same request mix, one key switch per call with MP on one stream
     for p in plans.values():
         p.configure("mp")

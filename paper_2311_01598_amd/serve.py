@@ -1,15 +1,18 @@
 """Serving loop: continuous batching of key-switch requests on one GPU.
 
 * Keys (relinearisation + rotation keys) stay resident in HBM per ring
-  degree; a request names a key, a ring degree and a level, and carries its
-  input polynomial (already rotated, for a rotation key).
+  degree, either full ([dnum][2][L+1+K][N]) or compressed (the b halves plus
+  the seed of the a halves, Sec. IV-D: half the resident bytes); a request
+  names a key, a ring degree and a level, and carries its input polynomial
+  (already rotated, for a rotation key).
 * Admission by memory: every batch needs workspace (from a preallocated HBM
   pool, first-fit) plus output buffers; requests wait while the bytes in
   flight plus theirs would exceed the budget, and a request that could never
   fit is rejected.
 * Continuous batching: whenever one of `streams` slots is free, the queued
-  requests of one ring degree (oldest first) form a batch that is launched
-  with ks_keyswitch_batch on that slot's stream; completions are polled with
+  requests of one ring degree and key kind (oldest first) form a batch that
+  is launched with ks_keyswitch_batch (or ks_keyswitch_batch_seeded) on that
+  slot's stream; completions are polled with
   events, so requests arriving while others run are admitted as slots and
   memory free up, and batches on different streams overlap on the device.
 * Metrics: per-request latency (arrival to observed completion), p50/p99,
@@ -69,7 +72,8 @@ class Request:
 
 class Server:
     def __init__(self, plans, keys, budget_bytes, streams=2, max_batch=16):
-        """plans: {log_n: Plan}; keys: {log_n: [evk tensors]} (resident)."""
+        """plans: {log_n: Plan}; keys: {log_n: [key]} (resident), a key being
+        a full evk tensor or a compressed key (b-half tensor, a_seed)."""
         import torch
         self.torch = torch
         self.plans, self.keys = plans, keys
@@ -87,6 +91,9 @@ class Server:
         self.batches = 0
 
     # ---------------------------------------------------------------- admission
+    def _compressed(self, r):
+        return isinstance(self.keys[r.log_n][r.key], tuple)
+
     def _out_bytes(self, r):
         return 2 * (r.level + 1) * self.plans[r.log_n].n * 4
 
@@ -114,10 +121,10 @@ class Server:
     def _form_batch(self):
         if not self.queue:
             return None
-        n0 = self.queue[0].log_n
+        n0, c0 = self.queue[0].log_n, self._compressed(self.queue[0])
         batch = []
         for r in list(self.queue):
-            if r.log_n != n0 or len(batch) >= self.max_batch:
+            if r.log_n != n0 or self._compressed(r) != c0 or len(batch) >= self.max_batch:
                 continue
             ws, need = self._need(batch + [r])
             if self.in_flight + need > self.budget:
@@ -144,9 +151,13 @@ class Server:
                 r.out = torch.empty((2, r.level + 1, plan.n), dtype=torch.int32, device="cuda")
                 r.t_start = now
                 r.status = "running"
-            jobs = [(self.keys[r.log_n][r.key], r.level, r.d, r.out) for r in batch]
             try:
-                plan.keyswitch_batch(jobs, workspace=self.pool.view(*blk), stream=st)
+                if self._compressed(batch[0]):
+                    jobs = [self.keys[r.log_n][r.key] + (r.level, r.d, r.out) for r in batch]
+                    plan.keyswitch_batch_seeded(jobs, workspace=self.pool.view(*blk), stream=st)
+                else:
+                    jobs = [(self.keys[r.log_n][r.key], r.level, r.d, r.out) for r in batch]
+                    plan.keyswitch_batch(jobs, workspace=self.pool.view(*blk), stream=st)
             except Exception as e:  # a failed launch fails only this batch
                 for r in batch:
                     r.status = f"failed: {e}"

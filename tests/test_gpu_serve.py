@@ -149,3 +149,39 @@ def test_invalid_requests_rejected(ks, setup):
     bad = [Request(0, NKEYS, LOG_N, 0, d, 0.0), Request(1, 0, LOG_N, NUM_Q, d, 0.0), Request(2, 0, 16, 0, d, 0.0)]
     st = server.run([(0.0, r) for r in bad], max_seconds=10)
     assert st["rejected"] == 3 and st["completed"] == 0
+
+
+@pytest.mark.gpu
+def test_compressed_keys_served_equal_alone(ks, setup):
+    """Keys resident half full, half compressed (b halves plus a seed): batches
+    never mix the two kinds, and every served result equals the request run
+    alone with MP on the expanded key (tolerance 0); one also equals the
+    oracle."""
+    from paper_2311_01598_amd.serve import Server, poisson_arrivals
+    plan, full_keys = setup
+    keys, expanded = [], []
+    for k, e in enumerate(full_keys):
+        if k % 2:
+            b = e.view(DNUM, 2, -1)[:, 0].contiguous()
+            ex = torch.zeros_like(e)
+            ex.view(DNUM, 2, -1)[:, 0] = b
+            plan.expand_seeded_a(4242 + k, ex)
+            keys.append((b, 4242 + k))
+            expanded.append(ex)
+        else:
+            keys.append(e)
+            expanded.append(e)
+    reqs = _requests(plan, 40, seed=13)
+    server = Server({LOG_N: plan}, {LOG_N: keys}, budget_bytes=64 << 20, streams=3, max_batch=8)
+    st = server.run(list(zip(poisson_arrivals(20000.0, len(reqs), seed=14), reqs)), max_seconds=60)
+    print(st, flush=True)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert any(k % 2 for k in (r.key for r in reqs)) and any(k % 2 == 0 for k in (r.key for r in reqs))
+    for r in reqs:
+        assert torch.equal(r.out, _alone(plan, expanded, r)), f"request {r.rid} key {r.key}"
+    from oracle import core
+    r = next(x for x in reqs if x.key % 2)
+    evk = expanded[r.key].cpu().numpy().view(np.uint32)
+    want = core.keyswitch(core.Params(LOG_N, NUM_Q, DNUM, plan.num_p), plan.moduli, r.level, evk,
+                          r.d.cpu().numpy().view(np.uint32))
+    assert np.array_equal(r.out.cpu().numpy().view(np.uint32), want)
