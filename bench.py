@@ -142,14 +142,19 @@ def seeded_rate(ks, plan, evks, d, steps, warmup, count, np, torch, synth):
             plan.keyswitch_seeded(keys[i % len(keys)], 1000 + i % len(keys), LEVEL, d, out=out, workspace=ws)
     single(warmup)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    single(steps)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]  # latency pass
     for i in range(steps):
         ev[i].record()
         plan.keyswitch_seeded(keys[i % len(keys)], 1000 + i % len(keys), LEVEL, d, out=out, workspace=ws)
     ev[steps].record()
     torch.cuda.synchronize()
     lat = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
-    ms = ev[0].elapsed_time(ev[steps])
     ks.ks_trace_enable(plan.handle, True)
     single(steps)
     ks.ks_trace_enable(plan.handle, False)
@@ -516,8 +521,12 @@ def main():
             lat.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
         return ms, wall
 
+    # throughput: K steps with nothing recorded between them; latency
+    # percentiles from a second pass with an event before and after each step
+    # (the events cost a few microseconds per step, kept out of `value`)
+    ms, wall = run(args.schedule, args.steps, args.warmup)
     lat = []
-    ms, wall = run(args.schedule, args.steps, args.warmup, lat)
+    run(args.schedule, args.steps, 0, lat)
     # Per-kernel durations: the same K steps again with start/stop events
     # attached to every kernel dispatch (kept out of the timed region above,
     # because the traced launch path costs host time between kernels).
