@@ -596,6 +596,12 @@ def main():
     res["stages"] = stages
     if args.batch:
         res["batched"] = batched_rate(ks, plan, evks, mods, args.batch, max(5, args.steps // 20), np, torch, synth)
+        bk = res["batched"]["ks_per_s"]
+        # HBM rates of the batched run: compulsory bytes (input, key, output)
+        # and the stages' algorithmic bytes, per second, against the peak
+        res["batched"]["hbm_gbs_algorithmic"] = round(nbytes * bk / 1e9, 1)
+        res["batched"]["stage_bytes_gbs"] = round(tot_bytes * bk / 1e9, 1)
+        res["batched"]["stage_bytes_frac"] = round(tot_bytes * bk / (HBM_PEAK_GBS * 1e9), 4)
     if args.bts:
         res["bts_scale"] = bts_rate(ks, max(20, args.steps // 4), np, torch, synth)
     if args.rotations:

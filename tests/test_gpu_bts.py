@@ -1,7 +1,8 @@
 """GPU parity at bootstrapping scale: the BTS1 / BTS2 / BTS3 parameter sets
 of Table III (N = 2^17; 28+28 towers with dnum 1, 40+20 with dnum 2, 45+15
-with dnum 3), 30-bit towers, at full size with every output element
-compared against the oracle.  These stress the 2^17 two-pass transform
+with dnum 3), 30-bit towers, and the serving workload's largest plan
+(N = 2^17, 48 towers, dnum 3, K = 16, two targets per conversion tile), at
+full size with every output element compared against the oracle.  These stress the 2^17 two-pass transform
 (512 x 256), conversions with more than 16 source towers (alpha 28 and 20,
 and K = 28 / 20 for ModDown, accumulated in chunks of 16 products), and
 the single-digit case where ModUp has no Q target.  BTS3 also runs with a
@@ -19,7 +20,9 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15),
+       # the serving workload's largest plan: N = 2^17, 48 towers, dnum 3, K = alpha = 16
+       "serve17": (17, 48, 3, 0)}
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +41,7 @@ def host(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-@pytest.mark.parametrize("name", ["bts1", "bts2", "bts3"])
+@pytest.mark.parametrize("name", ["bts1", "bts2", "bts3", "serve17"])
 def test_bts_full_size(ks, name):
     log_n, num_q, dnum, num_p = BTS[name]
     p = oracle.Params(log_n, num_q, dnum, num_p)
@@ -53,10 +56,15 @@ def test_bts_full_size(ks, name):
     want = oracle.keyswitch(p, mods, level, evk, d)
     plan = ks.Plan(log_n, num_q, dnum, num_p)
     runs = [("oc", None)] + ([("mp", None)] if name == "bts2" else []) + ([("oc", "seeded")] if name == "bts3" else [])
+    if name == "serve17":  # the serving loop's configuration: two targets per conversion tile
+        runs = [("oc2", None)]
     for sched, kind in runs:
         print(f"[{name}] {sched} {kind or ''}", flush=True)
         sys.stdout.flush()
-        plan.configure(sched)
+        if sched == "oc2":
+            plan.configure("oc", tile_towers=2)
+        else:
+            plan.configure(sched)
         if kind == "seeded":
             out = plan.keyswitch_seeded(dev(np.ascontiguousarray(evk[:, 0])), a_seed, level, dev(d))
         else:
