@@ -257,8 +257,9 @@ ks_status_t ks_rotate_hoisted_seeded(ks_plan_t plan, uint32_t level, const uint3
 
 /* One term of a double-hoisted rotation sum: the rotation's key evk
  * [dnum][2][L+1+K][N] (from s(X^galois) to s) and an optional plaintext
- * diagonal diag [L+1+K][N] (device, key-row order q_0..q_L, p_0..p_{K-1},
- * evaluation domain, canonical), or NULL for the constant 1. */
+ * diagonal diag [L+1+K][N] (device, 16-byte aligned, key-row order
+ * q_0..q_L, p_0..p_{K-1}, evaluation domain, canonical), or NULL for the
+ * constant 1. */
 typedef struct {
   const uint32_t *evk;
   uint32_t galois;

@@ -782,7 +782,7 @@ ks_status_t ks_rotate_sum_hoisted(ks_plan_t plan, uint32_t level, const uint32_t
   std::vector<RotTerm> ht(count);
   for (uint32_t r = 0; r < count; r++) {
     const ks_rotation_term_t &x = terms[r];
-    if (!x.evk || ((uintptr_t)x.evk & 15) || ((uintptr_t)x.diag & 3) || !galois_ok(pl, x.galois))
+    if (!x.evk || (((uintptr_t)x.evk | (uintptr_t)x.diag) & 15) || !galois_ok(pl, x.galois))
       return KS_ERR_INVALID_ARG;
     if (overlaps(out, out_b, x.evk, evk_b) || overlaps(workspace, workspace_bytes, x.evk, evk_b))
       return KS_ERR_INVALID_ARG;

@@ -110,3 +110,11 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[t]) == ctypes.sizeof(cls), t
         for f in fields:
             assert int(got[f"{t}.{f}"]) == getattr(cls, pyname.get(f, f)).offset, (t, f)
+
+
+def test_galois_rotation_matches_oracle():
+    from oracle import core
+    for log_n in (12, 16, 17):
+        for r in (0, 1, 2, 5, -1, -7, (1 << log_n) // 2 - 1):
+            assert ks.galois_rotation(log_n, r) == core.galois_rotation(log_n, r)
+    assert ks.galois_rotation(12, 1) == 5

@@ -287,3 +287,69 @@ def test_rotation_rejections(ks):
         plan.automorphism(c0, 6)
     assert e.value.status == ks.KS_ERR_INVALID_ARG
     plan.close()
+
+
+def test_argument_errors_of_the_callers(ks):
+    """Argument errors of the rotation, sum, multiplication, automorphism and
+    compressed-key entry points are rejected on the host before any launch
+    (every buffer here is in bounds either way); empty calls succeed."""
+    plan = ks.Plan(12, 4, 2, 2)
+    mods, n = plan.moduli, plan.n
+    c0 = dev(synth.uniform_limbs(mods[:4], n, 1))
+    c1 = dev(synth.uniform_limbs(mods[:4], n, 2))
+    evk = dev(synth.uniform_evk(mods, 2, n, 3))
+    big = torch.zeros((8, 4, n), dtype=torch.int32, device="cuda")
+    out = big[0:2]
+    E = ks.KsError
+    # empty calls
+    ks.ks_rotate_hoisted(plan.handle, 3, c0, c1, [], plan._ws(256, "cuda"))
+    ks.ks_rotate_sum_hoisted(plan.handle, 3, c0, c1, [], out, plan._ws(256, "cuda"))
+    ks.ks_automorphism(plan.handle, 5, 0, c0, out)
+    ks.ks_keyswitch_batch_seeded(plan.handle, [], plan._ws(256, "cuda"))
+    assert ks.ks_rotate_workspace_size(plan.handle, 3, 0) == 0
+    assert ks.ks_rotate_sum_workspace_size(plan.handle, 3, 0) == 0
+    # rotation sum
+    ws = plan._ws(ks.ks_rotate_sum_workspace_size(plan.handle, 3, 1), "cuda")
+    diag = big[4:8].reshape(-1)[: 6 * n]  # one diagonal of L+1+K = 6 rows
+    cases = [
+        (dict(terms=[(evk, 6, None)]), ks.KS_ERR_INVALID_ARG),              # even element
+        (dict(terms=[(evk, 5, diag[1:])]), ks.KS_ERR_INVALID_ARG),          # misaligned diagonal
+        (dict(terms=[(evk, 5, big[2:].reshape(-1))], out=big[2:4]), ks.KS_ERR_INVALID_ARG),  # out inside a diagonal
+        (dict(ws=ws[: ws.numel() // 2]), ks.KS_ERR_BUDGET),
+        (dict(out=big[0:2], c0=big[1]), ks.KS_ERR_INVALID_ARG),             # out over c0
+    ]
+    for kw, status in cases:
+        a = dict(terms=[(evk, 5, diag)], out=out, ws=ws, c0=c0)
+        a.update(kw)
+        with pytest.raises(E) as e:
+            ks.ks_rotate_sum_hoisted(plan.handle, 3, a["c0"], c1, a["terms"], a["out"], a["ws"])
+        assert e.value.status == status, kw
+    # multiplication
+    wsm = plan._ws(ks.ks_mult_workspace_size(plan.handle, 3), "cuda")
+    with pytest.raises(E) as e:
+        ks.ks_mult_relin(plan.handle, evk, 3, c0, c1, c0, c1, out, wsm[: wsm.numel() // 2])
+    assert e.value.status == ks.KS_ERR_BUDGET
+    with pytest.raises(E) as e:
+        ks.ks_mult_relin(plan.handle, evk, 3, big[0], c1, c0, c1, big[0:2], wsm)  # out over a0
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    with pytest.raises(E) as e:
+        ks.ks_mult_relin(plan.handle, evk, 4, c0, c1, c0, c1, out, wsm)  # level beyond L
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    # automorphism: output over the input, bad element
+    with pytest.raises(E) as e:
+        ks.ks_automorphism(plan.handle, 5, 2, big[0], big[0])
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    with pytest.raises(E) as e:
+        ks.ks_automorphism(plan.handle, 2 * n + 1, 1, c0, out)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    # expansion of compressed keys: misaligned destination
+    with pytest.raises(E) as e:
+        ks.ks_expand_seeded_a(plan.handle, 1, evk.view(-1)[1:])
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    # hoisted rotations with compressed keys: an output inside a key
+    b = evk.view(2, 2, -1)[:, 0].contiguous()
+    wsr = plan._ws(ks.ks_rotate_workspace_size(plan.handle, 3, 1), "cuda")
+    with pytest.raises(E) as e:
+        ks.ks_rotate_hoisted_seeded(plan.handle, 3, c0, c1, [(b, 1, 5, b.view(-1)[: 8 * n].view(2, 4, n))], wsr)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
+    plan.close()
