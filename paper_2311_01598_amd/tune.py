@@ -5,8 +5,9 @@ A configuration is (schedule, tile_towers, col_width, row_block): the
 execution order of Sec. IV (MP, DC or OC) and its tile shapes.  All
 configurations compute identical bits, so the tuner only measures time.
 Exhaustive search times every configuration (median of `reps` runs after a
-warm-up) and is the fallback and the judge of the cost-model-pruned search
-(costmodel.py), which times only the predicted best few.
+warm-up) and is the fallback, and the reference that the cost-model-pruned
+search (costmodel.py), which times only the predicted best few, is scored
+against.
 
 Command line (on a GPU machine):
     python -m paper_2311_01598_amd.tune collect --out timings.jsonl [--quick]
@@ -251,11 +252,10 @@ def main(argv=None):
     if a.cmd == "collect":
         collect(a.out, a.quick, a.reps)
     elif a.cmd == "report":
-        cmds = ("python3 -u -m paper_2311_01598_amd.tune collect --out gpurun_out/timings.jsonl --reps 3",
-                "python3 -u -m paper_2311_01598_amd.tune experiment --db gpurun_out/timings.jsonl "
-                "--out gpurun_out/costmodel_experiment.json",
-                "python3 -m paper_2311_01598_amd.tune report --db gpurun_out/timings.jsonl "
-                "--exp gpurun_out/costmodel_experiment.json --out profiles/costmodel_regret_n14-17.md")
+        # the commands that produced the report's inputs, with this call's paths
+        cmds = (f"python3 -u -m paper_2311_01598_amd.tune collect --out {a.db} --reps 3",
+                f"python3 -u -m paper_2311_01598_amd.tune experiment --db {a.db} --out {a.exp}",
+                f"python3 -m paper_2311_01598_amd.tune report --db {a.db} --exp {a.exp} --out {a.out}")
         open(a.out, "w").write(report(load_db(a.db), json.load(open(a.exp)), cmds))
     else:
         from . import costmodel
