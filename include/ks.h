@@ -273,9 +273,11 @@ ks_status_t ks_rotate_sum_workspace_size(ks_plan_t plan, uint32_t level, uint32_
  * with one ModUp of c1 and one ModDown for the whole sum:
  *   ACC = sum_r diag_r * sum_j sigma_r(ModUp_j(c1)) * evk_r[j]  (extended basis)
  *   out = (ModDown(ACC_0) + sum_r diag_r * sigma_r(c0), ModDown(ACC_1)).
- * The building block of a linear transform's inner sum.  It runs the
- * Max-Parallel stages (the sum needs every term's product before its one
- * ModDown) whatever the plan's schedule.  c0, c1 [level+1][N], out
+ * The building block of a linear transform's inner sum.  Under the OC
+ * schedule the summing is fused into the row stages (each tile sums every
+ * term for its rows before its one ModDown); under MP and DC it runs the
+ * Max-Parallel stages with the sum in one extended-basis accumulator.  Both
+ * give the same bits.  c0, c1 [level+1][N], out
  * [2][level+1][N] (device, 16-byte aligned); out must not overlap an input,
  * a key, a diagonal or the workspace (>= ks_rotate_sum_workspace_size,
  * 256-byte aligned). */

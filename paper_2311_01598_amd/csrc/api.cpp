@@ -798,6 +798,16 @@ ks_status_t ks_rotate_sum_hoisted(ks_plan_t plan, uint32_t level, const uint32_t
   uint32_t *XP = (uint32_t *)(ws + lay.xp), *W = (uint32_t *)(ws + lay.w);
   const RotTerm *dterms = (const RotTerm *)ws;
   TRY(upload_async(pl, ws, ht.data(), ht.size() * sizeof(RotTerm), st));
+  if (effective(pl) == KS_SCHED_OC) {
+    // fused: the OC phases with summing row stages, one job whose regions
+    // follow the term table (the OC regions are smaller than the MP ones)
+    const uint32_t tt = oc_tt(pl);
+    OcJob j = make_oc_job(pl, Job{terms[0].evk, 0, level, c1, out}, X, tt);
+    j.add0 = c0;
+    j.terms = dterms;
+    j.nterm = count;
+    return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, OC_ROWS_SUM, OC_PART_ALL, st));
+  }
   TRYK(mp_modup(pl, level, c1, X, Y, st));
   TRY(launch_rotsum_keymul(pl, level, c1, Y, dterms, count, ACC, st));
   TRYK(mp_moddown(pl, level, ACC, XP, W, out, st));

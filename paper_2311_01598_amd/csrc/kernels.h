@@ -97,9 +97,13 @@ constexpr uint32_t OC_ROW_Q_EXT = OC_NPHASE + 4;
 // their b halves and a seed).
 constexpr uint32_t OC_ROW_P_SEEDED_EXT = OC_NPHASE + 5;
 constexpr uint32_t OC_ROW_Q_SEEDED_EXT = OC_NPHASE + 6;
+// Double hoisting: ROW_P / ROW_Q summing the job's rotation terms before one
+// ModDown.
+constexpr uint32_t OC_ROW_P_SUM = OC_NPHASE + 7;
+constexpr uint32_t OC_ROW_Q_SUM = OC_NPHASE + 8;
 
 // Which row-stage kernels a launch uses.
-enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT, OC_ROWS_SEEDED_EXT };
+enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT, OC_ROWS_SEEDED_EXT, OC_ROWS_SUM };
 // Which phases a launch sequence runs: all, ModUp only (INTT_ROW .. UP_PQ),
 // or the rest (ROW_P .. ROW_Q) on the ModUp output of an earlier launch.
 enum OcPart : uint32_t { OC_PART_ALL = 0, OC_PART_MODUP, OC_PART_REST };
@@ -113,14 +117,17 @@ enum OcPart : uint32_t { OC_PART_ALL = 0, OC_PART_MODUP, OC_PART_REST };
 // extended row phases read digit word j of a row at the automorphism's
 // pi(j) (galois = k of X -> X^k, 1 = none) and add add0[t][pi(j)] and
 // add1[t][pi(j)] ([l+1][N] each, either may be null) to the two outputs.
+// The summing row phases take the rotation terms terms[0..nterm) instead of
+// evk and galois, and add0 = c0.
 struct OcJob {
   const uint32_t *d;
   const uint32_t *evk;
   uint32_t *out;
   uint32_t *xt, *ycol, *zp, *wcol;
   const uint32_t *add0, *add1;
+  const RotTerm *terms;
   uint64_t a_seed;
-  uint32_t level, ttu, ttd, galois;
+  uint32_t level, ttu, ttd, galois, nterm, pad;
   uint32_t tiles[OC_NPHASE];  // tile count of every phase for this job
 };
 

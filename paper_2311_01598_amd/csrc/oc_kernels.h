@@ -787,6 +787,199 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   __syncthreads();
 }
 
+// Double hoisting, fused (ROW_P_SUM / ROW_Q_SUM): the tile sums the job's
+// rotation terms before its one ModDown.  ROW_Q first transforms the two
+// ModDown terms (natural rows).  Then, per term: the twiddles of the term's
+// permuted 4-row block are staged, the digit rows are read through the
+// term's automorphism and multiplied by its key (the own digit of a Q tower
+// gathered from the input), the sum is reduced, multiplied by the term's
+// diagonal (exact: REDC then a Shoup product by 2^32) and added to the
+// running total.  The total, carrying 2^-32 like a single key switch's
+// accumulator, then takes the ModDown path of tile_row; ROW_Q adds
+// sum_r diag_r * sigma_r(c0).
+__device__ __forceinline__ uint32_t mulmod_exact32(uint32_t a, uint32_t b, const ModQ &m, uint32_t r32,
+                                                   uint32_t r32p) {
+  return csub(mul_shoup(redc64((uint64_t)a * b, m), r32, r32p, m.q), m.q);
+}
+
+template <bool IS_P>
+__device__ __forceinline__ void tile_row_sum(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
+  const size_t N = (size_t)1 << P.log_n;
+  const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
+  const uint32_t rbk = (1u << P.loga) / kRB4, unit = tile / rbk, blk = tile % rbk;
+  const uint32_t t = IS_P ? L1 + unit : unit;
+  const uint32_t g = oc_gidx(P.num_q, level, t);
+  const ModQ m = ldmodc(P.mods + g);
+  const uint32_t q = m.q;
+  const int r = threadIdx.x >> 6, slot = (threadIdx.x >> 4) & 3, tig = threadIdx.x & 15;
+  const int k0 = 4 * (threadIdx.x & 63);
+  const uint32_t row0 = blk * kRB4, m0 = (1u << P.loga) + row0;
+  const size_t roff = (size_t)(row0 + r) * 256;
+  const uint32_t ndig = cdiv(L1, P.alpha);
+  const uint32_t own = IS_P ? 0xffffffffu : t / P.alpha;
+  const uint32_t nfd = IS_P ? ndig : ndig - 1;  // transformed digits per term (Q: own digit bypassed)
+  auto digit = [&](uint32_t jb) -> uint32_t { return (!IS_P && jb >= own) ? jb + 1 : jb; };
+  uint2 *twl = row_tw(lds);
+  const uint2 *twr = twl + r * kRowTwS;
+  uint2 *twl_s = twl + kRB4 * kRowTwS;
+  const double qr = ldcd(P.qrecip + g);
+  const uint32_t r32 = (0u - q) % q;
+  const uint32_t r32p = shoup_companion(r32, q, qr);
+  const size_t evk_step = (size_t)P.ntot * N;
+  uint32_t x[16];
+  uint32_t tot0[4] = {0, 0, 0, 0}, tot1[4] = {0, 0, 0, 0};
+  // Q: the transformed ModDown terms wait in the natural-twiddle LDS table,
+  // which nothing reads after their round (8 words per thread, conflict-free)
+  uint32_t *wst = reinterpret_cast<uint32_t *>(twl);
+  if (!IS_P) {  // the two ModDown terms: slots 0 and 1, natural rows and twiddles
+    uint32_t tw4[kRB4 * kRowTw / kOcThreads];
+    row_tw_issue(tw4, P.tw_fwd32 + (size_t)g * N, m0);
+    const uint32_t *src = J.wcol + ((size_t)(slot & 1) * L1 + t) * N + roff;
+#pragma unroll
+    for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
+    row_tw_store(twl, tw4, q, qr, true);
+    __syncthreads();
+    row_round_fwd(x, slot < 2, row_buf(lds, slot, r), tig, twr, q);
+    uint32_t w0[4], w1[4];
+    lds4(w0, row_buf(lds, 0, r), k0);
+    lds4(w1, row_buf(lds, 1, r), k0);
+    __syncthreads();  // every thread is done with the natural twiddles and the rows
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      wst[threadIdx.x + kOcThreads * i] = canon4(w0[i], q);
+      wst[threadIdx.x + kOcThreads * (4 + i)] = canon4(w1[i], q);
+    }
+  }
+  uint32_t twi4[kRB4 * kRowTw / kOcThreads];
+  if (IS_P) row_tw_issue(twi4, P.tw_inv32 + (size_t)g * N, m0);
+  for (uint32_t ti = 0; ti < J.nterm; ti++) {
+    const RotTerm rt = J.terms[ti];
+    const size_t roff_s = galois_perm((uint32_t)roff, rt.galois, P.log_n) & ~255u;
+    uint32_t pofs[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) pofs[i] = galois_perm((uint32_t)roff + k0 + i, rt.galois, P.log_n) & 255u;
+    const uint32_t rs0 = (galois_perm(row0 * 256u, rt.galois, P.log_n) >> 8) & ~(uint32_t)(kRB4 - 1);
+    const uint2 *twr_s = twl_s + (uint32_t)((roff_s >> 8) - rs0) * kRowTwS;
+    const uint32_t *evk_t = rt.evk + (size_t)g * N + roff + k0;
+    uint32_t tws4[kRB4 * kRowTw / kOcThreads];
+    row_tw_issue(tws4, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + rs0);
+    auto load_src = [&](uint32_t base) {
+      const uint32_t *src = J.ycol + ((size_t)digit(min(base + slot, nfd - 1)) * T + t) * N + roff_s;
+#pragma unroll
+      for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
+    };
+    uint32_t ek[kSlots][2][4];
+    auto load_keys = [&](uint32_t base) {
+#pragma unroll
+      for (int s2 = 0; s2 < kSlots; s2++) {
+        const uint32_t d2 = digit(min(base + s2, nfd - 1));  // idle slots re-read a row the tile reads
+        ld4_nt(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
+        ld4_nt(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
+      }
+    };
+    if (nfd) {
+      load_src(0);
+      load_keys(0);
+    }
+    row_tw_store(twl_s, tws4, q, qr, true);  // the previous term's rounds ended with a barrier
+    __syncthreads();
+    uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
+    for (uint32_t base = 0; base < nfd; base += kSlots) {
+      if (base) {
+        load_src(base);
+        load_keys(base);
+      }
+      row_round_fwd(x, base + slot < nfd, row_buf(lds, slot, r), tig, twr_s, q);
+#pragma unroll
+      for (int s2 = 0; s2 < kSlots; s2++) {
+        if (base + s2 >= nfd) break;
+        uint32_t y[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) y[i] = canon4(row_buf(lds, s2, r)[rl(pofs[i])], q);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          acc0[i] = mad64(y[i], ek[s2][0][i], acc0[i]);
+          acc1[i] = mad64(y[i], ek[s2][1][i], acc1[i]);
+        }
+      }
+      __syncthreads();  // LDS rows are rewritten by the next round
+    }
+    if (!IS_P) {  // the own digit, loaded after the rounds: fewer registers held across them
+      uint32_t yo[4], eo0[4], eo1[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + roff_s + pofs[i]];
+      ld4_nt(eo0, evk_t + (2 * own + 0) * evk_step);
+      ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        acc0[i] = mad64(yo[i], eo0[i], acc0[i]);
+        acc1[i] = mad64(yo[i], eo1[i], acc1[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      uint32_t v0 = redc64(acc0[i], m), v1 = redc64(acc1[i], m);
+      if (rt.diag) {
+        const uint32_t pv = gp(rt.diag)[(size_t)g * N + roff + k0 + i];
+        v0 = mulmod_exact32(v0, pv, m, r32, r32p);
+        v1 = mulmod_exact32(v1, pv, m, r32, r32p);
+      }
+      tot0[i] = csub(tot0[i] + v0, q);
+      tot1[i] = csub(tot1[i] + v1, q);
+    }
+  }
+  if (IS_P) {
+    // ModDown P1 for this special tower, as in tile_row
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      row_buf(lds, 0, r)[rl(k0 + i)] = tot0[i];
+      row_buf(lds, 1, r)[rl(k0 + i)] = tot1[i];
+    }
+    row_tw_store(twl, twi4, q, qr, false);
+    __syncthreads();
+    uint32_t *lrow = row_buf(lds, slot & 1, r);
+    const bool act = slot < 2;
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 16; u++) x[u] = lrow[rl(16 * tig + u)];
+      gs_lds<5>(x, twr, tig, q);
+#pragma unroll
+      for (int u = 0; u < 16; u++) lrow[rl(16 * tig + u)] = x[u];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 16; u++) x[u] = lrow[rl(tig + 16 * u)];
+      gs_lds<1>(x, twr, tig, q);
+      uint32_t *dst = J.zp + ((size_t)slot * P.num_p + unit) * N + roff;
+#pragma unroll
+      for (int u = 0; u < 16; u++) gp(dst)[tig + 16 * u] = x[u];
+    }
+  } else {
+    const uint2 f = ldc2(P.dn_fin + t);
+    uint32_t o0[4], o1[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      o0[i] = csub(mul_shoup(tot0[i] + q - wst[threadIdx.x + kOcThreads * i], f.x, f.y, q), q);
+      o1[i] = csub(mul_shoup(tot1[i] + q - wst[threadIdx.x + kOcThreads * (4 + i)], f.x, f.y, q), q);
+    }
+    for (uint32_t ti = 0; ti < J.nterm; ti++) {  // + sum_r diag_r sigma_r(c0)
+      const RotTerm rt = J.terms[ti];
+      const size_t roff_s = galois_perm((uint32_t)roff, rt.galois, P.log_n) & ~255u;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const uint32_t pi = galois_perm((uint32_t)roff + k0 + i, rt.galois, P.log_n) & 255u;
+        uint32_t cv = gp(J.add0)[(size_t)t * N + roff_s + pi];
+        if (rt.diag) cv = mulmod_exact32(cv, gp(rt.diag)[(size_t)g * N + roff + k0 + i], m, r32, r32p);
+        o0[i] = csub(o0[i] + cv, q);
+      }
+    }
+    stg4_nt(J.out + ((size_t)0 * L1 + t) * N + roff + k0, make_uint4(o0[0], o0[1], o0[2], o0[3]));
+    stg4_nt(J.out + ((size_t)1 * L1 + t) * N + roff + k0, make_uint4(o1[0], o1[1], o1[2], o1[3]));
+  }
+  __syncthreads();
+}
+
 // One tile of one phase.
 template <int A, int TTU, int TTD>
 __device__ __forceinline__ void oc_tile(const DevPlan &P, const OcJob &J, uint32_t phase, uint32_t tile,
@@ -809,7 +1002,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int A, int PHASE, int TT>
 constexpr int oc_phase_lds_words() {
   return (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
-          PHASE == OC_ROW_Q_SEEDED_EXT)
+          PHASE == OC_ROW_Q_SEEDED_EXT || PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM)
              ? kRowTileLdsExt
          : (PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED)
              ? kRowTileLds
@@ -841,8 +1034,14 @@ __device__ __forceinline__ uint32_t xcd_col_tile(uint32_t b) {
 }
 
 // One launch per phase: grid x = tiles (max over jobs), grid z = job.
+// The summing row phases are asked for 3 workgroups per CU (3 waves per
+// SIMD): their per-term loop otherwise holds 174-184 VGPRs.
+template <int PHASE>
+constexpr int oc_min_blocks() { return (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) ? 3 : 1; }
+
 template <int A, int PHASE, int TT>
-__global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, const OcJob *jobs) {
+__global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE>()) void k_oc_phase(DevPlan P, OcJob one,
+                                                                                  const OcJob *jobs) {
   __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>()];
   // the job table is read-only while the kernel runs: scalar loads keep
   // every job field (pointers, level, tile counts) uniform in SGPRs
@@ -866,6 +1065,10 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
     constexpr bool SEEDED = PHASE == OC_ROW_P_SEEDED_EXT || PHASE == OC_ROW_Q_SEEDED_EXT;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
     tile_row<IS_P, SEEDED, true>(P, J, blockIdx.x, lds);
+  } else if constexpr (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) {
+    constexpr bool IS_P = PHASE == OC_ROW_P_SUM;
+    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row_sum<IS_P>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -879,10 +1082,11 @@ __global__ __launch_bounds__(kOcThreads) void k_oc_phase(DevPlan P, OcJob one, c
   }
 }
 
-static const char *const kOcPhaseName[OC_NPHASE + 7] = {
+static const char *const kOcPhaseName[OC_NPHASE + 9] = {
     "oc.intt_row",      "oc.intt_col.up",    "oc.bconv_col.up_p", "oc.row.p",        "oc.bconv_col.up_q",
     "oc.intt_col.down", "oc.bconv_col.down", "oc.row.q",          "oc.bconv_col.up", "oc.row.p.seeded",
-    "oc.row.q.seeded",  "oc.row.p.ext",      "oc.row.q.ext",      "oc.row.p.seeded_ext", "oc.row.q.seeded_ext"};
+    "oc.row.q.seeded",  "oc.row.p.ext",      "oc.row.q.ext",      "oc.row.p.seeded_ext", "oc.row.q.seeded_ext",
+    "oc.row.p.sum",     "oc.row.q.sum"};
 
 template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
@@ -908,6 +1112,7 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
     case OC_ROWS_SEEDED_EXT:
       launch_phase<A, OC_ROW_P_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
       break;
+    case OC_ROWS_SUM: launch_phase<A, OC_ROW_P_SUM, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
     default: launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
   }
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
@@ -918,6 +1123,7 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
     case OC_ROWS_SEEDED_EXT:
       launch_phase<A, OC_ROW_Q_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
       break;
+    case OC_ROWS_SUM: launch_phase<A, OC_ROW_Q_SUM, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
     default: launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
   }
 }
