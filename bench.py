@@ -242,6 +242,23 @@ def rotation_rate(ks, plan, evks, steps, np, torch, synth):
     torch.cuda.synchronize()
     res["hoisted_compressed_keys"] = {"m8": round(8 * reps / (a.elapsed_time(b) / 1e3), 1)}
     del keys_b
+    # 16 different ciphertexts, each with its own rotation, in one batch call
+    cts = [(torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 600 + 2 * i)).view(np.int32)).cuda(),
+            torch.from_numpy(synth.uniform_limbs(mods[:l1], n, synth.seed_for(2, 601 + 2 * i)).view(np.int32)).cuda())
+           for i in range(16)]
+    rjobs = [(evks[i % len(evks)], ks.galois_rotation(LOG_N, i + 1), LEVEL, a0_, a1_) for i, (a0_, a1_) in enumerate(cts)]
+    wsb = plan.workspace([LEVEL] * 16)
+    plan.configure("oc", tile_towers=2, batch_mode=1)
+    plan.rotate_batch(rjobs, workspace=wsb)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        plan.rotate_batch(rjobs, workspace=wsb)
+    b.record()
+    torch.cuda.synchronize()
+    res["batch16_one_rotation_each"] = round(16 * reps / (a.elapsed_time(b) / 1e3), 1)
+    plan.configure("oc", tile_towers=1, batch_mode=1)
+    del cts, wsb
     # double hoisting: the sum of the same 8 rotations, each times a plaintext
     # diagonal, with one ModUp and one ModDown (Max-Parallel stages)
     diags = [torch.from_numpy(synth.uniform_limbs(mods, n, synth.seed_for(2, 500 + i)).view(np.int32)).cuda()

@@ -217,6 +217,26 @@ typedef struct {
   uint32_t *out;
 } ks_rotation_t;
 
+/* One job of a rotation batch: the ciphertext (c0, c1) [level+1][N] each,
+ * its rotation key evk [dnum][2][L+1+K][N] (from s(X^galois) to s) and the
+ * output [2][level+1][N] (device pointers). */
+typedef struct {
+  const uint32_t *evk;
+  uint32_t galois;
+  uint32_t level;
+  const uint32_t *c0;
+  const uint32_t *c1;
+  uint32_t *out;
+} ks_rotate_job_t;
+
+/* Many ciphertexts, each rotated by its own element at its own level, in one
+ * launch per phase: the batch of ks_keyswitch_batch with every job a
+ * hoisted group of one (its result equals ks_rotate_hoisted of that job
+ * alone).  Workspace: ks_workspace_size with the jobs' levels.  Same rules
+ * as ks_keyswitch_batch; c0 counts as an input.  OC schedule only. */
+ks_status_t ks_rotate_batch(ks_plan_t plan, uint32_t count, const ks_rotate_job_t *jobs, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
 /* Bytes of workspace ks_rotate_hoisted needs for `count` rotations at
  * `level` (0 for count 0). */
 ks_status_t ks_rotate_workspace_size(ks_plan_t plan, uint32_t level, uint32_t count, size_t *bytes);

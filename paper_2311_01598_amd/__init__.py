@@ -60,6 +60,11 @@ class ks_rotation_term_t(ctypes.Structure):
     _fields_ = [("evk", ctypes.c_void_p), ("galois", ctypes.c_uint32), ("diag", ctypes.c_void_p)]
 
 
+class ks_rotate_job_t(ctypes.Structure):
+    _fields_ = [("evk", ctypes.c_void_p), ("galois", ctypes.c_uint32), ("level", ctypes.c_uint32),
+                ("c0", ctypes.c_void_p), ("c1", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 _U32P = ctypes.POINTER(ctypes.c_uint32)
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -80,6 +85,8 @@ _SIGS = {
                                                  ctypes.c_size_t, _VP]),
     "ks_expand_seeded_a": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
     "ks_automorphism": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP]),
+    "ks_rotate_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_rotate_job_t), _VP, ctypes.c_size_t,
+                                       _VP]),
     "ks_rotate_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "ks_rotate_hoisted": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, ctypes.c_uint32,
@@ -281,6 +288,17 @@ def ks_expand_seeded_a(plan, a_seed, evk, stream=None):
 def ks_automorphism(plan, galois, count, inp, out, stream=None):
     _check(_lib.ks_automorphism(plan, int(galois), int(count), _ptr(inp), _ptr(out), _stream(stream)),
            "ks_automorphism")
+
+
+def ks_rotate_batch(plan, jobs, workspace, workspace_bytes=None, stream=None):
+    """jobs: list of (evk, galois, level, c0, c1, out)."""
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    arr = (ks_rotate_job_t * max(len(jobs), 1))()
+    for i, (evk, galois, level, c0, c1, out) in enumerate(jobs):
+        arr[i] = ks_rotate_job_t(_ptr(evk), int(galois), int(level), _ptr(c0), _ptr(c1), _ptr(out))
+    _check(_lib.ks_rotate_batch(plan, len(jobs), arr, _ptr(workspace), int(workspace_bytes), _stream(stream)),
+           "ks_rotate_batch")
 
 
 def ks_rotate_workspace_size(plan, level, count):
@@ -503,6 +521,16 @@ class Plan:
             workspace = self._ws(ks_rotate_sum_workspace_size(self.handle, level, len(terms)), c1.device)
         ks_rotate_sum_hoisted(self.handle, level, c0, c1, terms, out, workspace, stream=stream)
         return out
+
+    def rotate_batch(self, jobs, workspace=None, stream=None):
+        """jobs: list of (evk, galois, level, c0, c1); returns one rotated
+        ciphertext per job, all in one launch per phase."""
+        import torch
+        outs = [torch.empty((2, j[2] + 1, self.n), dtype=torch.int32, device=j[4].device) for j in jobs]
+        if workspace is None:
+            workspace = self.workspace([j[2] for j in jobs])
+        ks_rotate_batch(self.handle, [tuple(j) + (o,) for j, o in zip(jobs, outs)], workspace, stream=stream)
+        return outs
 
     def rotate(self, evk, galois, level, c0, c1, workspace=None, stream=None):
         return self.rotate_hoisted(level, c0, c1, [(evk, galois)], workspace, stream)[0]

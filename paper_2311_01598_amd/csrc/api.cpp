@@ -219,7 +219,12 @@ struct Job {
   uint32_t level;
   const uint32_t *in;
   uint32_t *out;
+  uint32_t galois = 1;             // a rotation: the automorphism of its digits
+  const uint32_t *add0 = nullptr;  // a rotation: c0, added (permuted) to output 0
 };
+
+// Row-stage kernels of a call, and the halves its keys hold.
+bool rows_seeded(OcRowVariant rows) { return rows == OC_ROWS_SEEDED || rows == OC_ROWS_SEEDED_EXT; }
 
 // ---------------------------------------------------------------- OC
 OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
@@ -236,7 +241,8 @@ OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
   j.zp = j.ycol + (size_t)D * T * N;
   j.wcol = j.zp + (size_t)2 * K * N;
   j.a_seed = jb.a_seed;
-  j.galois = 1;
+  j.galois = jb.galois;
+  j.add0 = jb.add0;
   j.ttu = j.ttd = tt;
   oc_tiles_host(pl, level, tt, j.tiles);
   return j;
@@ -244,20 +250,21 @@ OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
 
 uint32_t oc_tt(const Plan &pl) { return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1); }
 
-ks_status_t run_oc(const Plan &pl, const Job &jb, bool seeded, uint32_t *ws, hipStream_t st) {
+ks_status_t run_oc(const Plan &pl, const Job &jb, OcRowVariant rows, uint32_t *ws, hipStream_t st) {
   const uint32_t tt = oc_tt(pl);
   const OcJob j = make_oc_job(pl, jb, ws, tt);
-  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, seeded ? OC_ROWS_SEEDED : OC_ROWS_PLAIN,
-                                  OC_PART_ALL, st));
+  return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, rows, OC_PART_ALL, st));
 }
 
-// Compressed keys are supported by the OC schedule only (callers check).
-ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const Job &jb, bool seeded, uint32_t *ws, hipStream_t st) {
+// Compressed keys and rotations are supported by the OC schedule only
+// (callers check).
+ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const Job &jb, OcRowVariant rows, uint32_t *ws,
+                    hipStream_t st) {
   ks_status_t r;
   switch (sch) {
     case KS_SCHED_MP: r = run_mp(pl, jb.evk, jb.level, jb.in, jb.out, ws, st); break;
     case KS_SCHED_DC: r = run_dc(pl, jb.evk, jb.level, jb.in, jb.out, ws, st); break;
-    default: r = run_oc(pl, jb, seeded, ws, st); break;
+    default: r = run_oc(pl, jb, rows, ws, st); break;
   }
   return r;
 }
@@ -266,7 +273,7 @@ ks_status_t run_one(const Plan &pl, ks_schedule_t sch, const Job &jb, bool seede
 // workspace, configuration); the job table is re-uploaded before each replay.
 struct GraphEntry {
   uint32_t count, mode, tt, spin, total;
-  bool seeded;
+  OcRowVariant rows;
   std::vector<uint32_t> max_tiles;
   const void *ws;
   hipGraphExec_t exec;
@@ -277,15 +284,14 @@ struct GraphCache {
 };
 
 ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<uint32_t> &max_tiles, uint32_t total,
-                            char *ws, const BatchLayout &lay, uint32_t mode, uint32_t tt, uint32_t spin, bool seeded,
-                            hipStream_t st) {
+                            char *ws, const BatchLayout &lay, uint32_t mode, uint32_t tt, uint32_t spin,
+                            OcRowVariant rows, hipStream_t st) {
   const OcJob *djobs = (const OcJob *)(ws + lay.jobs);
-  if (mode == 2 && seeded) return KS_ERR_UNSUPPORTED;
+  if (mode == 2 && rows != OC_ROWS_PLAIN) return KS_ERR_UNSUPPORTED;
   if (mode == 2)
     return dev_err(launch_oc_persistent(pl, djobs, (const OcSeg *)(ws + lay.segs), count * OC_NPHASE, total, count,
                                         (uint32_t *)(ws + lay.ctl), spin, st));
   const OcJob none{};
-  const OcRowVariant rows = seeded ? OC_ROWS_SEEDED : OC_ROWS_PLAIN;
   if (mode != 3 || count < 2)
     return dev_err(launch_oc_phases(pl, none, djobs, count, max_tiles.data(), tt, rows, OC_PART_ALL, st));
   // Mode 3: the batch runs as two halves, the second on the plan's side stream:
@@ -305,8 +311,8 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
   return KS_OK;
 }
 
-ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, bool seeded, const BatchLayout &lay, char *ws,
-                         hipStream_t st) {
+ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, OcRowVariant rows, const BatchLayout &lay,
+                         char *ws, hipStream_t st) {
   const uint32_t mode = pl.cfg.batch_mode;
   const uint32_t tt = mode == 2 ? 1 : oc_tt(pl);
   const uint32_t spin = pl.cfg.spin_limit ? pl.cfg.spin_limit : (1u << 20);
@@ -333,7 +339,7 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, bool seeded,
   TRY(upload_async(pl, ws, blob.data(), blob.size(), st));
 
   const bool use_graph = pl.cfg.graph != 2 && !pl.trace.on;
-  if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, seeded, st);
+  if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, rows, st);
 
   // graph keyed by (count, workspace, mode, tile, spin); the persistent launch
   // reads `total` from its arguments, so it is part of the key as well
@@ -346,13 +352,13 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, bool seeded,
   hipGraphExec_t exec = nullptr;
   for (auto &e : gc->entries)
     if (e.count == count && e.ws == ws && e.mode == mode && e.tt == tt && e.spin == spin && e.total == total &&
-        e.seeded == seeded && e.max_tiles == max_tiles)
+        e.rows == rows && e.max_tiles == max_tiles)
       exec = e.exec;
   if (!exec) {
     if (!gc->capture && hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking) != hipSuccess)
       return KS_ERR_DEVICE;
     TRY(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeThreadLocal));
-    ks_status_t r = launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, seeded, gc->capture);
+    ks_status_t r = launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, rows, gc->capture);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(gc->capture, &graph);
     if (r != KS_OK || e != hipSuccess) {
@@ -366,7 +372,7 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, bool seeded,
       (void)hipGraphExecDestroy(gc->entries.front().exec);
       gc->entries.erase(gc->entries.begin());
     }
-    gc->entries.push_back(GraphEntry{count, mode, tt, spin, total, seeded, max_tiles, ws, exec});
+    gc->entries.push_back(GraphEntry{count, mode, tt, spin, total, rows, max_tiles, ws, exec});
   }
   TRY(hipGraphLaunch(exec, st));
   return KS_OK;
@@ -554,27 +560,28 @@ static bool injected_fault() {
 
 namespace {
 
-ks_status_t keyswitch_one(ks_plan_t plan, const Job &jb, bool seeded, void *workspace, size_t workspace_bytes,
+ks_status_t keyswitch_one(ks_plan_t plan, const Job &jb, OcRowVariant rows, void *workspace, size_t workspace_bytes,
                           void *stream) {
   if (!plan) return KS_ERR_INVALID_ARG;
   const Plan &pl = plan->p;
   const ks_schedule_t sch = effective(pl);
-  if (seeded && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
+  if (rows != OC_ROWS_PLAIN && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (jb.level >= pl.num_q) return KS_ERR_INVALID_ARG;
   const size_t need = ws_limbs(pl, sch, jb.level) * limb_bytes(pl);
-  ks_status_t st = check_job(pl, jb.evk, jb.level, jb.in, jb.out, workspace, workspace_bytes, need, seeded ? 1 : 2);
+  ks_status_t st = check_job(pl, jb.evk, jb.level, jb.in, jb.out, workspace, workspace_bytes, need,
+                             rows_seeded(rows) ? 1 : 2);
   if (st != KS_OK) return st;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
-  return run_one(pl, sch, jb, seeded, (uint32_t *)workspace, (hipStream_t)stream);
+  return run_one(pl, sch, jb, rows, (uint32_t *)workspace, (hipStream_t)stream);
 }
 
-ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, bool seeded, void *workspace,
+ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, OcRowVariant rows, void *workspace,
                             size_t workspace_bytes, void *stream) {
   const uint32_t count = (uint32_t)jobs.size();
   Plan &pl = plan->p;
   const ks_schedule_t sch = effective(pl);
-  if (seeded && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
+  if (rows != OC_ROWS_PLAIN && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (!count) return KS_OK;
   std::vector<uint32_t> levels(count);
   for (uint32_t i = 0; i < count; i++) {
@@ -591,8 +598,17 @@ ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, bool s
   }
   for (uint32_t i = 0; i < count; i++) {
     ks_status_t st = check_job(pl, jobs[i].evk, jobs[i].level, jobs[i].in, jobs[i].out, workspace,
-                               workspace_bytes, need, seeded ? 1 : 2);
+                               workspace_bytes, need, rows_seeded(rows) ? 1 : 2);
     if (st != KS_OK) return st;
+    if (jobs[i].add0) {  // a rotation: its element, and c0 kept apart from every output and the workspace
+      if (!galois_ok(pl, jobs[i].galois) || ((uintptr_t)jobs[i].add0 & 15) ||
+          overlaps(workspace, workspace_bytes, jobs[i].add0, (size_t)(jobs[i].level + 1) * limb_bytes(pl)))
+        return KS_ERR_INVALID_ARG;
+      for (uint32_t k = 0; k < count; k++)
+        if (overlaps(jobs[k].out, 2 * (size_t)(jobs[k].level + 1) * limb_bytes(pl), jobs[i].add0,
+                     (size_t)(jobs[i].level + 1) * limb_bytes(pl)))
+          return KS_ERR_INVALID_ARG;
+    }
     // no job's output may overlap another job's output or input (either order)
     const size_t ob = 2 * (size_t)(jobs[i].level + 1) * limb_bytes(pl);
     const size_t ib = (size_t)(jobs[i].level + 1) * limb_bytes(pl);
@@ -609,12 +625,12 @@ ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, bool s
   hipStream_t st = (hipStream_t)stream;
   if (!together) {
     for (uint32_t i = 0; i < count; i++) {
-      ks_status_t r = run_one(pl, sch, jobs[i], seeded, (uint32_t *)workspace, st);
+      ks_status_t r = run_one(pl, sch, jobs[i], rows, (uint32_t *)workspace, st);
       if (r != KS_OK) return r;
     }
     return KS_OK;
   }
-  return run_oc_batch(pl, count, jobs.data(), seeded, lay, (char *)workspace, st);
+  return run_oc_batch(pl, count, jobs.data(), rows, lay, (char *)workspace, st);
 }
 
 }  // namespace
@@ -623,13 +639,13 @@ extern "C" {
 
 ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in, uint32_t *out,
                          void *workspace, size_t workspace_bytes, void *stream) {
-  return keyswitch_one(plan, Job{evk, 0, level, in, out}, false, workspace, workspace_bytes, stream);
+  return keyswitch_one(plan, Job{evk, 0, level, in, out}, OC_ROWS_PLAIN, workspace, workspace_bytes, stream);
 }
 
 ks_status_t ks_keyswitch_seeded(ks_plan_t plan, const uint32_t *evk_b, uint64_t a_seed, uint32_t level,
                                 const uint32_t *in, uint32_t *out, void *workspace, size_t workspace_bytes,
                                 void *stream) {
-  return keyswitch_one(plan, Job{evk_b, a_seed, level, in, out}, true, workspace, workspace_bytes, stream);
+  return keyswitch_one(plan, Job{evk_b, a_seed, level, in, out}, OC_ROWS_SEEDED, workspace, workspace_bytes, stream);
 }
 
 ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *jobs, void *workspace,
@@ -638,7 +654,7 @@ ks_status_t ks_keyswitch_batch(ks_plan_t plan, uint32_t count, const ks_job_t *j
   if (injected_fault()) return KS_ERR_DEVICE;
   std::vector<Job> jb(count);
   for (uint32_t i = 0; i < count; i++) jb[i] = Job{jobs[i].evk, 0, jobs[i].level, jobs[i].in, jobs[i].out};
-  return keyswitch_batch(plan, jb, false, workspace, workspace_bytes, stream);
+  return keyswitch_batch(plan, jb, OC_ROWS_PLAIN, workspace, workspace_bytes, stream);
 }
 
 ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_seeded_job_t *jobs, void *workspace,
@@ -647,7 +663,19 @@ ks_status_t ks_keyswitch_batch_seeded(ks_plan_t plan, uint32_t count, const ks_s
   if (injected_fault()) return KS_ERR_DEVICE;
   std::vector<Job> jb(count);
   for (uint32_t i = 0; i < count; i++) jb[i] = Job{jobs[i].evk_b, jobs[i].a_seed, jobs[i].level, jobs[i].in, jobs[i].out};
-  return keyswitch_batch(plan, jb, true, workspace, workspace_bytes, stream);
+  return keyswitch_batch(plan, jb, OC_ROWS_SEEDED, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_rotate_batch(ks_plan_t plan, uint32_t count, const ks_rotate_job_t *jobs, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+  if (!plan || (count && !jobs)) return KS_ERR_INVALID_ARG;
+  if (injected_fault()) return KS_ERR_DEVICE;
+  std::vector<Job> jb(count);
+  for (uint32_t i = 0; i < count; i++) {
+    if (!jobs[i].c0) return KS_ERR_INVALID_ARG;
+    jb[i] = Job{jobs[i].evk, 0, jobs[i].level, jobs[i].c1, jobs[i].out, jobs[i].galois, jobs[i].c0};
+  }
+  return keyswitch_batch(plan, jb, OC_ROWS_EXT, workspace, workspace_bytes, stream);
 }
 
 ks_status_t ks_automorphism(ks_plan_t plan, uint32_t galois, uint32_t count, const uint32_t *in, uint32_t *out,

@@ -88,6 +88,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "ks_rotation_t": ["evk", "galois", "out"],
         "ks_seeded_rotation_t": ["evk_b", "a_seed", "galois", "out"],
         "ks_rotation_term_t": ["evk", "galois", "diag"],
+        "ks_rotate_job_t": ["evk", "galois", "level", "c0", "c1", "out"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ks.h"', "int main(void) {"]
     for t, fields in checks.items():

@@ -197,6 +197,33 @@ def test_double_hoisted_sum_decrypts(ks):
     plan.close()
 
 
+@pytest.mark.parametrize("tt,mode", [(1, 1), (2, 3)])
+def test_rotation_batch_mixed_levels(ks, tt, mode):
+    """Nine ciphertexts at mixed levels, each rotated by its own element with
+    its own key, in one batch: each equals the oracle's rotation of that
+    ciphertext alone (a hoisted group of one)."""
+    p = oracle.Params(13, 8, 3, 0)
+    mods = oracle.moduli(p)
+    plan = ks.Plan(13, 8, 3)
+    plan.configure("oc", tile_towers=tt, batch_mode=mode)
+    keys = [synth.uniform_evk(mods, 3, p.n, synth.seed_for(29, k)) for k in range(3)]
+    keys_d = [dev(k) for k in keys]
+    levels = synth.batch_levels(9, 1, 8, synth.seed_for(29, 50))
+    jobs, wants = [], []
+    for i, level in enumerate(levels):
+        c0 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(29, 100 + i))
+        c1 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(29, 200 + i))
+        k = core.galois_rotation(13, i + 1) if i % 4 else (2 << 13) - 1
+        wants.append(core.rotate_hoisted(p, mods, level, c0, c1, [k], [keys[i % 3]])[0])
+        jobs.append((keys_d[i % 3], k, level, dev(c0), dev(c1)))
+    print(f"[rot batch] tt={tt} mode={mode} levels={levels}", flush=True)
+    outs = plan.rotate_batch(jobs)
+    torch.cuda.synchronize()
+    for i, (o, w) in enumerate(zip(outs, wants)):
+        assert np.array_equal(host(o), w), (i, levels[i])
+    plan.close()
+
+
 SHAPES = [
     (12, 5, 2, 0, [4, 0]),     # partial last digit; level 0
     (12, 4, 1, 0, [3]),        # dnum = 1
