@@ -391,13 +391,15 @@ def mixed_rate(ks, dnum, reps, np, torch, synth):
 
 
 def serving_rate(ks, count, np, torch, synth, seed=5):
-    """Serving workload: Poisson arrivals of key-switch requests, each for the
-    relinearisation key or one of 16 rotation keys (17 keys resident per ring
-    degree), N in {2^16, 2^17}, l+1 ~ U[8, 48], dnum=3.  Reports saturation
-    throughput (all requests queued at once), p50/p99 latency at 60 % of that
-    rate, and the same requests switched one at a time with MP."""
+    """Serving workload: Poisson arrivals of requests for the relinearisation
+    key (a key switch of d2) or one of 16 rotation keys (a rotation of a
+    ciphertext (c0, c1) by 5^k), 17 keys resident per ring degree, N in
+    {2^16, 2^17}, l+1 ~ U[8, 48], dnum=3.  Reports saturation throughput (all
+    requests queued at once), p50/p99 latency at 60 % of that rate, the same
+    requests one at a time with MP (a rotation as automorphisms then the MP
+    key switch), and key switches with compressed keys."""
     from paper_2311_01598_amd.serve import Request, Server, poisson_arrivals
-    plans, keys, pool = {}, {}, {}
+    plans, keys, pool, pool0 = {}, {}, {}, {}
     for log_n in (16, 17):
         p = ks.Plan(log_n, 48, 3)
         plans[log_n] = p
@@ -405,53 +407,69 @@ def serving_rate(ks, count, np, torch, synth, seed=5):
         keys[log_n] = [base] + [base.clone() for _ in range(16)]
         pool[log_n] = [torch.from_numpy(synth.uniform_limbs(p.moduli[:48], p.n, synth.seed_for(4, 100 * log_n + i))
                                         .view(np.int32)).cuda() for i in range(4)]
+        pool0[log_n] = [torch.from_numpy(synth.uniform_limbs(p.moduli[:48], p.n, synth.seed_for(4, 100 * log_n + 50 + i))
+                                         .view(np.int32)).cuda() for i in range(4)]
     rng = np.random.default_rng(synth.seed_for(4, seed))
 
-    def requests():
+    def requests(rotations=True):
         out = []
         for i in range(count):
             log_n = int(rng.choice((16, 17)))
             level = int(rng.integers(7, 48))
+            key = int(rng.integers(0, 17))
             d = pool[log_n][i % 4][:level + 1]
-            out.append(Request(i, int(rng.integers(0, 17)), log_n, level, d, 0.0))
+            if rotations and key:
+                out.append(Request(i, key, log_n, level, d, 0.0, c0=pool0[log_n][i % 4][:level + 1],
+                                   galois=ks.galois_rotation(log_n, key)))
+            else:
+                out.append(Request(i, key, log_n, level, d, 0.0))
         return out
     budget = 8 << 30
-    res = {"requests": count, "keys_per_degree": 17, "budget_gib": budget >> 30, "streams": 2, "max_batch": 16}
+    res = {"requests": count, "keys_per_degree": 17, "budget_gib": budget >> 30, "streams": 2, "max_batch": 16,
+           "mix": "key 0 (relinearisation): key switch; keys 1-16: rotation of (c0, c1) by 5^k"}
     sat = Server(plans, keys, budget, streams=2, max_batch=16)
     reqs = requests()
     sat.run([(0.0, r) for r in reqs[:64]])  # warm-up
     sat = Server(plans, keys, budget, streams=2, max_batch=16)
     st = sat.run([(0.0, r) for r in reqs])
-    res["saturation"] = {"ks_per_s": round(st["ks_per_s"], 1), "batches": st["batches"]}
+    res["saturation"] = {"requests_per_s": round(st["ks_per_s"], 1), "batches": st["batches"]}
     rate = 0.6 * st["ks_per_s"]
     srv = Server(plans, keys, budget, streams=2, max_batch=16)
     reqs = requests()
     st = srv.run(list(zip(poisson_arrivals(rate, count, synth.seed_for(4, seed + 1)), reqs)))
-    res["poisson"] = {"offered_per_s": round(rate, 1), "ks_per_s": round(st["ks_per_s"], 1),
+    res["poisson"] = {"offered_per_s": round(rate, 1), "requests_per_s": round(st["ks_per_s"], 1),
                       "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "batches": st["batches"],
                       "high_water_gib": round(st["high_water_bytes"] / 2**30, 3)}
-    # the same requests with every key compressed (b halves plus a seed):
+    # key-switch requests only, every key compressed (b halves plus a seed):
     # half the resident key bytes
     ckeys = {k: [(e.view(3, 2, -1)[:, 0].contiguous(), 900 + i) for i, e in enumerate(v)] for k, v in keys.items()}
     srv = Server(plans, ckeys, budget, streams=2, max_batch=16)
-    st = srv.run([(0.0, r) for r in requests()])
-    res["saturation_compressed_keys"] = {"ks_per_s": round(st["ks_per_s"], 1), "batches": st["batches"]}
+    st = srv.run([(0.0, r) for r in requests(rotations=False)])
+    res["saturation_key_switches_compressed_keys"] = {"requests_per_s": round(st["ks_per_s"], 1),
+                                                      "batches": st["batches"]}
     res["resident_key_gib"] = {"full": round(sum(e.numel() * 4 for v in keys.values() for e in v) / 2**30, 2),
                                "compressed": round(sum(b.numel() * 4 for v in ckeys.values() for b, _ in v) / 2**30,
                                                    2)}
     del ckeys
-    # the same request mix, one key switch per call with MP on one stream
+    # the same request mix, one request per call with MP on one stream
     for p in plans.values():
         p.configure("mp")
     ws = {k: p.workspace([47]) for k, p in plans.items()}
     outs = {k: torch.empty(2 * 48 * p.n, dtype=torch.int32, device="cuda") for k, p in plans.items()}
+    tmp = {k: torch.empty(2 * 48 * p.n, dtype=torch.int32, device="cuda") for k, p in plans.items()}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in reqs:
-        plans[r.log_n].keyswitch(keys[r.log_n][r.key], r.level, r.d, out=outs[r.log_n][:2 * (r.level + 1) * plans[r.log_n].n],
-                                 workspace=ws[r.log_n])
+        p = plans[r.log_n]
+        limbs = (r.level + 1) * p.n
+        d = r.d
+        if r.galois is not None:  # rotation: permute c1 and c0, then the key switch
+            d = tmp[r.log_n][:limbs]
+            ks.ks_automorphism(p.handle, r.galois, r.level + 1, r.d, d)
+            ks.ks_automorphism(p.handle, r.galois, r.level + 1, r.c0, tmp[r.log_n][limbs:2 * limbs])
+        p.keyswitch(keys[r.log_n][r.key], r.level, d, out=outs[r.log_n][:2 * limbs], workspace=ws[r.log_n])
     torch.cuda.synchronize()
-    res["mp_one_at_a_time_ks_per_s"] = round(count / (time.perf_counter() - t0), 1)
+    res["mp_one_at_a_time_requests_per_s"] = round(count / (time.perf_counter() - t0), 1)
     for p in plans.values():
         p.close()
     return res

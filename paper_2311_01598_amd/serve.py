@@ -2,17 +2,20 @@
 
 * Keys (relinearisation + rotation keys) stay resident in HBM per ring
   degree, either full ([dnum][2][L+1+K][N]) or compressed (the b halves plus
-  the seed of the a halves, Sec. IV-D: half the resident bytes); a request
-  names a key, a ring degree and a level, and carries its input polynomial
-  (already rotated, for a rotation key).
+  the seed of the a halves, Sec. IV-D: half the resident bytes).  A request
+  names a key, a ring degree and a level and is either a key switch of its
+  input polynomial, or a rotation of a ciphertext (c0, c1) by a Galois
+  element with a full rotation key (the automorphism applied inside the
+  key switch).
 * Admission by memory: every batch needs workspace (from a preallocated HBM
   pool, first-fit) plus output buffers; requests wait while the bytes in
   flight plus theirs would exceed the budget, and a request that could never
   fit is rejected.
 * Continuous batching: whenever one of `streams` slots is free, the queued
-  requests of one ring degree and key kind (oldest first) form a batch that
-  is launched with ks_keyswitch_batch (or ks_keyswitch_batch_seeded) on that
-  slot's stream; completions are polled with
+  requests of one ring degree and kind (key switch with a full or a
+  compressed key, or rotation; oldest first) form a batch that is launched
+  with ks_keyswitch_batch, ks_keyswitch_batch_seeded or ks_rotate_batch on
+  that slot's stream; completions are polled with
   events, so requests arriving while others run are admitted as slots and
   memory free up, and batches on different streams overlap on the device.
 * Metrics: per-request latency (arrival to observed completion), p50/p99,
@@ -62,12 +65,16 @@ class HbmPool:
 
 
 class Request:
-    __slots__ = ("rid", "key", "log_n", "level", "d", "t_arrive", "t_start", "t_done", "out", "status", "ready")
+    """A key switch of `d` with key `key`, or (galois and c0 given) the
+    rotation of the ciphertext (c0, d) by that Galois element."""
+    __slots__ = ("rid", "key", "log_n", "level", "d", "t_arrive", "t_start", "t_done", "out", "status", "ready",
+                 "c0", "galois")
 
-    def __init__(self, rid, key, log_n, level, d, t_arrive):
+    def __init__(self, rid, key, log_n, level, d, t_arrive, c0=None, galois=None):
         self.rid, self.key, self.log_n, self.level, self.d = rid, key, log_n, level, d
         self.t_arrive, self.t_start, self.t_done = t_arrive, None, None
         self.out, self.status, self.ready = None, "queued", None
+        self.c0, self.galois = c0, galois
 
 
 class Server:
@@ -94,6 +101,9 @@ class Server:
     def _compressed(self, r):
         return isinstance(self.keys[r.log_n][r.key], tuple)
 
+    def _kind(self, r):
+        return "rotation" if r.galois is not None else ("compressed" if self._compressed(r) else "full")
+
     def _out_bytes(self, r):
         return 2 * (r.level + 1) * self.plans[r.log_n].n * 4
 
@@ -105,7 +115,8 @@ class Server:
     def submit(self, r):
         """Queue a request; rejects one that could never fit the budget."""
         if (r.log_n not in self.plans or not 0 <= r.key < len(self.keys[r.log_n])
-                or not 0 <= r.level < self.plans[r.log_n].num_q):
+                or not 0 <= r.level < self.plans[r.log_n].num_q
+                or (r.galois is not None and (r.c0 is None or self._compressed(r)))):
             r.status = "rejected: invalid request"
             self.rejected.append(r)
             return False
@@ -121,10 +132,10 @@ class Server:
     def _form_batch(self):
         if not self.queue:
             return None
-        n0, c0 = self.queue[0].log_n, self._compressed(self.queue[0])
+        n0, k0 = self.queue[0].log_n, self._kind(self.queue[0])
         batch = []
         for r in list(self.queue):
-            if r.log_n != n0 or self._compressed(r) != c0 or len(batch) >= self.max_batch:
+            if r.log_n != n0 or self._kind(r) != k0 or len(batch) >= self.max_batch:
                 continue
             ws, need = self._need(batch + [r])
             if self.in_flight + need > self.budget:
@@ -148,11 +159,17 @@ class Server:
             for r in batch:
                 st.wait_event(r.ready)
                 r.d.record_stream(st)
+                if r.c0 is not None:
+                    r.c0.record_stream(st)
                 r.out = torch.empty((2, r.level + 1, plan.n), dtype=torch.int32, device="cuda")
                 r.t_start = now
                 r.status = "running"
             try:
-                if self._compressed(batch[0]):
+                if self._kind(batch[0]) == "rotation":
+                    from . import ks_rotate_batch
+                    jobs = [(self.keys[r.log_n][r.key], r.galois, r.level, r.c0, r.d, r.out) for r in batch]
+                    ks_rotate_batch(plan.handle, jobs, self.pool.view(*blk), stream=st)
+                elif self._compressed(batch[0]):
                     jobs = [self.keys[r.log_n][r.key] + (r.level, r.d, r.out) for r in batch]
                     plan.keyswitch_batch_seeded(jobs, workspace=self.pool.view(*blk), stream=st)
                 else:

@@ -185,3 +185,46 @@ def test_compressed_keys_served_equal_alone(ks, setup):
     want = core.keyswitch(core.Params(LOG_N, NUM_Q, DNUM, plan.num_p), plan.moduli, r.level, evk,
                           r.d.cpu().numpy().view(np.uint32))
     assert np.array_equal(r.out.cpu().numpy().view(np.uint32), want)
+
+
+@pytest.mark.gpu
+def test_rotation_requests_served_equal_alone(ks, setup):
+    """A mix of key-switch requests and rotation requests (c0, c1, Galois
+    element, full rotation key): batches hold one kind, and every served
+    rotation equals the same rotation run alone (a hoisted group of one),
+    every key switch the MP key switch alone; one rotation also equals the
+    oracle."""
+    from paper_2311_01598_amd.serve import Request, Server, poisson_arrivals
+    from oracle import core
+    plan, keys = setup
+    rng = np.random.default_rng(17)
+    reqs = []
+    for i in range(40):
+        level = int(rng.integers(0, NUM_Q))
+        d = torch.from_numpy(synth.uniform_limbs(plan.moduli[:level + 1], plan.n, 17000 + i).view(np.int32)).cuda()
+        key = int(rng.integers(0, NKEYS))
+        if i % 2:
+            c0 = torch.from_numpy(synth.uniform_limbs(plan.moduli[:level + 1], plan.n, 18000 + i).view(np.int32)).cuda()
+            reqs.append(Request(i, key, LOG_N, level, d, 0.0, c0=c0, galois=core.galois_rotation(LOG_N, key + 1)))
+        else:
+            reqs.append(Request(i, key, LOG_N, level, d, 0.0))
+    server = Server({LOG_N: plan}, {LOG_N: keys}, budget_bytes=64 << 20, streams=3, max_batch=8)
+    st = server.run(list(zip(poisson_arrivals(20000.0, len(reqs), seed=18), reqs)), max_seconds=60)
+    print(st, flush=True)
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["rejected"] == 0
+    for r in reqs:
+        if r.galois is None:
+            want = _alone(plan, keys, r)
+        else:
+            want = plan.rotate(keys[r.key], r.galois, r.level, r.c0, r.d)
+        assert torch.equal(r.out, want), f"request {r.rid}"
+    r = next(x for x in reqs if x.galois is not None)
+    ev = keys[r.key].cpu().numpy().view(np.uint32)
+    want = core.rotate_hoisted(core.Params(LOG_N, NUM_Q, DNUM, plan.num_p), plan.moduli, r.level,
+                               r.c0.cpu().numpy().view(np.uint32), r.d.cpu().numpy().view(np.uint32), [r.galois],
+                               [ev])[0]
+    assert np.array_equal(r.out.cpu().numpy().view(np.uint32), want)
+    # a rotation request with a compressed key is rejected (rotation batches take full keys)
+    bad = Request(99, 0, LOG_N, 0, reqs[0].d[:1], 0.0, c0=reqs[0].d[:1], galois=5)
+    srv = Server({LOG_N: plan}, {LOG_N: [(keys[0].view(DNUM, 2, -1)[:, 0].contiguous(), 1)]}, budget_bytes=64 << 20)
+    assert srv.run([(0.0, bad)], max_seconds=10)["rejected"] == 1
