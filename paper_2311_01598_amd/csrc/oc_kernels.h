@@ -577,7 +577,7 @@ __device__ __forceinline__ void ld4_nt(uint32_t (&v)[4], const uint32_t *p) {
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
-template <bool IS_P, bool SEEDED, bool EXT>
+template <bool IS_P, bool SEEDED, bool EXT, bool ONE = false>
 __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
@@ -618,7 +618,10 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   auto gen_a = [&](uint32_t (&a)[4], uint32_t j) { seeded_a4(a, J.a_seed, ctr0 + j * (uint32_t)evk_step, m); };
 
   // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the
-  // foreign digits.  Job jb of a round runs in slot jb % 4.
+  // foreign digits.  Job jb of a round runs in slot jb % 4.  ONE: the launch
+  // guarantees njobs <= 4, and the tile is compiled without the round loop,
+  // whose back edge keeps about 70 more VGPRs live (81 instead of 153 for
+  // ROW_Q: 5 instead of 3 waves per SIMD).
   const uint32_t njobs = IS_P ? ndig : ndig + 1;
   auto job_digit = [&](uint32_t jb) -> uint32_t {
     if (!IS_P && jb < 2) return 0xffffffffu;
@@ -646,6 +649,9 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
 #pragma unroll
     for (int s2 = 0; s2 < kSlots; s2++) {
       const uint32_t jb2 = base + s2;
+      // the ModDown terms of the first round have no key (known at compile
+      // time: no registers and no loads for them)
+      if (!IS_P && jb2 < 2) continue;
       uint32_t d2 = jb2 < njobs ? job_digit(jb2) : 0xffffffffu;
       d2 = d2 == 0xffffffffu ? dummy : d2;
       ld4_nt(ek[s2][0], evk_t + (kHalves * d2 + 0) * evk_step);
@@ -686,7 +692,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // at most 16 digits (checked at plan creation): one REDC per sum
   uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
   uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0};
-  for (uint32_t base = 0; base < njobs; base += kSlots) {
+  for (uint32_t base = 0; base < (ONE ? 1u : njobs); base += kSlots) {
     if (base) {
       load_src(x, base);
       load_keys(base);
@@ -1035,13 +1041,20 @@ __device__ __forceinline__ uint32_t xcd_col_tile(uint32_t b) {
 
 // One launch per phase: grid x = tiles (max over jobs), grid z = job.
 // The summing row phases are asked for 3 workgroups per CU (3 waves per
-// SIMD): their per-term loop otherwise holds 174-184 VGPRs.
-template <int PHASE>
-constexpr int oc_min_blocks() { return (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) ? 3 : 1; }
+// SIMD): their per-term loop otherwise holds 174-184 VGPRs.  (Asking the
+// one-round ROW_Q kernel for 6 instead of its natural 5 costs a 16-byte
+// spill per thread and was measured slower.)
+template <int PHASE_ID>
+constexpr int oc_min_blocks() {
+  constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
+  return (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) ? 3 : 1;
+}
 
-template <int A, int PHASE, int TT>
-__global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE>()) void k_oc_phase(DevPlan P, OcJob one,
-                                                                                  const OcJob *jobs) {
+template <int A, int PHASE_ID, int TT>
+__global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_phase(
+    DevPlan P, OcJob one, const OcJob *jobs) {
+  constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
+  constexpr bool ONE = (PHASE_ID & OC_ONE_ROUND) != 0;
   __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>()];
   // the job table is read-only while the kernel runs: scalar loads keep
   // every job field (pointers, level, tile counts) uniform in SGPRs
@@ -1055,16 +1068,20 @@ __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE>()) void k_oc_phase
     for (int i = 0; i < (int)(sizeof(OcJob) / 4); i++) dst[i] = src[i];
   }
   constexpr bool COL = PHASE != OC_INTT_ROW && PHASE != OC_ROW_P && PHASE != OC_ROW_Q;
-  if constexpr (PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED) {
+  if constexpr (PHASE == OC_ROW_P || PHASE == OC_ROW_Q) {
+    constexpr bool IS_P = PHASE == OC_ROW_P;
+    if (blockIdx.x >= J.tiles[PHASE]) return;
+    tile_row<IS_P, false, false, ONE>(P, J, blockIdx.x, lds);
+  } else if constexpr (PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SEEDED;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, true, false>(P, J, blockIdx.x, lds);
+    tile_row<IS_P, true, false, ONE>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
                        PHASE == OC_ROW_Q_SEEDED_EXT) {
     constexpr bool IS_P = PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_P_SEEDED_EXT;
     constexpr bool SEEDED = PHASE == OC_ROW_P_SEEDED_EXT || PHASE == OC_ROW_Q_SEEDED_EXT;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, SEEDED, true>(P, J, blockIdx.x, lds);
+    tile_row<IS_P, SEEDED, true, ONE>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SUM;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
@@ -1092,8 +1109,34 @@ template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
                          hipStream_t st) {
   if (!tiles) return;  // e.g. no Q target outside the only digit at level 0
-  KS_LAUNCH(pl, kOcPhaseName[PHASE], (k_oc_phase<A, PHASE, TT>), dim3(tiles, 1, count), dim3(kOcThreads), 0, st,
+  KS_LAUNCH(pl, kOcPhaseName[PHASE & ~OC_ONE_ROUND], (k_oc_phase<A, PHASE, TT>), dim3(tiles, 1, count),
+            dim3(kOcThreads), 0, st,
             pl.dev, one, jobs);
+}
+
+// The row stage of one tower kind (special: ROW_P, else ROW_Q) in the
+// variant `rows`; ONE = OC_ONE_ROUND or 0 (the summing stages have their own
+// per-term loop and take no flag).
+template <int A, bool SPECIAL, uint32_t ONE>
+static void launch_row(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
+                       const uint32_t *max_tiles, OcRowVariant rows, hipStream_t st) {
+  const uint32_t tiles = max_tiles[SPECIAL ? OC_ROW_P : OC_ROW_Q];
+  switch (rows) {
+    case OC_ROWS_SEEDED:
+      launch_phase<A, (SPECIAL ? OC_ROW_P_SEEDED : OC_ROW_Q_SEEDED) | ONE, 1>(pl, one, jobs, count, tiles, st);
+      break;
+    case OC_ROWS_EXT:
+      launch_phase<A, (SPECIAL ? OC_ROW_P_EXT : OC_ROW_Q_EXT) | ONE, 1>(pl, one, jobs, count, tiles, st);
+      break;
+    case OC_ROWS_SEEDED_EXT:
+      launch_phase<A, (SPECIAL ? OC_ROW_P_SEEDED_EXT : OC_ROW_Q_SEEDED_EXT) | ONE, 1>(pl, one, jobs, count, tiles,
+                                                                                        st);
+      break;
+    case OC_ROWS_SUM:
+      launch_phase<A, SPECIAL ? OC_ROW_P_SUM : OC_ROW_Q_SUM, 1>(pl, one, jobs, count, tiles, st);
+      break;
+    default: launch_phase<A, (SPECIAL ? OC_ROW_P : OC_ROW_Q) | ONE, 1>(pl, one, jobs, count, tiles, st); break;
+  }
 }
 
 template <int A, int TT>
@@ -1106,26 +1149,15 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
     launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
   }
   if (part == OC_PART_MODUP) return;
-  switch (rows) {
-    case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_P_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
-    case OC_ROWS_EXT: launch_phase<A, OC_ROW_P_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
-    case OC_ROWS_SEEDED_EXT:
-      launch_phase<A, OC_ROW_P_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st);
-      break;
-    case OC_ROWS_SUM: launch_phase<A, OC_ROW_P_SUM, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
-    default: launch_phase<A, OC_ROW_P, 1>(pl, one, jobs, count, max_tiles[OC_ROW_P], st); break;
-  }
+  // the largest l+1 of the launch (ROW_Q tiles: row blocks x towers) decides
+  // whether the row tiles of every job fit one round of the slot loop
+  const uint32_t ndig = cdiv(max_tiles[OC_ROW_Q] / ((1u << A) / kRBQ), pl.alpha);
+  if (ndig <= (uint32_t)kSlots) launch_row<A, true, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
+  else launch_row<A, true, 0>(pl, one, jobs, count, max_tiles, rows, st);
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
-  switch (rows) {
-    case OC_ROWS_SEEDED: launch_phase<A, OC_ROW_Q_SEEDED, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
-    case OC_ROWS_EXT: launch_phase<A, OC_ROW_Q_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
-    case OC_ROWS_SEEDED_EXT:
-      launch_phase<A, OC_ROW_Q_SEEDED_EXT, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
-      break;
-    case OC_ROWS_SUM: launch_phase<A, OC_ROW_Q_SUM, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
-    default: launch_phase<A, OC_ROW_Q, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st); break;
-  }
+  if (ndig + 1 <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
+  else launch_row<A, false, 0>(pl, one, jobs, count, max_tiles, rows, st);
 }
 
 template <int A>
