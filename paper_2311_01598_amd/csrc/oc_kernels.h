@@ -620,8 +620,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // transform jobs: IS_P: every digit; Q: the two ModDown terms, then the
   // foreign digits.  Job jb of a round runs in slot jb % 4.  ONE: the launch
   // guarantees njobs <= 4, and the tile is compiled without the round loop,
-  // whose back edge keeps about 70 more VGPRs live (81 instead of 153 for
-  // ROW_Q: 5 instead of 3 waves per SIMD).
+  // whose back edge keeps about 70 more VGPRs live (71 instead of 153 for
+  // ROW_Q: 6 instead of 3 waves per SIMD).
   const uint32_t njobs = IS_P ? ndig : ndig + 1;
   auto job_digit = [&](uint32_t jb) -> uint32_t {
     if (!IS_P && jb < 2) return 0xffffffffu;
@@ -670,7 +670,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   uint32_t x[16];
   load_src(x, 0);
   uint32_t yo[4], eo0[4], eo1[4];
-  if (!IS_P) {  // own digit: the input tower itself (Sec. IV-C bypass)
+  auto load_own = [&]() {  // own digit: the input tower itself (Sec. IV-C bypass)
     if (EXT) {
 #pragma unroll
       for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + roff_s + pofs[i]];
@@ -679,7 +679,11 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     }
     ld4_nt(eo0, evk_t + (kHalves * own + 0) * evk_step);
     if (!SEEDED) ld4_nt(eo1, evk_t + (kHalves * own + 1) * evk_step);
-  }
+  };
+  // ONE: issued after the forward transform, so that they are not held
+  // through it (their latency is covered by the slot products and the other
+  // waves)
+  if (!IS_P && !ONE) load_own();
   load_keys(0);
   // ROW_P: the inverse twiddles of its ModDown P1 pass are loaded now, so
   // that their latency overlaps the forward round instead of following it
@@ -700,6 +704,7 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
     // a ModDown term is a natural row; a digit row is permuted under EXT
     const bool perm_row = EXT && base + slot < njobs && job_digit(base + slot) != 0xffffffffu;
     row_round_fwd(x, base + slot < njobs, row_buf(lds, slot, r), tig, perm_row ? twr_s : twr, q);
+    if (!IS_P && ONE) load_own();
 #pragma unroll
     for (int s2 = 0; s2 < kSlots; s2++) {
       const uint32_t jb2 = base + s2;
