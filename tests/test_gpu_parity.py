@@ -120,6 +120,39 @@ def test_oc_tiles_n16(ks, big_case, tile):
     plan.close()
 
 
+def test_row_round_builds_in_mixed_batches(ks):
+    """Row tiles run their transforms in rounds of 4 (ROW_P: one per digit;
+    ROW_Q: the foreign digits and the two ModDown terms).  A launch uses the
+    one-round build only when every job of it fits one round.  With alpha = 2
+    the levels below need 1..5 digits, covering:
+    - both row stages in one round (up to 3 digits);
+    - ROW_P in one round and ROW_Q in two (4 digits);
+    - both in two rounds (5 digits);
+    - small jobs inside a launch built for a larger one.
+    Every job, alone and in every batch, equals the oracle."""
+    p = oracle.Params(13, 10, 5, 3)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 5, p.n, synth.seed_for(7, 0))
+    levels = [1, 3, 5, 7, 9]  # 1, 2, 3, 4, 5 digits
+    ins = {l: synth.uniform_limbs(mods[:l + 1], p.n, synth.seed_for(7, 10 + l)) for l in levels}
+    want = {l: oracle.keyswitch(p, mods, l, evk, ins[l]) for l in levels}
+    plan = ks.Plan(13, 10, 5, 3)
+    evk_d = dev(evk)
+    ins_d = {l: dev(ins[l]) for l in levels}
+    for tile in (1, 2):
+        plan.configure("oc", tile_towers=tile)
+        for l in levels:
+            say(f"[rounds] tile={tile} single level={l}")
+            assert np.array_equal(host(plan.keyswitch(evk_d, l, ins_d[l])), want[l]), (tile, l)
+        for batch in ([5, 1, 3], [7, 1], [7, 5, 3, 1], [9, 1], [9, 7, 5, 3, 1]):
+            say(f"[rounds] tile={tile} batch={batch}")
+            outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in batch]
+            plan.keyswitch_batch([(evk_d, l, ins_d[l], o) for l, o in zip(batch, outs)])
+            for l, o in zip(batch, outs):
+                assert np.array_equal(host(o), want[l]), (tile, batch, l)
+    plan.close()
+
+
 SHAPES = [
     # (log_n, num_q, dnum, num_p, levels)
     (13, 5, 2, 0, [4, 2]),        # partial last digit
