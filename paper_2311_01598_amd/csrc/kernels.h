@@ -101,10 +101,10 @@ constexpr uint32_t OC_ROW_Q_SEEDED_EXT = OC_NPHASE + 6;
 // ModDown.
 constexpr uint32_t OC_ROW_P_SUM = OC_NPHASE + 7;
 constexpr uint32_t OC_ROW_Q_SUM = OC_NPHASE + 8;
-// Flag on a row phase's launch id (plain, seeded and extended row stages):
-// every job of the launch has at most 4 transform jobs per row tile (ROW_P:
-// ndig, ROW_Q: ndig + 1), so the tiles run one round of their slot loop,
-// compiled without the loop (a third of the registers).
+// Flag on a row phase's launch id: every job of the launch has at most 4
+// transforms per round loop of a row tile (ROW_P: ndig, ROW_Q: ndig + 1, the
+// summing ROW_Q: ndig - 1 per term), so the tiles run one round, compiled
+// without the loop (far fewer live registers).
 constexpr uint32_t OC_ONE_ROUND = 64;
 
 // Which row-stage kernels a launch uses.

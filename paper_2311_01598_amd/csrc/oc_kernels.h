@@ -813,7 +813,7 @@ __device__ __forceinline__ uint32_t mulmod_exact32(uint32_t a, uint32_t b, const
   return csub(mul_shoup(redc64((uint64_t)a * b, m), r32, r32p, m.q), m.q);
 }
 
-template <bool IS_P>
+template <bool IS_P, bool ONE = false>
 __device__ __forceinline__ void tile_row_sum(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
@@ -895,7 +895,8 @@ __device__ __forceinline__ void tile_row_sum(const DevPlan &P, const OcJob &J, u
     row_tw_store(twl_s, tws4, q, qr, true);  // the previous term's rounds ended with a barrier
     __syncthreads();
     uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
-    for (uint32_t base = 0; base < nfd; base += kSlots) {
+    // ONE: the launch guarantees nfd <= 4 (one round per term)
+    for (uint32_t base = 0; base < (ONE ? 1u : nfd); base += kSlots) {
       if (base) {
         load_src(base);
         load_keys(base);
@@ -1090,7 +1091,7 @@ __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_ph
   } else if constexpr (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SUM;
     if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row_sum<IS_P>(P, J, blockIdx.x, lds);
+    tile_row_sum<IS_P, ONE>(P, J, blockIdx.x, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -1120,8 +1121,7 @@ static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, ui
 }
 
 // The row stage of one tower kind (special: ROW_P, else ROW_Q) in the
-// variant `rows`; ONE = OC_ONE_ROUND or 0 (the summing stages have their own
-// per-term loop and take no flag).
+// variant `rows`; ONE = OC_ONE_ROUND or 0.
 template <int A, bool SPECIAL, uint32_t ONE>
 static void launch_row(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,
                        const uint32_t *max_tiles, OcRowVariant rows, hipStream_t st) {
@@ -1138,7 +1138,7 @@ static void launch_row(const Plan &pl, const OcJob &one, const OcJob *jobs, uint
                                                                                         st);
       break;
     case OC_ROWS_SUM:
-      launch_phase<A, SPECIAL ? OC_ROW_P_SUM : OC_ROW_Q_SUM, 1>(pl, one, jobs, count, tiles, st);
+      launch_phase<A, (SPECIAL ? OC_ROW_P_SUM : OC_ROW_Q_SUM) | ONE, 1>(pl, one, jobs, count, tiles, st);
       break;
     default: launch_phase<A, (SPECIAL ? OC_ROW_P : OC_ROW_Q) | ONE, 1>(pl, one, jobs, count, tiles, st); break;
   }
@@ -1156,12 +1156,16 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   if (part == OC_PART_MODUP) return;
   // the largest l+1 of the launch (ROW_Q tiles: row blocks x towers) decides
   // whether the row tiles of every job fit one round of the slot loop
+  // (a ROW_Q tile transforms the foreign digits and the two ModDown terms; a
+  // summing ROW_Q tile transforms the ModDown terms once, then per term only
+  // the foreign digits)
   const uint32_t ndig = cdiv(max_tiles[OC_ROW_Q] / ((1u << A) / kRBQ), pl.alpha);
+  const uint32_t qjobs = rows == OC_ROWS_SUM ? ndig - 1 : ndig + 1;
   if (ndig <= (uint32_t)kSlots) launch_row<A, true, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
   else launch_row<A, true, 0>(pl, one, jobs, count, max_tiles, rows, st);
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
-  if (ndig + 1 <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
+  if (qjobs <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
   else launch_row<A, false, 0>(pl, one, jobs, count, max_tiles, rows, st);
 }
 
