@@ -1056,19 +1056,40 @@ constexpr int oc_min_blocks() {
   return (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) ? 3 : 1;
 }
 
+// The row phases read the key.  In a batch their jobs are interleaved per
+// group of 8 tiles: block b runs on XCD b % 8, and with grid x =
+// roundup8(tiles) * njobs it takes tile (k / njobs) * 8 + b % 8 of job
+// k % njobs (k = b / 8).  Tile t of every job then runs on XCD t % 8 within
+// one window of 8 njobs blocks, so jobs that share a key read each key row
+// from that XCD's L2 after the first.  (With jobs along grid z, the same
+// tile of the next job ran a full round of tiles later, after its key rows
+// had left the L2.)
+template <int PHASE>
+constexpr bool oc_row_phase() {
+  return PHASE == OC_ROW_P || PHASE == OC_ROW_Q || PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED ||
+         PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
+         PHASE == OC_ROW_Q_SEEDED_EXT || PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM;
+}
+
 template <int A, int PHASE_ID, int TT>
 __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_phase(
-    DevPlan P, OcJob one, const OcJob *jobs) {
+    DevPlan P, OcJob one, const OcJob *jobs, uint32_t njobs) {
   constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
   constexpr bool ONE = (PHASE_ID & OC_ONE_ROUND) != 0;
   __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>()];
+  uint32_t bx = blockIdx.x, jz = blockIdx.z;
+  if (oc_row_phase<PHASE>() && jobs) {
+    const uint32_t k = blockIdx.x >> 3;
+    jz = k % njobs;
+    bx = (k / njobs) * 8 + (blockIdx.x & 7);
+  }
   // the job table is read-only while the kernel runs: scalar loads keep
   // every job field (pointers, level, tile counts) uniform in SGPRs
   OcJob J = one;
   if (jobs) {
     static_assert(sizeof(OcJob) % 4 == 0, "job entries are whole words");
     const __attribute__((address_space(4))) uint32_t *src =
-        (const __attribute__((address_space(4))) uint32_t *)(jobs + blockIdx.z);
+        (const __attribute__((address_space(4))) uint32_t *)(jobs + jz);
     uint32_t *dst = reinterpret_cast<uint32_t *>(&J);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(OcJob) / 4); i++) dst[i] = src[i];
@@ -1076,22 +1097,22 @@ __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_ph
   constexpr bool COL = PHASE != OC_INTT_ROW && PHASE != OC_ROW_P && PHASE != OC_ROW_Q;
   if constexpr (PHASE == OC_ROW_P || PHASE == OC_ROW_Q) {
     constexpr bool IS_P = PHASE == OC_ROW_P;
-    if (blockIdx.x >= J.tiles[PHASE]) return;
-    tile_row<IS_P, false, false, ONE>(P, J, blockIdx.x, lds);
+    if (bx >= J.tiles[PHASE]) return;
+    tile_row<IS_P, false, false, ONE>(P, J, bx, lds);
   } else if constexpr (PHASE == OC_ROW_P_SEEDED || PHASE == OC_ROW_Q_SEEDED) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SEEDED;
-    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, true, false, ONE>(P, J, blockIdx.x, lds);
+    if (bx >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row<IS_P, true, false, ONE>(P, J, bx, lds);
   } else if constexpr (PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_Q_EXT || PHASE == OC_ROW_P_SEEDED_EXT ||
                        PHASE == OC_ROW_Q_SEEDED_EXT) {
     constexpr bool IS_P = PHASE == OC_ROW_P_EXT || PHASE == OC_ROW_P_SEEDED_EXT;
     constexpr bool SEEDED = PHASE == OC_ROW_P_SEEDED_EXT || PHASE == OC_ROW_Q_SEEDED_EXT;
-    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row<IS_P, SEEDED, true, ONE>(P, J, blockIdx.x, lds);
+    if (bx >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row<IS_P, SEEDED, true, ONE>(P, J, bx, lds);
   } else if constexpr (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SUM;
-    if (blockIdx.x >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row_sum<IS_P, ONE>(P, J, blockIdx.x, lds);
+    if (bx >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
+    tile_row_sum<IS_P, ONE>(P, J, bx, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -1115,9 +1136,10 @@ template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
                          hipStream_t st) {
   if (!tiles) return;  // e.g. no Q target outside the only digit at level 0
-  KS_LAUNCH(pl, kOcPhaseName[PHASE & ~OC_ONE_ROUND], (k_oc_phase<A, PHASE, TT>), dim3(tiles, 1, count),
-            dim3(kOcThreads), 0, st,
-            pl.dev, one, jobs);
+  const dim3 grid = (oc_row_phase<(PHASE & ~OC_ONE_ROUND)>() && jobs) ? dim3((tiles + 7) / 8 * 8 * count, 1, 1)
+                                                                      : dim3(tiles, 1, count);
+  KS_LAUNCH(pl, kOcPhaseName[PHASE & ~OC_ONE_ROUND], (k_oc_phase<A, PHASE, TT>), grid, dim3(kOcThreads), 0, st,
+            pl.dev, one, jobs, count);
 }
 
 // The row stage of one tower kind (special: ROW_P, else ROW_Q) in the
