@@ -83,12 +83,18 @@ def stage_bytes(log_n, l1, k, alpha):
     }
 
 
-def kernel_source_digest():
+def kernel_source_digest(csrc=None):
+    """Digest of the library sources with comments and blank space removed:
+    the traffic counters stay valid across comment edits, not code edits."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2311_01598_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2311_01598_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        text = open(os.path.join(csrc, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

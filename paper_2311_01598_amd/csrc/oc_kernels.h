@@ -1045,11 +1045,12 @@ __device__ __forceinline__ uint32_t xcd_col_tile(uint32_t b) {
   }
 }
 
-// One launch per phase: grid x = tiles (max over jobs), grid z = job.
-// The summing row phases are asked for 3 workgroups per CU (3 waves per
-// SIMD): their per-term loop otherwise holds 174-184 VGPRs.  (Asking the
-// one-round ROW_Q kernel for 6 instead of its natural 5 costs a 16-byte
-// spill per thread and was measured slower.)
+// One launch per phase: grid x = tiles (max over jobs), grid z = job; the
+// row phases of a batch interleave their jobs in x instead (see
+// oc_row_phase).  The multi-round summing row phases are asked for 3
+// workgroups per CU (3 waves per SIMD): their loops otherwise hold 174-184
+// VGPRs.  The others need no bound (the one-round ROW_Q reaches 6 waves per
+// SIMD, its LDS limit, at 71 VGPRs).
 template <int PHASE_ID>
 constexpr int oc_min_blocks() {
   constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
