@@ -153,6 +153,33 @@ def test_row_round_builds_in_mixed_batches(ks):
     plan.close()
 
 
+def test_batch_row_tiles_not_a_multiple_of_8(ks):
+    """In a batch the row phases deal tiles to the 8 XCDs in groups of 8 per
+    job, padding the largest tile count to a multiple of 8.  At N = 2^12 a
+    row tile count is 4 x towers: with K = 3 and l+1 = 5 (the largest job)
+    both ROW_P (12 tiles) and ROW_Q (20) need padding.  Every job equals the
+    oracle, alone and in the batch, at both conversion tile widths."""
+    p = oracle.Params(12, 5, 5, 3)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 5, p.n, synth.seed_for(8, 0))
+    levels = [4, 2, 0, 3]
+    ins = [synth.uniform_limbs(mods[:l + 1], p.n, synth.seed_for(8, 1 + i)) for i, l in enumerate(levels)]
+    want = [oracle.keyswitch(p, mods, l, evk, x) for l, x in zip(levels, ins)]
+    plan = ks.Plan(12, 5, 5, 3)
+    evk_d = dev(evk)
+    ins_d = [dev(x) for x in ins]
+    for tile in (1, 2):
+        say(f"[pad8] tile={tile}")
+        plan.configure("oc", tile_towers=tile)
+        outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in levels]
+        plan.keyswitch_batch([(evk_d, l, x, o) for l, x, o in zip(levels, ins_d, outs)])
+        for i, (o, w) in enumerate(zip(outs, want)):
+            assert np.array_equal(host(o), w), (tile, i)
+        for l, x, w in zip(levels, ins_d, want):
+            assert np.array_equal(host(plan.keyswitch(evk_d, l, x)), w), (tile, l)
+    plan.close()
+
+
 SHAPES = [
     # (log_n, num_q, dnum, num_p, levels)
     (13, 5, 2, 0, [4, 2]),        # partial last digit
