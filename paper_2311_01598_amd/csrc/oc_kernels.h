@@ -637,7 +637,8 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
   // Loads are unconditional (an idle slot re-reads the round's last row, a
   // job without a key reads a key row the tile reads anyway) so that the
   // number of loads in flight is the same on every path and each wait
-  // covers exactly the loads it needs.
+  // covers exactly the loads it needs.  The one exception is decided at
+  // compile time: the ModDown slots of a Q tile's first round load no key.
   auto load_src = [&](uint32_t (&x)[16], uint32_t base) {
     const uint32_t *src = job_src(min(base + slot, njobs - 1));
 #pragma unroll
