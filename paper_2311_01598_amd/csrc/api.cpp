@@ -460,7 +460,7 @@ ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
   if (st != KS_OK) return st;
   ks_plan *pl = new (std::nothrow) ks_plan();
   if (!pl) return KS_ERR_NOMEM;
-  pl->p.cfg = ks_config_t{KS_SCHED_OC, 1, 16, 8, 1, 2, 0};
+  pl->p.cfg = ks_config_t{KS_SCHED_OC, 2, 16, 8, 1, 2, 0};  // the starting configuration ks.h documents
   st = plan_build(p, &pl->p);
   if (st != KS_OK) {
     plan_free(&pl->p);
