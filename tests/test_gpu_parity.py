@@ -180,6 +180,35 @@ def test_batch_row_tiles_not_a_multiple_of_8(ks):
     plan.close()
 
 
+def test_batch_of_100_jobs_three_keys(ks):
+    """The row phases decode (tile, job) from the block index of a launch
+    over all jobs (jobs interleaved per group of 8 tiles).  100 jobs at random
+    levels, each with one of 3 keys, each equal its own single-call result
+    (and, for a sample, the oracle), at both conversion tile widths."""
+    p = oracle.Params(12, 6, 3, 2)
+    mods = oracle.moduli(p)
+    keys = [synth.uniform_evk(mods, 3, p.n, synth.seed_for(9, k)) for k in range(3)]
+    rng = np.random.default_rng(9)
+    levels = [int(x) for x in rng.integers(0, 6, 100)]
+    kid = [int(x) for x in rng.integers(0, 3, 100)]
+    ins = [synth.uniform_limbs(mods[:l + 1], p.n, synth.seed_for(9, 10 + i)) for i, l in enumerate(levels)]
+    plan = ks.Plan(12, 6, 3, 2)
+    keys_d = [dev(k) for k in keys]
+    ins_d = [dev(x) for x in ins]
+    for i in (0, 37, 99):
+        want = oracle.keyswitch(p, mods, levels[i], keys[kid[i]], ins[i])
+        assert np.array_equal(host(plan.keyswitch(keys_d[kid[i]], levels[i], ins_d[i])), want), i
+    for tile in (1, 2):
+        say(f"[batch100] tile={tile}")
+        plan.configure("oc", tile_towers=tile)
+        singles = [host(plan.keyswitch(keys_d[kid[i]], l, ins_d[i])) for i, l in enumerate(levels)]
+        outs = [torch.empty((2, l + 1, p.n), dtype=torch.int32, device="cuda") for l in levels]
+        plan.keyswitch_batch([(keys_d[kid[i]], l, ins_d[i], outs[i]) for i, l in enumerate(levels)])
+        for i, (o, w) in enumerate(zip(outs, singles)):
+            assert np.array_equal(host(o), w), (tile, i, levels[i])
+    plan.close()
+
+
 SHAPES = [
     # (log_n, num_q, dnum, num_p, levels)
     (13, 5, 2, 0, [4, 2]),        # partial last digit
