@@ -146,7 +146,8 @@ def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
     hist = model.fit(Xtr, ytr, steps=steps, log_every=max(1, steps // 10))
     reg_pick, reg_pruned, reg_rand, reg_default = [], [], [], []
     per = []
-    default = tune.config_key({"schedule": "oc", "tile_towers": 1, "col_width": 16, "row_block": 8, "batch_mode": 1})
+    # the plan's starting configuration (ks_plan_create)
+    default = tune.config_key({"schedule": "oc", "tile_towers": 2, "col_width": 16, "row_block": 8, "batch_mode": 1})
     for k, times in groups.items():
         if k[:4] not in test_pts or len(times) < len(cfgs):
             continue

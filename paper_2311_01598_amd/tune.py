@@ -225,7 +225,7 @@ def report(rows, exp, commands=()):
         f"| model pick (no timing) | 0 | {f(s['regret_model_pick'])} |",
         f"| model top-{s['top_m']}, timed | {s['top_m']} | {f(s['regret_pruned_top_m'])} |",
         f"| {s['top_m']} random configurations, timed | {s['top_m']} | {f(s['regret_random_top_m'])} |",
-        f"| fixed default (oc/t1) | 0 | {f(s['regret_fixed_default'])} |", "",
+        f"| fixed default (oc/t2, the plan's starting configuration) | 0 | {f(s['regret_fixed_default'])} |", "",
         f"Best configuration per workload over the whole database: {dict(best)}.",
         f"Best OC over best MP configuration, per workload: median {np.median(sp):.2f}x, "
         f"min {sp.min():.2f}x, max {sp.max():.2f}x."]
