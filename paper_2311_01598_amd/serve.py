@@ -13,7 +13,8 @@
   fit is rejected.
 * Continuous batching: whenever one of `streams` slots is free, the queued
   requests of one ring degree and kind (key switch with a full or a
-  compressed key, or rotation; oldest first) form a batch that is launched
+  compressed key, or rotation) form a batch: the oldest request, then the
+  others with its key, then the rest in arrival order.  The batch is launched
   with ks_keyswitch_batch, ks_keyswitch_batch_seeded or ks_rotate_batch on
   that slot's stream; completions are polled with
   events, so requests arriving while others run are admitted as slots and
@@ -132,11 +133,15 @@ class Server:
     def _form_batch(self):
         if not self.queue:
             return None
-        n0, k0 = self.queue[0].log_n, self._kind(self.queue[0])
+        head = self.queue[0]
+        n0, k0 = head.log_n, self._kind(head)
+        # the oldest request, then the queued ones that share its key (the
+        # jobs of a batch that share a key read it from L2 after the first),
+        # then the rest of its degree and kind; arrival order within each
+        same = [r for r in self.queue if r.log_n == n0 and self._kind(r) == k0]
+        same.sort(key=lambda r: r.key != head.key)  # stable
         batch = []
-        for r in list(self.queue):
-            if r.log_n != n0 or self._kind(r) != k0 or len(batch) >= self.max_batch:
-                continue
+        for r in same[:self.max_batch]:
             ws, need = self._need(batch + [r])
             if self.in_flight + need > self.budget:
                 break
