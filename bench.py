@@ -510,7 +510,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); "
-              "multi-GPU key switching is a design note, not part of this build.", file=sys.stderr)
+              "the library runs on one GPU; multi-GPU key switching is described in the design notes only.", file=sys.stderr)
         return 2
     import numpy as np
     import torch

@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
   KS_OK = 0,
   KS_ERR_INVALID_ARG = 1,  /* bad pointer, size, level, alias, modulus */
-  KS_ERR_UNSUPPORTED = 2,  /* valid but outside what this build supports */
+  KS_ERR_UNSUPPORTED = 2,  /* valid, but not supported by this library */
   KS_ERR_NOMEM = 3,        /* device or host allocation failed */
   KS_ERR_BUDGET = 4,       /* workspace smaller than ks_workspace_size() */
   KS_ERR_DEVICE = 5        /* a HIP call or kernel launch failed */
