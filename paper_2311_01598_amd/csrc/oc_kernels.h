@@ -266,7 +266,15 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
 // towers, fused with the forward column pass.  Sources are canonical
 // (prescaled) limbs src + i*N, i < nsrc; constant of source i for target e
 // is cbase[i * cstride + tcol[e]] (REDC form).
-template <int A, int TT>
+// Targets of a tile share one LDS exchange region (transformed one after the
+// other), so that two-target tiles are not held to 4 per CU by their LDS.
+constexpr bool kConvSharedLds = true;
+template <int TT>
+constexpr int conv_lds_regions() { return kConvSharedLds ? 1 : TT; }
+
+// ONEC: the launch guarantees nsrc <= 16 (one chunk of sums): compiled
+// without the chunk loop, no partial result is live during the products.
+template <int A, int TT, bool ONEC = false>
 __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t *src, uint32_t nsrc,
                                                const uint32_t *cbase, uint32_t cstride, const uint32_t (&tg)[TT],
                                                const uint32_t (&tcol)[TT], uint32_t *const (&tout)[TT],
@@ -288,7 +296,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     ct[e].issue(P.tw_fwd32 + (size_t)tg[e] * N);
     qr[e] = ldcd(P.qrecip + tg[e]);
   }
-  uint2 *twl = reinterpret_cast<uint2 *>(lds + TT * G::LDS);
+  uint2 *twl = reinterpret_cast<uint2 *>(lds + conv_lds_regions<TT>() * G::LDS);
   uint32_t y[TT][E];
 #pragma unroll
   for (int e = 0; e < TT; e++)
@@ -305,7 +313,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
     for (int u = 0; u < E; u++) xv[u] = buf_ld(rs, vsrc, sb + ((uint32_t)u << (LOB + 10)));
   };
-  for (uint32_t i0 = 0; i0 < nsrc; i0 += 16) {
+  for (uint32_t i0 = 0; i0 < (ONEC ? 1u : nsrc); i0 += 16) {
     const uint32_t i1 = min(nsrc, i0 + 16);
     uint64_t acc[TT][E];
 #pragma unroll
@@ -333,19 +341,39 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
     for (int e = 0; e < TT; e++)
 #pragma unroll
-      for (int u = 0; u < E; u++) y[e][u] = csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
+      for (int u = 0; u < E; u++) y[e][u] = ONEC ? redc64(acc[e][u], mq[e]) : csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
   }
 #pragma unroll
   for (int e = 0; e < TT; e++) ct[e].store(twl + e * (1 << A), mq[e].q, qr[e], true);
   __syncthreads();
+  // forward column pass of each target: phase 1 in registers, phase 2 after
+  // an LDS exchange (region r = e, or 0 when the targets share one)
+  auto phase2 = [&](int e, int r) {
+    using Ph2 = Phase<A, 1 + R1, R2>;
+    const LdsTw tw{twl + e * (1 << A)};
+    const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
+#pragma unroll
+    for (int gi = 0; gi < Ph2::GROUPS / TPS; gi++) {
+      const int gg = tig + gi * TPS;
+      uint32_t x[1 << R2];
+#pragma unroll
+      for (int u = 0; u < (1 << R2); u++) x[u] = lds[r * G::LDS + Ph2::elem(gg, u) * W + w];
+      ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
+      const uint32_t vb = ((uint32_t)Ph2::base(gg) * 256u + c0 + w) * 4u;
+#pragma unroll
+      for (int u = 0; u < (1 << R2); u++) buf_st(rt, vb, (uint32_t)u << (Ph2::LOB + 10), x[u]);
+    }
+  };
+  constexpr bool SHARED = R2 > 0 && conv_lds_regions<TT>() == 1 && TT > 1;
 #pragma unroll
   for (int e = 0; e < TT; e++) {
     if ((uint32_t)e < ntgt) {
       const LdsTw tw{twl + e * (1 << A)};
       ct_group<A, 1, R1>(y[e], tig, 1u, tw, mq[e].q);
       if constexpr (R2 > 0) {
+        const int r = SHARED ? 0 : e;
 #pragma unroll
-        for (int u = 0; u < E; u++) lds[e * G::LDS + Ph1::elem(tig, u) * W + w] = y[e][u];
+        for (int u = 0; u < E; u++) lds[r * G::LDS + Ph1::elem(tig, u) * W + w] = y[e][u];
       } else {
         const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
         const uint32_t vb = ((uint32_t)Ph1::base(tig) * 256u + c0 + w) * 4u;
@@ -353,34 +381,23 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
         for (int u = 0; u < E; u++) buf_st(rt, vb, (uint32_t)u << (LOB + 10), y[e][u]);
       }
     }
-  }
-  if constexpr (R2 > 0) {
-    __syncthreads();
-    using Ph2 = Phase<A, 1 + R1, R2>;
-#pragma unroll
-    for (int e = 0; e < TT; e++) {
-      if ((uint32_t)e < ntgt) {
-        const LdsTw tw{twl + e * (1 << A)};
-        const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
-#pragma unroll
-        for (int gi = 0; gi < Ph2::GROUPS / TPS; gi++) {
-          const int gg = tig + gi * TPS;
-          uint32_t x[1 << R2];
-#pragma unroll
-          for (int u = 0; u < (1 << R2); u++) x[u] = lds[e * G::LDS + Ph2::elem(gg, u) * W + w];
-          ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
-          const uint32_t vb = ((uint32_t)Ph2::base(gg) * 256u + c0 + w) * 4u;
-#pragma unroll
-          for (int u = 0; u < (1 << R2); u++) buf_st(rt, vb, (uint32_t)u << (Ph2::LOB + 10), x[u]);
-        }
-      }
+    if constexpr (SHARED) {  // this target's phase 2 before the next one's phase 1 overwrites the region
+      __syncthreads();
+      if ((uint32_t)e < ntgt) phase2(e, 0);
+      if (e + 1 < TT) __syncthreads();
     }
+  }
+  if constexpr (R2 > 0 && !SHARED) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < TT; e++)
+      if ((uint32_t)e < ntgt) phase2(e, e);
   }
   __syncthreads();
 }
 
 // UP_P and UP_Q tiles: decode (digit, target chunk, column block).
-template <int A, int TT>
+template <int A, int TT, bool ONEC = false>
 __device__ __forceinline__ void tile_up(const DevPlan &P, const OcJob &J, uint32_t tile, bool special, uint32_t ttu,
                                         uint32_t *lds) {
   using G = ColGeom<A>;
@@ -425,12 +442,12 @@ __device__ __forceinline__ void tile_up(const DevPlan &P, const OcJob &J, uint32
     tout[e] = ok ? J.ycol + ((size_t)j * T + t) * N : nullptr;
     if (ok) ntgt = e + 1;
   }
-  tile_bconv_col<A, TT>(P, J.xt + (size_t)lo * N, s, P.up_conv + ((size_t)j * P.alpha + (s - 1)) * P.alpha * P.ntot,
+  tile_bconv_col<A, TT, ONEC>(P, J.xt + (size_t)lo * N, s, P.up_conv + ((size_t)j * P.alpha + (s - 1)) * P.alpha * P.ntot,
                         P.ntot, tg, tcol, tout, ntgt, c0, lds);
 }
 
 // DN tiles: decode (poly, Q-target chunk, column block).
-template <int A, int TT>
+template <int A, int TT, bool ONEC = false>
 __device__ __forceinline__ void tile_dn(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t ttd, uint32_t *lds) {
   using G = ColGeom<A>;
   const size_t N = (size_t)1 << P.log_n;
@@ -446,7 +463,7 @@ __device__ __forceinline__ void tile_dn(const DevPlan &P, const OcJob &J, uint32
     tout[e] = ok ? J.wcol + ((size_t)s * L1 + i) * N : nullptr;
     if (ok) ntgt = e + 1;
   }
-  tile_bconv_col<A, TT>(P, J.zp + (size_t)s * P.num_p * N, P.num_p, P.dn_conv, P.num_q, tg, tcol, tout, ntgt, c0, lds);
+  tile_bconv_col<A, TT, ONEC>(P, J.zp + (size_t)s * P.num_p * N, P.num_p, P.dn_conv, P.num_q, tg, tcol, tout, ntgt, c0, lds);
 }
 
 // ROW_P / ROW_Q tiles: (tower, block of kRB4 = 4 rows).  A row's
@@ -1021,7 +1038,7 @@ constexpr int oc_phase_lds_words() {
              ? kRowTileLds
          : PHASE == OC_INTT_ROW                   ? kRowLds
          : (PHASE == OC_INTT_COL || PHASE == OC_INTT_COL_DN) ? ColGeom<A>::LDS + 2 * (1 << A)
-                                                           : TT * (ColGeom<A>::LDS + 2 * (1 << A));
+                                                           : conv_lds_regions<TT>() * ColGeom<A>::LDS + TT * 2 * (1 << A);
 }
 template <int A, int TT>
 constexpr int oc_lds_words() {
@@ -1120,7 +1137,10 @@ __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_ph
     const bool special = blockIdx.x < np;
     const uint32_t b = special ? blockIdx.x : blockIdx.x - np;
     if (!special && b >= J.tiles[OC_UP_Q]) return;
-    tile_up<A, TT>(P, J, xcd_col_tile<ColGeom<A>::CB>(b), special, J.ttu, lds);
+    tile_up<A, TT, ONE>(P, J, xcd_col_tile<ColGeom<A>::CB>(b), special, J.ttu, lds);
+  } else if constexpr (PHASE == OC_DN) {
+    if (blockIdx.x >= J.tiles[OC_DN]) return;
+    tile_dn<A, TT, ONE>(P, J, xcd_col_tile<ColGeom<A>::CB>(blockIdx.x), J.ttd, lds);
   } else {
     if (blockIdx.x >= J.tiles[PHASE]) return;
     const uint32_t tile = COL ? xcd_col_tile<ColGeom<A>::CB>(blockIdx.x) : blockIdx.x;
@@ -1174,8 +1194,12 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   if (part != OC_PART_REST) {
     launch_phase<A, OC_INTT_ROW, 1>(pl, one, jobs, count, max_tiles[OC_INTT_ROW], st);
     launch_phase<A, OC_INTT_COL, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL], st);
-    // a job's merged grid needs at most its own UP_P + UP_Q tiles
-    launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
+    // a job's merged grid needs at most its own UP_P + UP_Q tiles; sums of
+    // at most 16 products (alpha <= 16) take the one-chunk build
+    if (pl.alpha <= 16)
+      launch_phase<A, OC_UP_PQ | OC_ONE_ROUND, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
+    else
+      launch_phase<A, OC_UP_PQ, TT>(pl, one, jobs, count, max_tiles[OC_UP_P] + max_tiles[OC_UP_Q], st);
   }
   if (part == OC_PART_MODUP) return;
   // the largest l+1 of the launch (ROW_Q tiles: row blocks x towers) decides
@@ -1188,7 +1212,8 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   if (ndig <= (uint32_t)kSlots) launch_row<A, true, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
   else launch_row<A, true, 0>(pl, one, jobs, count, max_tiles, rows, st);
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
-  launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
+  if (pl.num_p <= 16) launch_phase<A, OC_DN | OC_ONE_ROUND, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
+  else launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
   if (qjobs <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
   else launch_row<A, false, 0>(pl, one, jobs, count, max_tiles, rows, st);
 }
