@@ -106,6 +106,11 @@ constexpr uint32_t OC_ROW_Q_SUM = OC_NPHASE + 8;
 // summing ROW_Q: ndig - 1 per term), so the tiles run one round, compiled
 // without the loop (far fewer live registers).
 constexpr uint32_t OC_ONE_ROUND = 64;
+// Flag on the summing ROW_Q launch id (with OC_ONE_ROUND): every term has at
+// most 2 foreign digits, so a round transforms two terms' digits at once.
+constexpr uint32_t OC_PAIR_TERMS = 128;
+// The phase a launch id runs (launch ids carry the flags above).
+constexpr uint32_t OC_PHASE_BITS = 63;
 
 // Which row-stage kernels a launch uses.
 enum OcRowVariant : uint32_t { OC_ROWS_PLAIN = 0, OC_ROWS_SEEDED, OC_ROWS_EXT, OC_ROWS_SEEDED_EXT, OC_ROWS_SUM };

@@ -831,8 +831,9 @@ __device__ __forceinline__ uint32_t mulmod_exact32(uint32_t a, uint32_t b, const
   return csub(mul_shoup(redc64((uint64_t)a * b, m), r32, r32p, m.q), m.q);
 }
 
-template <bool IS_P, bool ONE = false>
+template <bool IS_P, bool ONE = false, bool PAIR = false>
 __device__ __forceinline__ void tile_row_sum(const DevPlan &P, const OcJob &J, uint32_t tile, uint32_t *lds) {
+  static_assert(!PAIR || (!IS_P && ONE), "term pairs: summing ROW_Q tiles of one round");
   const size_t N = (size_t)1 << P.log_n;
   const uint32_t level = J.level, L1 = level + 1, T = L1 + P.num_p;
   const uint32_t rbk = (1u << P.loga) / kRB4, unit = tile / rbk, blk = tile % rbk;
@@ -881,81 +882,176 @@ __device__ __forceinline__ void tile_row_sum(const DevPlan &P, const OcJob &J, u
   }
   uint32_t twi4[kRB4 * kRowTw / kOcThreads];
   if (IS_P) row_tw_issue(twi4, P.tw_inv32 + (size_t)g * N, m0);
-  for (uint32_t ti = 0; ti < J.nterm; ti++) {
-    const RotTerm rt = J.terms[ti];
-    const size_t roff_s = galois_perm((uint32_t)roff, rt.galois, P.log_n) & ~255u;
-    uint32_t pofs[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) pofs[i] = galois_perm((uint32_t)roff + k0 + i, rt.galois, P.log_n) & 255u;
-    const uint32_t rs0 = (galois_perm(row0 * 256u, rt.galois, P.log_n) >> 8) & ~(uint32_t)(kRB4 - 1);
-    const uint2 *twr_s = twl_s + (uint32_t)((roff_s >> 8) - rs0) * kRowTwS;
-    const uint32_t *evk_t = rt.evk + (size_t)g * N + roff + k0;
-    uint32_t tws4[kRB4 * kRowTw / kOcThreads];
-    row_tw_issue(tws4, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + rs0);
-    auto load_src = [&](uint32_t base) {
-      const uint32_t *src = J.ycol + ((size_t)digit(min(base + slot, nfd - 1)) * T + t) * N + roff_s;
-#pragma unroll
-      for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
-    };
-    uint32_t ek[kSlots][2][4];
-    auto load_keys = [&](uint32_t base) {
-#pragma unroll
-      for (int s2 = 0; s2 < kSlots; s2++) {
-        const uint32_t d2 = digit(min(base + s2, nfd - 1));  // idle slots re-read a row the tile reads
-        ld4_nt(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
-        ld4_nt(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
+  if constexpr (!PAIR) {
+    for (uint32_t ti = 0; ti < J.nterm; ti++) {
+      const RotTerm rt = J.terms[ti];
+      const size_t roff_s = galois_perm((uint32_t)roff, rt.galois, P.log_n) & ~255u;
+      uint32_t pofs[4];
+  #pragma unroll
+      for (int i = 0; i < 4; i++) pofs[i] = galois_perm((uint32_t)roff + k0 + i, rt.galois, P.log_n) & 255u;
+      const uint32_t rs0 = (galois_perm(row0 * 256u, rt.galois, P.log_n) >> 8) & ~(uint32_t)(kRB4 - 1);
+      const uint2 *twr_s = twl_s + (uint32_t)((roff_s >> 8) - rs0) * kRowTwS;
+      const uint32_t *evk_t = rt.evk + (size_t)g * N + roff + k0;
+      uint32_t tws4[kRB4 * kRowTw / kOcThreads];
+      row_tw_issue(tws4, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + rs0);
+      auto load_src = [&](uint32_t base) {
+        const uint32_t *src = J.ycol + ((size_t)digit(min(base + slot, nfd - 1)) * T + t) * N + roff_s;
+  #pragma unroll
+        for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
+      };
+      uint32_t ek[kSlots][2][4];
+      auto load_keys = [&](uint32_t base) {
+  #pragma unroll
+        for (int s2 = 0; s2 < kSlots; s2++) {
+          const uint32_t d2 = digit(min(base + s2, nfd - 1));  // idle slots re-read a row the tile reads
+          ld4_nt(ek[s2][0], evk_t + (2 * d2 + 0) * evk_step);
+          ld4_nt(ek[s2][1], evk_t + (2 * d2 + 1) * evk_step);
+        }
+      };
+      if (nfd) {
+        load_src(0);
+        load_keys(0);
       }
-    };
-    if (nfd) {
-      load_src(0);
-      load_keys(0);
-    }
-    row_tw_store(twl_s, tws4, q, qr, true);  // the previous term's rounds ended with a barrier
-    __syncthreads();
-    uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
-    // ONE: the launch guarantees nfd <= 4 (one round per term)
-    for (uint32_t base = 0; base < (ONE ? 1u : nfd); base += kSlots) {
-      if (base) {
-        load_src(base);
-        load_keys(base);
+      row_tw_store(twl_s, tws4, q, qr, true);  // the previous term's rounds ended with a barrier
+      __syncthreads();
+      uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
+      // ONE: the launch guarantees nfd <= 4 (one round per term)
+      for (uint32_t base = 0; base < (ONE ? 1u : nfd); base += kSlots) {
+        if (base) {
+          load_src(base);
+          load_keys(base);
+        }
+        row_round_fwd(x, base + slot < nfd, row_buf(lds, slot, r), tig, twr_s, q);
+  #pragma unroll
+        for (int s2 = 0; s2 < kSlots; s2++) {
+          if (base + s2 >= nfd) break;
+          uint32_t y[4];
+  #pragma unroll
+          for (int i = 0; i < 4; i++) y[i] = canon4(row_buf(lds, s2, r)[rl(pofs[i])], q);
+  #pragma unroll
+          for (int i = 0; i < 4; i++) {
+            acc0[i] = mad64(y[i], ek[s2][0][i], acc0[i]);
+            acc1[i] = mad64(y[i], ek[s2][1][i], acc1[i]);
+          }
+        }
+        __syncthreads();  // LDS rows are rewritten by the next round
       }
-      row_round_fwd(x, base + slot < nfd, row_buf(lds, slot, r), tig, twr_s, q);
-#pragma unroll
-      for (int s2 = 0; s2 < kSlots; s2++) {
-        if (base + s2 >= nfd) break;
-        uint32_t y[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) y[i] = canon4(row_buf(lds, s2, r)[rl(pofs[i])], q);
-#pragma unroll
+      if (!IS_P) {  // the own digit, loaded after the rounds: fewer registers held across them
+        uint32_t yo[4], eo0[4], eo1[4];
+  #pragma unroll
+        for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + roff_s + pofs[i]];
+        ld4_nt(eo0, evk_t + (2 * own + 0) * evk_step);
+        ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
+  #pragma unroll
         for (int i = 0; i < 4; i++) {
-          acc0[i] = mad64(y[i], ek[s2][0][i], acc0[i]);
-          acc1[i] = mad64(y[i], ek[s2][1][i], acc1[i]);
+          acc0[i] = mad64(yo[i], eo0[i], acc0[i]);
+          acc1[i] = mad64(yo[i], eo1[i], acc1[i]);
         }
       }
-      __syncthreads();  // LDS rows are rewritten by the next round
-    }
-    if (!IS_P) {  // the own digit, loaded after the rounds: fewer registers held across them
-      uint32_t yo[4], eo0[4], eo1[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + roff_s + pofs[i]];
-      ld4_nt(eo0, evk_t + (2 * own + 0) * evk_step);
-      ld4_nt(eo1, evk_t + (2 * own + 1) * evk_step);
-#pragma unroll
+  #pragma unroll
       for (int i = 0; i < 4; i++) {
-        acc0[i] = mad64(yo[i], eo0[i], acc0[i]);
-        acc1[i] = mad64(yo[i], eo1[i], acc1[i]);
+        uint32_t v0 = redc64(acc0[i], m), v1 = redc64(acc1[i], m);
+        if (rt.diag) {
+          const uint32_t pv = gp(rt.diag)[(size_t)g * N + roff + k0 + i];
+          v0 = mulmod_exact32(v0, pv, m, r32, r32p);
+          v1 = mulmod_exact32(v1, pv, m, r32, r32p);
+        }
+        tot0[i] = csub(tot0[i] + v0, q);
+        tot1[i] = csub(tot1[i] + v1, q);
       }
     }
+  } else {
+    // Terms a = ti and b = ti + 1 share a round: a's digits run in slots
+    // [0, nfd), b's in [nfd, 2 nfd), each read through its own automorphism
+    // with its own permuted twiddles (b's table after a's).
+    uint2 *twl_b = twl_s + kRB4 * kRowTwS;
+    struct View {
+      const uint32_t *evk_t, *diag;
+      uint32_t roff_s, rs0, pofs[4];
+    };
+    auto view = [&](const RotTerm &rt) {
+      View v;
+      v.roff_s = galois_perm((uint32_t)roff, rt.galois, P.log_n) & ~255u;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      uint32_t v0 = redc64(acc0[i], m), v1 = redc64(acc1[i], m);
-      if (rt.diag) {
-        const uint32_t pv = gp(rt.diag)[(size_t)g * N + roff + k0 + i];
-        v0 = mulmod_exact32(v0, pv, m, r32, r32p);
-        v1 = mulmod_exact32(v1, pv, m, r32, r32p);
+      for (int i = 0; i < 4; i++) v.pofs[i] = galois_perm((uint32_t)roff + k0 + i, rt.galois, P.log_n) & 255u;
+      v.rs0 = (galois_perm(row0 * 256u, rt.galois, P.log_n) >> 8) & ~(uint32_t)(kRB4 - 1);
+      v.evk_t = rt.evk + (size_t)g * N + roff + k0;
+      v.diag = rt.diag;
+      return v;
+    };
+    for (uint32_t ti = 0; ti < J.nterm; ti += 2) {
+      const bool hb = ti + 1 < J.nterm;
+      const View va = view(J.terms[ti]);
+      const View vb = view(J.terms[hb ? ti + 1 : ti]);
+      // this thread's slot: term b past nfd, idle past 2 nfd (or without b)
+      const bool in_b = (uint32_t)slot >= nfd;
+      const bool act = in_b ? (hb && (uint32_t)slot < 2 * nfd) : true;
+      const uint32_t dj = in_b ? (uint32_t)slot - nfd : (uint32_t)slot;
+      // Idle slots read the own digit's rows: always in range (its ycol
+      // region is allocated, never written, and the values go unused; its
+      // key rows are read by the tile anyway), also without foreign digits.
+      {
+        const uint32_t *src = act ? J.ycol + ((size_t)digit(dj) * T + t) * N + (in_b ? vb.roff_s : va.roff_s)
+                                  : J.ycol + ((size_t)own * T + t) * N + va.roff_s;
+#pragma unroll
+        for (int u = 0; u < 16; u++) x[u] = gp(src)[tig + 16 * u];
       }
-      tot0[i] = csub(tot0[i] + v0, q);
-      tot1[i] = csub(tot1[i] + v1, q);
+      uint32_t ek[kSlots][2][4];
+#pragma unroll
+      for (int s2 = 0; s2 < kSlots; s2++) {
+        const bool b2 = hb && (uint32_t)s2 >= nfd && (uint32_t)s2 < 2 * nfd;
+        const uint32_t d2 = (uint32_t)s2 < nfd ? digit(s2) : b2 ? digit(s2 - nfd) : own;
+        const uint32_t *ev = b2 ? vb.evk_t : va.evk_t;
+        ld4_nt(ek[s2][0], ev + (2 * d2 + 0) * evk_step);
+        ld4_nt(ek[s2][1], ev + (2 * d2 + 1) * evk_step);
+      }
+      uint32_t twa[kRB4 * kRowTw / kOcThreads], twb[kRB4 * kRowTw / kOcThreads];
+      row_tw_issue(twa, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + va.rs0);
+      row_tw_issue(twb, P.tw_fwd32 + (size_t)g * N, (1u << P.loga) + vb.rs0);
+      row_tw_store(twl_s, twa, q, qr, true);  // the previous pair's round ended with a barrier
+      row_tw_store(twl_b, twb, q, qr, true);
+      __syncthreads();
+      const uint2 *twr_a = twl_s + (uint32_t)((va.roff_s >> 8) - va.rs0) * kRowTwS;
+      const uint2 *twr_b = twl_b + (uint32_t)((vb.roff_s >> 8) - vb.rs0) * kRowTwS;
+      row_round_fwd(x, act && nfd > 0, row_buf(lds, slot, r), tig, in_b ? twr_b : twr_a, q);
+      uint64_t acc[2][2][4] = {};
+#pragma unroll
+      for (int s2 = 0; s2 < kSlots; s2++) {
+        const bool b2 = (uint32_t)s2 >= nfd;
+        if (b2 && !(hb && (uint32_t)s2 < 2 * nfd)) break;
+        const View &v = b2 ? vb : va;
+        uint32_t y[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) y[i] = canon4(row_buf(lds, s2, r)[rl(v.pofs[i])], q);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          acc[b2][0][i] = mad64(y[i], ek[s2][0][i], acc[b2][0][i]);
+          acc[b2][1][i] = mad64(y[i], ek[s2][1][i], acc[b2][1][i]);
+        }
+      }
+      __syncthreads();  // LDS rows and tables are rewritten by the next pair
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        if (e && !hb) break;
+        const View &v = e ? vb : va;
+        uint32_t yo[4], eo0[4], eo1[4];  // the own digit, as above
+#pragma unroll
+        for (int i = 0; i < 4; i++) yo[i] = gp(J.d)[(size_t)t * N + v.roff_s + v.pofs[i]];
+        ld4_nt(eo0, v.evk_t + (2 * own + 0) * evk_step);
+        ld4_nt(eo1, v.evk_t + (2 * own + 1) * evk_step);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          uint32_t v0 = redc64(mad64(yo[i], eo0[i], acc[e][0][i]), m);
+          uint32_t v1 = redc64(mad64(yo[i], eo1[i], acc[e][1][i]), m);
+          if (v.diag) {
+            const uint32_t pv = gp(v.diag)[(size_t)g * N + roff + k0 + i];
+            v0 = mulmod_exact32(v0, pv, m, r32, r32p);
+            v1 = mulmod_exact32(v1, pv, m, r32, r32p);
+          }
+          tot0[i] = csub(tot0[i] + v0, q);
+          tot1[i] = csub(tot1[i] + v1, q);
+        }
+      }
     }
   }
   if (IS_P) {
@@ -1071,7 +1167,7 @@ __device__ __forceinline__ uint32_t xcd_col_tile(uint32_t b) {
 // SIMD, its LDS limit, at 71 VGPRs).
 template <int PHASE_ID>
 constexpr int oc_min_blocks() {
-  constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
+  constexpr int PHASE = PHASE_ID & OC_PHASE_BITS;
   return (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) ? 3 : 1;
 }
 
@@ -1093,9 +1189,10 @@ constexpr bool oc_row_phase() {
 template <int A, int PHASE_ID, int TT>
 __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_phase(
     DevPlan P, OcJob one, const OcJob *jobs, uint32_t njobs) {
-  constexpr int PHASE = PHASE_ID & ~OC_ONE_ROUND;
+  constexpr int PHASE = PHASE_ID & OC_PHASE_BITS;
   constexpr bool ONE = (PHASE_ID & OC_ONE_ROUND) != 0;
-  __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>()];
+  constexpr bool PAIR = (PHASE_ID & OC_PAIR_TERMS) != 0;
+  __shared__ uint32_t lds[oc_phase_lds_words<A, PHASE, TT>() + (PAIR ? 2 * kRB4 * kRowTwS : 0)];
   uint32_t bx = blockIdx.x, jz = blockIdx.z;
   if (oc_row_phase<PHASE>() && jobs) {
     const uint32_t k = blockIdx.x >> 3;
@@ -1131,7 +1228,8 @@ __global__ __launch_bounds__(kOcThreads, oc_min_blocks<PHASE_ID>()) void k_oc_ph
   } else if constexpr (PHASE == OC_ROW_P_SUM || PHASE == OC_ROW_Q_SUM) {
     constexpr bool IS_P = PHASE == OC_ROW_P_SUM;
     if (bx >= J.tiles[IS_P ? OC_ROW_P : OC_ROW_Q]) return;
-    tile_row_sum<IS_P, ONE>(P, J, bx, lds);
+    if constexpr (PAIR) tile_row_sum<false, true, true>(P, J, bx, lds);
+    else tile_row_sum<IS_P, ONE>(P, J, bx, lds);
   } else if constexpr (PHASE == OC_UP_PQ) {
     const uint32_t np = J.tiles[OC_UP_P];
     const bool special = blockIdx.x < np;
@@ -1158,9 +1256,9 @@ template <int A, int PHASE, int TT>
 static void launch_phase(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, uint32_t tiles,
                          hipStream_t st) {
   if (!tiles) return;  // e.g. no Q target outside the only digit at level 0
-  const dim3 grid = (oc_row_phase<(PHASE & ~OC_ONE_ROUND)>() && jobs) ? dim3((tiles + 7) / 8 * 8 * count, 1, 1)
+  const dim3 grid = (oc_row_phase<(PHASE & OC_PHASE_BITS)>() && jobs) ? dim3((tiles + 7) / 8 * 8 * count, 1, 1)
                                                                       : dim3(tiles, 1, count);
-  KS_LAUNCH(pl, kOcPhaseName[PHASE & ~OC_ONE_ROUND], (k_oc_phase<A, PHASE, TT>), grid, dim3(kOcThreads), 0, st,
+  KS_LAUNCH(pl, kOcPhaseName[PHASE & OC_PHASE_BITS], (k_oc_phase<A, PHASE, TT>), grid, dim3(kOcThreads), 0, st,
             pl.dev, one, jobs, count);
 }
 
@@ -1214,7 +1312,9 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
   launch_phase<A, OC_INTT_COL_DN, 1>(pl, one, jobs, count, max_tiles[OC_INTT_COL_DN], st);
   if (pl.num_p <= 16) launch_phase<A, OC_DN | OC_ONE_ROUND, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
   else launch_phase<A, OC_DN, TT>(pl, one, jobs, count, max_tiles[OC_DN], st);
-  if (qjobs <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
+  if (rows == OC_ROWS_SUM && qjobs <= 2)  // two terms per round
+    launch_phase<A, OC_ROW_Q_SUM | OC_ONE_ROUND | OC_PAIR_TERMS, 1>(pl, one, jobs, count, max_tiles[OC_ROW_Q], st);
+  else if (qjobs <= (uint32_t)kSlots) launch_row<A, false, OC_ONE_ROUND>(pl, one, jobs, count, max_tiles, rows, st);
   else launch_row<A, false, 0>(pl, one, jobs, count, max_tiles, rows, st);
 }
 

@@ -143,21 +143,24 @@ def _diag(mods, n, seed):
     return synth.uniform_limbs(mods, n, seed)
 
 
-@pytest.mark.parametrize("shape,with_diag", [((12, 4, 2, 2, 3), False), ((12, 4, 2, 2, 2), True),
-                                             ((16, 24, 3, 8, 23), True), ((13, 9, 3, 2, 5), True),
-                                             ((12, 7, 7, 1, 6), False)])
-def test_double_hoisted_sum(ks, shape, with_diag):
+@pytest.mark.parametrize("shape,with_diag,nterm", [((12, 4, 2, 2, 3), False, 4), ((12, 4, 2, 2, 2), True, 4),
+                                                   ((16, 24, 3, 8, 23), True, 4), ((13, 9, 3, 2, 5), True, 4),
+                                                   ((12, 7, 7, 1, 6), False, 4), ((13, 9, 3, 3, 8), True, 3),
+                                                   ((13, 9, 3, 3, 8), False, 1), ((12, 6, 3, 2, 1), True, 3)])
+def test_double_hoisted_sum(ks, shape, with_diag, nterm):
+    """Terms with at most 2 foreign digits are summed two per round in the
+    OC row stage; odd term counts leave the last one alone."""
     log_n, num_q, dnum, num_p, level = shape
     p = oracle.Params(log_n, num_q, dnum, num_p)
     mods = oracle.moduli(p)
     c0 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(27, 0))
     c1 = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(27, 1))
-    gal = [core.galois_rotation(log_n, r) for r in (0, 1, 3)] + [(2 << log_n) - 1]
+    gal = ([core.galois_rotation(log_n, r) for r in (0, 1, 3)] + [(2 << log_n) - 1])[:nterm]
     keys = [synth.uniform_evk(mods, dnum, p.n, synth.seed_for(27, 10 + i)) for i in range(len(gal))]
     diags = [_diag(mods, p.n, synth.seed_for(27, 30 + i)) for i in range(len(gal))] if with_diag else None
     want = core.rotate_sum_hoisted(p, mods, level, c0, c1, gal, keys, diags)
     plan = ks.Plan(log_n, num_q, dnum, num_p)
-    print(f"[rot sum] {shape} diag={with_diag}", flush=True)
+    print(f"[rot sum] {shape} diag={with_diag} terms={nterm}", flush=True)
     terms = [(dev(k), g, dev(diags[i]) if with_diag else None) for i, (k, g) in enumerate(zip(keys, gal))]
     for sched in ("oc", "mp"):  # the sum runs the same stages under any schedule
         plan.configure(sched)
