@@ -146,10 +146,12 @@ def _diag(mods, n, seed):
 @pytest.mark.parametrize("shape,with_diag,nterm", [((12, 4, 2, 2, 3), False, 4), ((12, 4, 2, 2, 2), True, 4),
                                                    ((16, 24, 3, 8, 23), True, 4), ((13, 9, 3, 2, 5), True, 4),
                                                    ((12, 7, 7, 1, 6), False, 4), ((13, 9, 3, 3, 8), True, 3),
-                                                   ((13, 9, 3, 3, 8), False, 1), ((12, 6, 3, 2, 1), True, 3)])
+                                                   ((13, 9, 3, 3, 8), False, 1), ((12, 6, 3, 2, 1), True, 3),
+                                                   ((12, 8, 4, 2, 7), True, 3), ((12, 10, 5, 2, 9), False, 4)])
 def test_double_hoisted_sum(ks, shape, with_diag, nterm):
-    """Terms with at most 2 foreign digits are summed two per round in the
-    OC row stage; odd term counts leave the last one alone."""
+    """Every build of the OC summing row stage: terms with at most 2 foreign
+    digits run two per round (odd term counts leave the last one alone),
+    terms with 3 or 4 one per round, terms with more over several rounds."""
     log_n, num_q, dnum, num_p, level = shape
     p = oracle.Params(log_n, num_q, dnum, num_p)
     mods = oracle.moduli(p)
