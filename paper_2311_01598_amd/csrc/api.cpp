@@ -248,10 +248,13 @@ OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
   return j;
 }
 
-uint32_t oc_tt(const Plan &pl) { return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1); }
+// l1: the largest l+1 of the launch
+uint32_t oc_tt(const Plan &pl, uint32_t l1) {
+  return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1, l1);
+}
 
 ks_status_t run_oc(const Plan &pl, const Job &jb, OcRowVariant rows, uint32_t *ws, hipStream_t st) {
-  const uint32_t tt = oc_tt(pl);
+  const uint32_t tt = oc_tt(pl, jb.level + 1);
   const OcJob j = make_oc_job(pl, jb, ws, tt);
   return dev_err(launch_oc_phases(pl, j, nullptr, 1, j.tiles, tt, rows, OC_PART_ALL, st));
 }
@@ -314,7 +317,9 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
 ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, OcRowVariant rows, const BatchLayout &lay,
                          char *ws, hipStream_t st) {
   const uint32_t mode = pl.cfg.batch_mode;
-  const uint32_t tt = mode == 2 ? 1 : oc_tt(pl);
+  uint32_t l1max = 0;
+  for (uint32_t i = 0; i < count; i++) l1max = std::max(l1max, jobs[i].level + 1);
+  const uint32_t tt = mode == 2 ? 1 : oc_tt(pl, l1max);
   const uint32_t spin = pl.cfg.spin_limit ? pl.cfg.spin_limit : (1u << 20);
   // host tables
   std::vector<OcJob> hj(count);
@@ -742,7 +747,7 @@ ks_status_t rotate_hoisted(ks_plan_t plan, uint32_t level, const uint32_t *c0, c
   if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   char *ws = (char *)workspace;
-  const uint32_t tt = oc_tt(pl);
+  const uint32_t tt = oc_tt(pl, level + 1);
   std::vector<OcJob> hj(count);
   for (uint32_t r = 0; r < count; r++) {
     OcJob &j = hj[r];
@@ -829,7 +834,7 @@ ks_status_t ks_rotate_sum_hoisted(ks_plan_t plan, uint32_t level, const uint32_t
   if (effective(pl) == KS_SCHED_OC) {
     // fused: the OC phases with summing row stages, one job whose regions
     // follow the term table (the OC regions are smaller than the MP ones)
-    const uint32_t tt = oc_tt(pl);
+    const uint32_t tt = oc_tt(pl, level + 1);
     OcJob j = make_oc_job(pl, Job{terms[0].evk, 0, level, c1, out}, X, tt);
     j.add0 = c0;
     j.terms = dterms;
@@ -873,7 +878,7 @@ ks_status_t ks_mult_relin(ks_plan_t plan, const uint32_t *evk, uint32_t level, c
   uint32_t *d = (uint32_t *)workspace;
   const size_t limbs = (size_t)(level + 1) * pl.n;
   TRY(launch_tensor(pl, level, a0, a1, b0, b1, d, st));
-  const uint32_t tt = oc_tt(pl);
+  const uint32_t tt = oc_tt(pl, level + 1);
   OcJob j = make_oc_job(pl, Job{evk, 0, level, d + 2 * limbs, out},
                         (uint32_t *)((char *)workspace + mult_tensor_bytes(pl, level)), tt);
   j.add0 = d;

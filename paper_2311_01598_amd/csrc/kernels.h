@@ -176,7 +176,7 @@ __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint3
 
 // Effective targets per basis-conversion tile (1 or 2) for a column pass of
 // length 2^loga.
-uint32_t oc_effective_tt(uint32_t loga, uint32_t want);
+uint32_t oc_effective_tt(uint32_t loga, uint32_t want, uint32_t l1);
 // Tile counts of every phase (host).
 void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles);
 // One launch per phase; jobs == nullptr runs `one` alone.  rows: the

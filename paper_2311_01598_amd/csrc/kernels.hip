@@ -512,10 +512,14 @@ hipError_t launch_rotsum_c0(const Plan &pl, uint32_t level, const uint32_t *c0, 
 }
 
 // ------------------------------------------------------------ OC entry
-uint32_t oc_effective_tt(uint32_t loga, uint32_t want) {
-  // two targets per tile keep 2 x 16 accumulators per thread; columns of
-  // 32 elements per thread (loga 5 and 9) stay at one
-  return (want >= 2 && loga != 5 && loga != 9) ? 2 : 1;
+uint32_t oc_effective_tt(uint32_t loga, uint32_t want, uint32_t l1) {
+  // Two targets per tile keep 2 x 16 accumulators per thread.  Columns of 32
+  // elements per thread: at loga 9 two targets (169 VGPRs, 2 waves per SIMD)
+  // halve the source re-reads, which pays from 17 towers up (l1 = the
+  // largest l+1 of the launch); below, the lower occupancy costs more.  loga
+  // 5 stays at one.
+  if (want < 2 || loga == 5) return 1;
+  return (loga != 9 || l1 >= 17) ? 2 : 1;
 }
 
 static uint32_t col_blocks(uint32_t loga) {

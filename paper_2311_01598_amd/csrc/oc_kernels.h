@@ -1321,7 +1321,7 @@ static void launch_phases_tt(const Plan &pl, const OcJob &one, const OcJob *jobs
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
                      uint32_t tt, OcRowVariant rows, OcPart part, hipStream_t st) {
-  if (tt >= 2 && ColGeom<A>::E <= 16) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, rows, part, st);
+  if (tt >= 2 && ColGeom<A>::E <= 32) launch_phases_tt<A, 2>(pl, one, jobs, count, max_tiles, rows, part, st);
   else launch_phases_tt<A, 1>(pl, one, jobs, count, max_tiles, rows, part, st);
   return hipGetLastError();
 }
