@@ -53,7 +53,8 @@ typedef enum {
 
 /* Execution orders of Sec. IV. */
 typedef enum {
-  KS_SCHED_AUTO = 0,  /* the plan's tuned choice (OC unless tuned otherwise) */
+  KS_SCHED_AUTO = 0,  /* per call, the autotuner's entry for the call's shape
+                         (ks_plan_set_tuned); OC when nothing is tuned */
   KS_SCHED_MP = 1,    /* Max-Parallel, Sec. IV-A: each stage over all towers */
   KS_SCHED_DC = 2,    /* Digit-Centric, Sec. IV-B: one digit at a time */
   KS_SCHED_OC = 3     /* Output-Centric, Sec. IV-C: one output tower tile at a time */
@@ -77,7 +78,11 @@ typedef struct {
  * plan's current value. */
 typedef struct {
   ks_schedule_t schedule;
-  uint32_t tile_towers;  /* OC: target towers per basis-conversion tile (1, 2) */
+  uint32_t tile_towers;  /* OC: target towers per basis-conversion tile (1, 2;
+                            4 is accepted and runs as 2).  Where a column
+                            holds 32 elements per thread (N = 2^13, and
+                            N = 2^17 when the launch's largest job has fewer
+                            than 17 towers) the tiles take one target */
   uint32_t col_width;    /* MP/DC: columns per column-pass workgroup (8, 16, 32) */
   uint32_t row_block;    /* MP/DC: rows per row-pass workgroup (4, 8, 16) */
   uint32_t batch_mode;   /* OC batches: 1 = one launch per phase over all jobs,
@@ -86,11 +91,14 @@ typedef struct {
                             the second half of the jobs on a second stream
                             owned by the plan (forked from and joined back
                             to `stream` with events) */
-  uint32_t graph;        /* batches: 1 = capture the launches in a hipGraph and
-                            replay it (currently switched off:
-                            KS_ERR_UNSUPPORTED), 2 = launch directly */
+  uint32_t graph;        /* OC batches: 1 = capture the phase launches (modes 1
+                            and 3) once per (count, workspace, configuration,
+                            tile counts) in a hipGraph and replay it, 2 =
+                            launch directly */
   uint32_t spin_limit;   /* persistent launch: polls before a dependency wait
                             gives up and flags an error (tests use tiny values) */
+  uint32_t batch_order;  /* OC batches: 1 = jobs in the caller's order, 2 = by
+                            decreasing level (results are the same) */
 } ks_config_t;
 
 typedef struct ks_plan *ks_plan_t;
@@ -109,6 +117,17 @@ typedef struct {
  * [num_q + num_p].  Sec. II (RNS towers of word-size moduli). */
 ks_status_t ks_params_moduli(const ks_params_t *p, uint32_t *host_out);
 
+/* Host only, needs no device; for tests of the (switched-off) persistent
+ * batch launch's work list, the tables it would run: for `count` jobs at
+ * `levels`, tiles [count][8] = tile count of every Output-Centric phase
+ * (one target per conversion tile), the segments in launch order (phase-major,
+ * then job-major; count * 8 of them) as seg_start / seg_job / seg_phase,
+ * deps [8] = bit mask of the phases each phase waits for (same job), and
+ * *total = the number of work items. */
+ks_status_t ks_oc_work_list(const ks_params_t *p, uint32_t count, const uint32_t *levels, uint32_t *tiles,
+                            uint32_t *seg_start, uint32_t *seg_job, uint32_t *seg_phase, uint32_t *deps,
+                            uint32_t *total);
+
 /* Host only: psi for modulus q at ring degree 2^log_n (the smallest
  * primitive 2N-th root of unity), or 0 if q is not a prime = 1 mod 2N. */
 uint32_t ks_root_of_unity(uint32_t q, uint32_t log_n);
@@ -117,7 +136,7 @@ uint32_t ks_root_of_unity(uint32_t q, uint32_t log_n);
  * twiddle, basis-conversion and ModDown tables (Sec. III-B/C) and upload
  * them.  *out owns them until ks_plan_destroy.  The plan starts with the
  * configuration {OC, tile_towers 2, col_width 16, row_block 8, batch_mode 1,
- * graph 2, spin_limit 0}: two targets per conversion tile (one where a column
+ * graph 2, spin_limit 0, batch_order 1}: two targets per conversion tile (one where a column
  * holds 32 elements per thread, N = 2^13 and 2^17) equal one target for a
  * single key switch and are faster for batches. */
 ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out);
@@ -126,6 +145,24 @@ ks_status_t ks_plan_destroy(ks_plan_t plan);
 ks_status_t ks_plan_moduli(ks_plan_t plan, uint32_t *host_out);
 ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg);
 ks_status_t ks_plan_get_config(ks_plan_t plan, ks_config_t *cfg);
+
+/* Autotuner results (the tuning layer above the paper's method: every
+ * configuration computes the same bits, Sec. IV, so tuning only measures
+ * time).  ks_plan_set_tuned records the configuration (schedule MP, DC or
+ * OC; zero fields mean "the plan's value at call time") for calls of `count`
+ * key switches (count >= 1) whose largest level is `level`.  While the
+ * plan's schedule is KS_SCHED_AUTO, ks_keyswitch (count 1),
+ * ks_keyswitch_batch and ks_workspace_size take the entry for the call's
+ * shape: the same level, else the nearest tuned level (the higher on a tie);
+ * among those, the largest tuned count not above the call's count, else the
+ * smallest.  Calls that run the OC order only (compressed keys, rotations,
+ * ks_keyswitch_noalloc) take OC with the plan's settings when that entry
+ * names another schedule.  ks_plan_resolve_config writes the configuration
+ * a call of that shape runs with (never AUTO).  Workspaces must be sized
+ * with ks_workspace_size under the same tuned entries. */
+ks_status_t ks_plan_set_tuned(ks_plan_t plan, uint32_t level, uint32_t count, const ks_config_t *cfg);
+ks_status_t ks_plan_clear_tuned(ks_plan_t plan);
+ks_status_t ks_plan_resolve_config(ks_plan_t plan, uint32_t level, uint32_t count, ks_config_t *out);
 
 /* Bytes of device workspace ks_keyswitch (count = 1) or ks_keyswitch_batch
  * needs for jobs at the given levels under the plan's current schedule.
@@ -145,10 +182,11 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
  * entries; the key may differ per job).  Each job's output equals
  * ks_keyswitch of that job alone.  Outputs must not overlap each other, any
  * input or the workspace.  With the OC schedule the jobs run together: one
- * launch per phase over all jobs, or one persistent work-queue launch, and
- * the launches are captured once per (count, workspace, configuration) in a
- * hipGraph that is replayed afterwards.  The job table travels in the
- * workspace, so concurrent batches need distinct workspaces.  For tests of
+ * launch per phase over all jobs (batch_mode 1), or the same split over two
+ * streams (3); with graph = 1 those launches are captured once per (count,
+ * workspace, configuration, tile counts) in a hipGraph that later calls
+ * replay.  The job table travels in the workspace (uploaded before every
+ * launch or replay), so concurrent batches need distinct workspaces.  For tests of
  * failure handling, the environment variable KS_FAULT_INJECT=<n> makes the
  * n-th call after the variable took its current value return KS_ERR_DEVICE
  * without enqueuing work. */

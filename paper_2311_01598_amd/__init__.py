@@ -34,7 +34,7 @@ class ks_params_t(ctypes.Structure):
 class ks_config_t(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("tile_towers", ctypes.c_uint32), ("col_width", ctypes.c_uint32),
                 ("row_block", ctypes.c_uint32), ("batch_mode", ctypes.c_uint32), ("graph", ctypes.c_uint32),
-                ("spin_limit", ctypes.c_uint32)]
+                ("spin_limit", ctypes.c_uint32), ("batch_order", ctypes.c_uint32)]
 
 
 class ks_job_t(ctypes.Structure):
@@ -75,6 +75,11 @@ _SIGS = {
     "ks_plan_moduli": (ctypes.c_int, [_VP, _U32P]),
     "ks_plan_set_config": (ctypes.c_int, [_VP, ctypes.POINTER(ks_config_t)]),
     "ks_plan_get_config": (ctypes.c_int, [_VP, ctypes.POINTER(ks_config_t)]),
+    "ks_oc_work_list": (ctypes.c_int, [ctypes.POINTER(ks_params_t), ctypes.c_uint32, _U32P, _U32P, _U32P, _U32P,
+                                       _U32P, _U32P, _U32P]),
+    "ks_plan_set_tuned": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ks_config_t)]),
+    "ks_plan_clear_tuned": (ctypes.c_int, [_VP]),
+    "ks_plan_resolve_config": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ks_config_t)]),
     "ks_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.POINTER(ctypes.c_size_t)]),
     "ks_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
@@ -208,22 +213,41 @@ def ks_plan_moduli(plan, count):
     return list(out)
 
 
-CONFIG_FIELDS = ("tile_towers", "col_width", "row_block", "batch_mode", "graph", "spin_limit")
+CONFIG_FIELDS = ("tile_towers", "col_width", "row_block", "batch_mode", "graph", "spin_limit", "batch_order")
 
 
 def ks_plan_set_config(plan, schedule=0, **fields):
-    if isinstance(schedule, str):
-        schedule = SCHEDULES[schedule]
-    unknown = set(fields) - set(CONFIG_FIELDS)
-    if unknown:
-        raise TypeError(f"unknown config fields {sorted(unknown)}")
-    c = ks_config_t(schedule, *[int(fields.get(f, 0)) for f in CONFIG_FIELDS])
+    c = _config(schedule, fields)
     _check(_lib.ks_plan_set_config(plan, ctypes.byref(c)), "ks_plan_set_config")
 
 
 def ks_plan_get_config(plan):
     c = ks_config_t()
     _check(_lib.ks_plan_get_config(plan, ctypes.byref(c)), "ks_plan_get_config")
+    return {"schedule": c.schedule, **{f: getattr(c, f) for f in CONFIG_FIELDS}}
+
+
+def _config(schedule, fields):
+    if isinstance(schedule, str):
+        schedule = SCHEDULES[schedule]
+    unknown = set(fields) - set(CONFIG_FIELDS)
+    if unknown:
+        raise TypeError(f"unknown config fields {sorted(unknown)}")
+    return ks_config_t(schedule, *[int(fields.get(f, 0)) for f in CONFIG_FIELDS])
+
+
+def ks_plan_set_tuned(plan, level, count, schedule, **fields):
+    c = _config(schedule, fields)
+    _check(_lib.ks_plan_set_tuned(plan, int(level), int(count), ctypes.byref(c)), "ks_plan_set_tuned")
+
+
+def ks_plan_clear_tuned(plan):
+    _check(_lib.ks_plan_clear_tuned(plan), "ks_plan_clear_tuned")
+
+
+def ks_plan_resolve_config(plan, level, count):
+    c = ks_config_t()
+    _check(_lib.ks_plan_resolve_config(plan, int(level), int(count), ctypes.byref(c)), "ks_plan_resolve_config")
     return {"schedule": c.schedule, **{f: getattr(c, f) for f in CONFIG_FIELDS}}
 
 
@@ -433,6 +457,18 @@ class Plan:
     def configure(self, schedule=0, **fields):
         ks_plan_set_config(self.handle, schedule, **fields)
 
+    def set_tuned(self, level, count, schedule, **fields):
+        """Record the tuner's configuration for calls of `count` key switches
+        whose largest level is `level` (used while the schedule is "auto")."""
+        ks_plan_set_tuned(self.handle, level, count, schedule, **fields)
+
+    def clear_tuned(self):
+        ks_plan_clear_tuned(self.handle)
+
+    def resolve(self, level, count=1):
+        """The configuration a call of that shape runs with."""
+        return ks_plan_resolve_config(self.handle, level, count)
+
     @property
     def config(self):
         return ks_plan_get_config(self.handle)
@@ -557,3 +593,4 @@ class Plan:
             self.close()
         except Exception:
             pass
+

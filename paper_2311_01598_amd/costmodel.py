@@ -1,35 +1,42 @@
-"""Learned cost model of the autotuner: an fp32 MLP (14 features -> 64 -> 64
+"""Learned cost model of the autotuner: an fp32 MLP (16 features -> 64 -> 64
 -> 1, ReLU) that predicts log(milliseconds per key switch) of a
 configuration, trained on the GPU by the library's own kernels
 (ks_mlp_forward / ks_mlp_mse_grad / ks_mlp_backward / ks_mlp_adam).
 
 Pruned search: rank every configuration by predicted time and time only the
 top M; exhaustive search (tune.exhaustive) stays as fallback and judge.
+`default_model()` loads the weights trained on the timing database of this
+GPU (data/costmodel.npz, written by `tune train`), which the live tuner
+uses to prune.
 """
 import json
 import math
+import os
 
 import numpy as np
 
 from . import tune
 
-FEATURES = ("log_n", "towers", "dnum", "alpha", "num_p", "ndig", "log2_count", "is_mp", "is_dc", "is_oc",
-            "tile_towers", "log2_col", "log2_row", "split")
+FEATURES = ("log_n", "towers", "dnum", "alpha", "num_p", "ndig", "log2_count", "spread", "is_mp", "is_dc",
+            "is_oc", "tile_towers", "log2_col", "log2_row", "split", "order_desc")
 HIDDEN = 64
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "costmodel.npz")
 
 
-def features(log_n, num_q, dnum, num_p, level, count, cfg):
+def features(log_n, num_q, dnum, num_p, level, count, cfg, spread=1.0):
+    """spread: mean over the call's jobs of l+1, divided by the largest l+1
+    (1 for a single level)."""
     alpha = -(-num_q // dnum)
     towers = level + 1
     ndig = -(-towers // alpha)
     s = cfg["schedule"]
-    return [log_n, towers, dnum, alpha, num_p, ndig, math.log2(count), s == "mp", s == "dc", s == "oc",
+    return [log_n, towers, dnum, alpha, num_p, ndig, math.log2(count), spread, s == "mp", s == "dc", s == "oc",
             cfg["tile_towers"], math.log2(cfg["col_width"]), math.log2(cfg["row_block"]),
-            cfg.get("batch_mode", 1) == 3]
+            cfg.get("batch_mode", 1) == 3, cfg.get("batch_order", 1) == 2]
 
 
 def record_features(r):
-    return features(r["log_n"], r["num_q"], r["dnum"], r["num_p"], r["level"], r["count"], r)
+    return features(r["log_n"], r["num_q"], r["dnum"], r["num_p"], r["level"], r["count"], r, r.get("spread", 1.0))
 
 
 class CostModel:
@@ -94,11 +101,11 @@ class CostModel:
         ks.ks_mlp_forward(self.F, self.H, B, self.params, self._x(X), Y, act)
         return Y.cpu().numpy().astype(np.float64) * self.y_sd + self.y_mu
 
-    def rank(self, params, level, count, configs=None):
+    def rank(self, params, level, count, configs=None, spread=1.0):
         """Configurations sorted by predicted time (best first)."""
         configs = configs or tune.config_space()
         log_n, num_q, dnum, num_p = params
-        pred = self.predict([features(log_n, num_q, dnum, num_p, level, count, c) for c in configs])
+        pred = self.predict([features(log_n, num_q, dnum, num_p, level, count, c, spread) for c in configs])
         return [configs[i] for i in np.argsort(pred)]
 
     def save(self, path):
@@ -115,13 +122,27 @@ class CostModel:
         return m
 
 
+def default_model():
+    """The cost model trained on this GPU's timing database, or None when no
+    weights are present (the tuner then times every configuration)."""
+    return CostModel.load(WEIGHTS) if os.path.exists(WEIGHTS) else None
+
+
 def pruned_search(model, work, top_m=3, reps=5):
     """Time only the model's top-M configurations; returns (best, timed)."""
     params = (work.plan.log_n, work.plan.num_q, work.plan.dnum, work.plan.num_p)
-    cands = model.rank(params, work.level, work.count)[:top_m]
+    cands = model.rank(params, work.level, work.count, spread=work.spread)[:top_m]
     times = {tune.config_key(c): tune.time_config(work, c, reps) for c in cands}
     best = min(cands, key=lambda c: times[tune.config_key(c)])
     return best, times
+
+
+def train(rows, steps=3000, seed=0):
+    """The model trained on every timing of a database (for the live tuner)."""
+    model = CostModel(seed=seed)
+    hist = model.fit([record_features(r) for r in rows], [math.log(r["ms"]) for r in rows], steps=steps,
+                     log_every=max(1, steps // 10))
+    return model, hist
 
 
 def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
@@ -152,7 +173,7 @@ def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
         if k[:4] not in test_pts or len(times) < len(cfgs):
             continue
         best = min(times.values())
-        pred = model.predict([features(*k[:4], k[4], k[5], c) for c in cfgs])
+        pred = model.predict([features(*k[:4], k[4], k[5], c, k[6]) for c in cfgs])
         order = [keys[i] for i in np.argsort(pred)]
         pick = times[order[0]]
         pruned = min(times[x] for x in order[:top_m])
@@ -173,4 +194,5 @@ def experiment(rows, top_m=3, seed=0, steps=3000, holdout=0.2):
         "timings_per_workload": {"exhaustive": len(cfgs), "pruned": top_m},
         "final_train_loss": hist[-1][1] if hist else None,
     }
-    return {"summary": summary, "features": list(FEATURES), "loss_history": hist, "per_workload": per}
+    return {"summary": summary, "features": list(FEATURES), "loss_history": hist, "per_workload": per,
+            "model": model}

@@ -19,8 +19,55 @@ namespace {
 
 inline size_t limb_bytes(const Plan &pl) { return (size_t)pl.n * sizeof(uint32_t); }
 
+// The schedule the current call runs (run_cfg: the call's resolved
+// configuration); AUTO with nothing tuned is OC.
 ks_schedule_t effective(const Plan &pl) {
-  return pl.cfg.schedule == KS_SCHED_AUTO ? KS_SCHED_OC : pl.cfg.schedule;
+  const ks_config_t &c = run_cfg(pl);
+  return c.schedule == KS_SCHED_AUTO ? KS_SCHED_OC : c.schedule;
+}
+
+// The configuration of a call of `count` key switches whose largest level is
+// `level`: the plan's own, or, when its schedule is AUTO, the tuned entry for
+// that shape -- the same level, else the nearest tuned level (the higher on a
+// tie); among those, the largest tuned count not above `count`, else the
+// smallest -- with its zero fields taken from the plan's configuration.
+// With nothing tuned, AUTO runs OC with the plan's settings.  oc_only: calls
+// that run the OC order only (compressed keys, rotations, the scratch-backed
+// call) take OC with the plan's settings when the entry names another
+// schedule.
+ks_config_t resolve_cfg(Plan &pl, uint32_t level, uint32_t count, bool oc_only) {
+  std::lock_guard<std::mutex> g(pl.lock);
+  ks_config_t c = pl.cfg;
+  if (c.schedule != KS_SCHED_AUTO) return c;
+  const auto dist = [level](uint32_t l) { return l > level ? l - level : level - l; };
+  const TunedEntry *best = nullptr;
+  for (const TunedEntry &e : pl.tuned) {
+    bool take = !best;
+    if (!take) {
+      if (dist(e.level) != dist(best->level)) take = dist(e.level) < dist(best->level);
+      else if (e.level != best->level) take = e.level > best->level;
+      else if ((e.count <= count) != (best->count <= count)) take = e.count <= count;
+      else take = e.count <= count ? e.count > best->count : e.count < best->count;
+    }
+    if (take) best = &e;
+  }
+  const ks_config_t base = c;
+  c.schedule = KS_SCHED_OC;
+  if (best) {
+    const ks_config_t &t = best->cfg;
+    c.schedule = t.schedule;
+    if (t.tile_towers) c.tile_towers = t.tile_towers;
+    if (t.col_width) c.col_width = t.col_width;
+    if (t.row_block) c.row_block = t.row_block;
+    if (t.batch_mode) c.batch_mode = t.batch_mode;
+    if (t.graph) c.graph = t.graph;
+    if (t.batch_order) c.batch_order = t.batch_order;
+  }
+  if (oc_only && c.schedule != KS_SCHED_OC) {
+    c = base;
+    c.schedule = KS_SCHED_OC;
+  }
+  return c;
 }
 
 // Workspace of one key switch at `level`, in limbs, per schedule.
@@ -250,7 +297,8 @@ OcJob make_oc_job(const Plan &pl, const Job &jb, uint32_t *ws, uint32_t tt) {
 
 // l1: the largest l+1 of the launch
 uint32_t oc_tt(const Plan &pl, uint32_t l1) {
-  return oc_effective_tt(pl.dev.loga, pl.cfg.tile_towers ? pl.cfg.tile_towers : 1, l1);
+  const ks_config_t &c = run_cfg(pl);
+  return oc_effective_tt(pl.dev.loga, c.tile_towers ? c.tile_towers : 1, l1);
 }
 
 ks_status_t run_oc(const Plan &pl, const Job &jb, OcRowVariant rows, uint32_t *ws, hipStream_t st) {
@@ -314,13 +362,30 @@ ks_status_t launch_oc_batch(const Plan &pl, uint32_t count, const std::vector<ui
   return KS_OK;
 }
 
+}  // namespace
+
+uint32_t ks::oc_segments(const uint32_t *tiles, uint32_t count, std::vector<OcSeg> &segs) {
+  segs.clear();
+  segs.reserve((size_t)count * OC_NPHASE);
+  uint32_t total = 0;
+  for (uint32_t p = 0; p < OC_NPHASE; p++)
+    for (uint32_t i = 0; i < count; i++) {
+      segs.push_back(OcSeg{total, i, p, 0});
+      total += tiles[(size_t)i * OC_NPHASE + p];
+    }
+  return total;
+}
+
+namespace {
+
 ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, OcRowVariant rows, const BatchLayout &lay,
                          char *ws, hipStream_t st) {
-  const uint32_t mode = pl.cfg.batch_mode;
+  const ks_config_t &cfg = run_cfg(pl);
+  const uint32_t mode = cfg.batch_mode;
   uint32_t l1max = 0;
   for (uint32_t i = 0; i < count; i++) l1max = std::max(l1max, jobs[i].level + 1);
   const uint32_t tt = mode == 2 ? 1 : oc_tt(pl, l1max);
-  const uint32_t spin = pl.cfg.spin_limit ? pl.cfg.spin_limit : (1u << 20);
+  const uint32_t spin = cfg.spin_limit ? cfg.spin_limit : (1u << 20);
   // host tables
   std::vector<OcJob> hj(count);
   std::vector<uint32_t> max_tiles(OC_NPHASE, 0);
@@ -328,14 +393,10 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, OcRowVariant
     hj[i] = make_oc_job(pl, jobs[i], (uint32_t *)(ws + lay.region[i]), tt);
     for (uint32_t p = 0; p < OC_NPHASE; p++) max_tiles[p] = std::max(max_tiles[p], hj[i].tiles[p]);
   }
+  std::vector<uint32_t> tiles((size_t)count * OC_NPHASE);
+  for (uint32_t i = 0; i < count; i++) std::copy(hj[i].tiles, hj[i].tiles + OC_NPHASE, &tiles[(size_t)i * OC_NPHASE]);
   std::vector<OcSeg> segs;
-  segs.reserve((size_t)count * OC_NPHASE);
-  uint32_t total = 0;
-  for (uint32_t p = 0; p < OC_NPHASE; p++)
-    for (uint32_t i = 0; i < count; i++) {
-      segs.push_back(OcSeg{total, i, p, 0});
-      total += hj[i].tiles[p];
-    }
+  const uint32_t total = oc_segments(tiles.data(), count, segs);
   // the job and segment tables live in the workspace (the graph reads them there)
   // control words (zero), segment table and job table in one upload
   std::vector<char> blob(lay.regions, 0);
@@ -343,7 +404,7 @@ ks_status_t run_oc_batch(Plan &pl, uint32_t count, const Job *jobs, OcRowVariant
   std::memcpy(blob.data() + lay.jobs, hj.data(), hj.size() * sizeof(OcJob));
   TRY(upload_async(pl, ws, blob.data(), blob.size(), st));
 
-  const bool use_graph = pl.cfg.graph != 2 && !pl.trace.on;
+  const bool use_graph = cfg.graph != 2 && !pl.trace.on;
   if (!use_graph) return launch_oc_batch(pl, count, max_tiles, total, ws, lay, mode, tt, spin, rows, st);
 
   // graph keyed by (count, workspace, mode, tile, spin); the persistent launch
@@ -465,7 +526,7 @@ ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
   if (st != KS_OK) return st;
   ks_plan *pl = new (std::nothrow) ks_plan();
   if (!pl) return KS_ERR_NOMEM;
-  pl->p.cfg = ks_config_t{KS_SCHED_OC, 2, 16, 8, 1, 2, 0};  // the starting configuration ks.h documents
+  pl->p.cfg = ks_config_t{KS_SCHED_OC, 2, 16, 8, 1, 2, 0, 1};  // the starting configuration ks.h documents
   st = plan_build(p, &pl->p);
   if (st != KS_OK) {
     plan_free(&pl->p);
@@ -496,8 +557,7 @@ ks_status_t ks_plan_moduli(ks_plan_t plan, uint32_t *host_out) {
   return KS_OK;
 }
 
-ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
-  if (!plan || !cfg) return KS_ERR_INVALID_ARG;
+static ks_status_t check_cfg(const ks_config_t *cfg) {
   if ((int)cfg->schedule < 0 || (int)cfg->schedule > 3) return KS_ERR_INVALID_ARG;
   auto ok = [](uint32_t v, std::initializer_list<uint32_t> allowed) {
     if (!v) return true;
@@ -505,12 +565,19 @@ ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
     return false;
   };
   if (!ok(cfg->tile_towers, {1, 2, 4}) || !ok(cfg->col_width, {8, 16, 32}) || !ok(cfg->row_block, {4, 8, 16}) ||
-      !ok(cfg->batch_mode, {1, 2, 3}) || !ok(cfg->graph, {1, 2}))
+      !ok(cfg->batch_mode, {1, 2, 3}) || !ok(cfg->graph, {1, 2}) || !ok(cfg->batch_order, {1, 2}))
     return KS_ERR_INVALID_ARG;
-  // The persistent work-queue launch and graph capture of batches are
-  // switched off: a batch run through them stopped making progress on the
-  // device and the cause is not yet established.
-  if (cfg->batch_mode == 2 || cfg->graph == 1) return KS_ERR_UNSUPPORTED;
+  // The persistent work-queue launch is switched off: a batch run through it
+  // stopped making progress on the device and the cause is not established.
+  // (Graph capture of the per-phase launches, modes 1 and 3, is on.)
+  if (cfg->batch_mode == 2) return KS_ERR_UNSUPPORTED;
+  return KS_OK;
+}
+
+ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
+  if (!plan || !cfg) return KS_ERR_INVALID_ARG;
+  const ks_status_t v = check_cfg(cfg);
+  if (v != KS_OK) return v;
   std::lock_guard<std::mutex> g(plan->p.lock);
   ks_config_t &c = plan->p.cfg;
   c.schedule = cfg->schedule;
@@ -520,6 +587,59 @@ ks_status_t ks_plan_set_config(ks_plan_t plan, const ks_config_t *cfg) {
   if (cfg->batch_mode) c.batch_mode = cfg->batch_mode;
   if (cfg->graph) c.graph = cfg->graph;
   if (cfg->spin_limit) c.spin_limit = cfg->spin_limit;
+  if (cfg->batch_order) c.batch_order = cfg->batch_order;
+  return KS_OK;
+}
+
+ks_status_t ks_oc_work_list(const ks_params_t *p, uint32_t count, const uint32_t *levels, uint32_t *tiles,
+                            uint32_t *seg_start, uint32_t *seg_job, uint32_t *seg_phase, uint32_t *deps,
+                            uint32_t *total) {
+  const ks_status_t v = validate_params(p);
+  if (v != KS_OK) return v;
+  if (!count || !levels || !tiles || !seg_start || !seg_job || !seg_phase || !deps || !total)
+    return KS_ERR_INVALID_ARG;
+  const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum, K = p->num_p ? p->num_p : alpha;
+  for (uint32_t i = 0; i < count; i++) {
+    if (levels[i] >= p->num_q) return KS_ERR_INVALID_ARG;
+    oc_tiles_params(p->log_n, alpha, K, levels[i], 1, tiles + (size_t)i * OC_NPHASE);
+  }
+  std::vector<OcSeg> segs;
+  *total = oc_segments(tiles, count, segs);
+  for (size_t k = 0; k < segs.size(); k++) {
+    seg_start[k] = segs[k].start;
+    seg_job[k] = segs[k].job;
+    seg_phase[k] = segs[k].phase;
+  }
+  for (uint32_t q = 0; q < OC_NPHASE; q++) deps[q] = oc_deps(q);
+  return KS_OK;
+}
+
+ks_status_t ks_plan_set_tuned(ks_plan_t plan, uint32_t level, uint32_t count, const ks_config_t *cfg) {
+  if (!plan || !cfg || !count) return KS_ERR_INVALID_ARG;
+  if (level >= plan->p.num_q || cfg->schedule == KS_SCHED_AUTO) return KS_ERR_INVALID_ARG;
+  const ks_status_t v = check_cfg(cfg);
+  if (v != KS_OK) return v;
+  std::lock_guard<std::mutex> g(plan->p.lock);
+  for (TunedEntry &e : plan->p.tuned)
+    if (e.level == level && e.count == count) {
+      e.cfg = *cfg;
+      return KS_OK;
+    }
+  plan->p.tuned.push_back(TunedEntry{level, count, *cfg});
+  return KS_OK;
+}
+
+ks_status_t ks_plan_clear_tuned(ks_plan_t plan) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(plan->p.lock);
+  plan->p.tuned.clear();
+  return KS_OK;
+}
+
+ks_status_t ks_plan_resolve_config(ks_plan_t plan, uint32_t level, uint32_t count, ks_config_t *out) {
+  if (!plan || !out || !count || level >= plan->p.num_q) return KS_ERR_INVALID_ARG;
+  *out = resolve_cfg(plan->p, level, count, false);
+  if (out->schedule == KS_SCHED_AUTO) out->schedule = KS_SCHED_OC;
   return KS_OK;
 }
 
@@ -533,6 +653,9 @@ ks_status_t ks_plan_get_config(ks_plan_t plan, ks_config_t *cfg) {
 ks_status_t ks_workspace_size(ks_plan_t plan, uint32_t count, const uint32_t *levels, size_t *bytes) {
   if (!plan || !bytes || (count && !levels)) return KS_ERR_INVALID_ARG;
   const Plan &pl = plan->p;
+  uint32_t lmax = 0;
+  for (uint32_t i = 0; i < count; i++) lmax = std::max(lmax, levels[i]);
+  const RunCfgScope scope(resolve_cfg(plan->p, lmax, count, false));
   size_t mx = 0;
   for (uint32_t i = 0; i < count; i++) {
     if (levels[i] >= pl.num_q) return KS_ERR_INVALID_ARG;
@@ -566,9 +689,10 @@ static bool injected_fault() {
 namespace {
 
 ks_status_t keyswitch_one(ks_plan_t plan, const Job &jb, OcRowVariant rows, void *workspace, size_t workspace_bytes,
-                          void *stream) {
+                          void *stream, bool oc_only = false) {
   if (!plan) return KS_ERR_INVALID_ARG;
   const Plan &pl = plan->p;
+  const RunCfgScope scope(resolve_cfg(plan->p, jb.level, 1, oc_only || rows != OC_ROWS_PLAIN));
   const ks_schedule_t sch = effective(pl);
   if (rows != OC_ROWS_PLAIN && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (jb.level >= pl.num_q) return KS_ERR_INVALID_ARG;
@@ -581,11 +705,19 @@ ks_status_t keyswitch_one(ks_plan_t plan, const Job &jb, OcRowVariant rows, void
   return run_one(pl, sch, jb, rows, (uint32_t *)workspace, (hipStream_t)stream);
 }
 
-ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs, OcRowVariant rows, void *workspace,
+ks_status_t keyswitch_batch(ks_plan_t plan, const std::vector<Job> &jobs_in, OcRowVariant rows, void *workspace,
                             size_t workspace_bytes, void *stream) {
-  const uint32_t count = (uint32_t)jobs.size();
+  const uint32_t count = (uint32_t)jobs_in.size();
   Plan &pl = plan->p;
+  uint32_t lmax = 0;
+  for (const Job &j : jobs_in) lmax = std::max(lmax, j.level);
+  const RunCfgScope scope(resolve_cfg(pl, lmax, count, rows != OC_ROWS_PLAIN));
   const ks_schedule_t sch = effective(pl);
+  // batch order (a tuner choice): as given, or by decreasing level; every
+  // job's result is the same either way
+  std::vector<Job> jobs(jobs_in);
+  if (run_cfg(pl).batch_order == 2)
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.level > b.level; });
   if (rows != OC_ROWS_PLAIN && sch != KS_SCHED_OC) return KS_ERR_UNSUPPORTED;
   if (!count) return KS_OK;
   std::vector<uint32_t> levels(count);

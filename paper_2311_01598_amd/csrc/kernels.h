@@ -155,6 +155,19 @@ __host__ __device__ __forceinline__ uint32_t oc_gidx(uint32_t num_q, uint32_t le
 }
 __host__ __device__ __forceinline__ uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+// Phases each phase waits for in the persistent launch (bit q = phase q
+// complete for the same job).
+__host__ __device__ constexpr uint32_t oc_deps(uint32_t phase) {
+  return phase == OC_INTT_COL      ? (1u << OC_INTT_ROW)
+         : phase == OC_UP_P        ? (1u << OC_INTT_COL)
+         : phase == OC_ROW_P       ? (1u << OC_UP_P)
+         : phase == OC_UP_Q        ? (1u << OC_INTT_COL)
+         : phase == OC_INTT_COL_DN ? (1u << OC_ROW_P)
+         : phase == OC_DN          ? (1u << OC_INTT_COL_DN)
+         : phase == OC_ROW_Q       ? ((1u << OC_DN) | (1u << OC_UP_Q))
+                                   : 0u;
+}
+
 // Tile counts of every phase for a job at `level`.
 __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint32_t alpha, uint32_t K,
                                                uint32_t level, uint32_t ttu, uint32_t ttd, uint32_t *n) {
@@ -179,6 +192,12 @@ __host__ __device__ inline void oc_phase_tiles(uint32_t loga, uint32_t cb, uint3
 uint32_t oc_effective_tt(uint32_t loga, uint32_t want, uint32_t l1);
 // Tile counts of every phase (host).
 void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles);
+// The same from the parameters alone (no plan, no device).
+void oc_tiles_params(uint32_t log_n, uint32_t alpha, uint32_t K, uint32_t level, uint32_t tt, uint32_t *tiles);
+// The work list of the persistent batch launch: one segment per (phase,
+// job), phase-major then job-major, each starting where the previous ends.
+// tiles: count x OC_NPHASE tile counts.  Returns the total item count.
+uint32_t oc_segments(const uint32_t *tiles, uint32_t count, std::vector<OcSeg> &segs);
 // One launch per phase; jobs == nullptr runs `one` alone.  rows: the
 // row-stage kernels (plain, compressed keys, or extended); part: which
 // phases run.

@@ -109,7 +109,7 @@ static hipError_t col_dispatch(const Plan &pl, const uint32_t *src, uint32_t *ds
 
 template <bool INV>
 static hipError_t col_by_a(const Plan &pl, const uint32_t *src, uint32_t *dst, const LimbList &L, hipStream_t st) {
-  const uint32_t W = pl.cfg.col_width ? pl.cfg.col_width : 16;
+  const uint32_t W = run_cfg(pl).col_width ? run_cfg(pl).col_width : 16;
   switch (pl.dev.loga) {
     case 4: return col_dispatch<INV, 4>(pl, src, dst, L, W, st);
     case 5: return col_dispatch<INV, 5>(pl, src, dst, L, W, st);
@@ -130,7 +130,7 @@ hipError_t launch_col(const Plan &pl, bool inverse, const uint32_t *src, uint32_
 template <bool INV>
 static hipError_t row_launch(const Plan &pl, const uint32_t *src, uint32_t *dst, const LimbList &L, hipStream_t st) {
   const uint32_t rows = 1u << pl.dev.loga;
-  uint32_t RB = pl.cfg.row_block ? pl.cfg.row_block : 8;
+  uint32_t RB = run_cfg(pl).row_block ? run_cfg(pl).row_block : 8;
   if (RB > rows) RB = rows;
   if (RB >= 16) {
     KS_LAUNCH(pl, INV ? "ntt.row.inv" : "ntt.row.fwd", (k_row<INV, 16>), dim3(rows / 16, L.count), dim3(256), 0, st, pl.dev, src, dst, L);
@@ -532,6 +532,11 @@ static uint32_t col_blocks(uint32_t loga) {
 
 void oc_tiles_host(const Plan &pl, uint32_t level, uint32_t tt, uint32_t *tiles) {
   oc_phase_tiles(pl.dev.loga, col_blocks(pl.dev.loga), pl.alpha, pl.num_p, level, tt, tt, tiles);
+}
+
+void oc_tiles_params(uint32_t log_n, uint32_t alpha, uint32_t K, uint32_t level, uint32_t tt, uint32_t *tiles) {
+  const uint32_t loga = log_n - kRowLog;
+  oc_phase_tiles(loga, col_blocks(loga), alpha, K, level, tt, tt, tiles);
 }
 
 hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count,

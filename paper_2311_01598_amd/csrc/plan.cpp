@@ -317,6 +317,15 @@ hipError_t upload_async(const Plan &pl, void *dst, const void *src, size_t bytes
   return hipEventRecord(slot->done, st);
 }
 
+namespace {
+thread_local const ks_config_t *t_run_cfg = nullptr;
+}
+
+const ks_config_t &run_cfg(const Plan &pl) { return t_run_cfg ? *t_run_cfg : pl.cfg; }
+
+RunCfgScope::RunCfgScope(const ks_config_t &c) : cfg_(c), prev_(t_run_cfg) { t_run_cfg = &cfg_; }
+RunCfgScope::~RunCfgScope() { t_run_cfg = prev_; }
+
 bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t *stop) {
   Trace &t = pl.trace;
   if (!t.on) return false;

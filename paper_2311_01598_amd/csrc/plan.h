@@ -86,6 +86,14 @@ struct Fork {
   hipEvent_t fork = nullptr, join = nullptr;
 };
 
+// One autotuner result: the configuration for calls of `count` key
+// switches whose largest level is `level` (used when the plan's schedule is
+// KS_SCHED_AUTO).
+struct TunedEntry {
+  uint32_t level, count;
+  ks_config_t cfg;
+};
+
 struct Plan {
   uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
   int device = -1;
@@ -94,11 +102,28 @@ struct Plan {
   DevPlan dev{};
   std::vector<void *> allocs;
   ks_config_t cfg{};
-  std::mutex lock;  // guards the graph cache and config
+  std::vector<TunedEntry> tuned;
+  std::mutex lock;  // guards the graph cache, the configuration and the tuned entries
   void *graph_cache = nullptr;
   mutable Trace trace;
   mutable Staging staging;
   mutable Fork fork;
+};
+
+// The configuration the current call runs with: installed by the entry
+// points for the duration of one call on the calling thread (the tuned
+// entry when the plan's schedule is AUTO), the plan's own otherwise.
+const ks_config_t &run_cfg(const Plan &pl);
+class RunCfgScope {
+ public:
+  explicit RunCfgScope(const ks_config_t &c);
+  ~RunCfgScope();
+  RunCfgScope(const RunCfgScope &) = delete;
+  RunCfgScope &operator=(const RunCfgScope &) = delete;
+
+ private:
+  ks_config_t cfg_;
+  const ks_config_t *prev_;
 };
 
 // The plan's side stream and events, created on first use (caller holds

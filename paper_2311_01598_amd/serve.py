@@ -11,6 +11,10 @@
   pool, first-fit) plus output buffers; requests wait while the bytes in
   flight plus theirs would exceed the budget, and a request that could never
   fit is rejected.
+* Launch configuration: each plan's own.  A plan tuned for its batch shapes
+  (tune.Tuner) runs with schedule AUTO, so every batch takes the autotuner's
+  choice for its largest level and size; an untuned plan runs its starting
+  configuration (OC, two targets per conversion tile).
 * Continuous batching: whenever one of `streams` slots is free, the queued
   requests of one ring degree and kind (key switch with a full or a
   compressed key, or rotation) form a batch: the oldest request, then the
@@ -23,6 +27,7 @@
   key switches per second, bytes in flight high-water mark, queue depth.
 """
 import collections
+import gc
 import time
 
 import numpy as np
@@ -79,19 +84,20 @@ class Request:
 
 
 class Server:
-    def __init__(self, plans, keys, budget_bytes, streams=2, max_batch=16):
+    def __init__(self, plans, keys, budget_bytes, streams=2, max_batch=16, keep_outputs=True):
         """plans: {log_n: Plan}; keys: {log_n: [key]} (resident), a key being
-        a full evk tensor or a compressed key (b-half tensor, a_seed)."""
+        a full evk tensor or a compressed key (b-half tensor, a_seed).
+        keep_outputs=False drops each request's output once it has completed
+        (a long measurement run that only needs the latencies)."""
         import torch
         self.torch = torch
         self.plans, self.keys = plans, keys
-        for p in plans.values():  # OC, two targets per conversion tile: the faster choice for batches
-            p.configure("oc", batch_mode=1, tile_towers=2)
         self.budget = budget_bytes
         self.pool = HbmPool(budget_bytes)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.busy = [None] * streams  # per slot: (event, requests, pool block, bytes)
         self.max_batch = max_batch
+        self.keep_outputs = keep_outputs
         self.queue = collections.deque()
         self.in_flight = 0
         self.high_water = 0
@@ -204,6 +210,8 @@ class Server:
                 for r in batch:
                     r.t_done = t
                     r.status = "done"
+                    if not self.keep_outputs:
+                        r.out = None
                     self.done.append(r)
                 self.pool.release(*blk)
                 self.in_flight -= need
@@ -223,24 +231,36 @@ class Server:
     def idle(self):
         return not self.queue and all(b is None for b in self.busy)
 
-    def run(self, arrivals, max_seconds=600.0):
+    def run(self, arrivals, max_seconds=600.0, pause_gc=True):
         """arrivals: list of (t_offset_s, Request) sorted by time; drives the
-        loop in real time until every request has finished."""
-        t0 = time.perf_counter()
-        i = 0
-        while i < len(arrivals) or not self.idle():
-            now = time.perf_counter() - t0
-            while i < len(arrivals) and arrivals[i][0] <= now:
-                r = arrivals[i][1]
-                r.t_arrive = t0 + arrivals[i][0]
-                self.submit(r)
-                i += 1
-            if not self.step():
-                time.sleep(20e-6)
-            if now > max_seconds:
-                raise TimeoutError("serving loop exceeded its time limit")
-        self.torch.cuda.synchronize()
-        return self.stats(time.perf_counter() - t0)
+        loop in real time until every request has finished.  pause_gc: the
+        loop allocates many short-lived objects, and a full cyclic garbage
+        collection in the middle of it stalls every request in flight, so
+        it collects once before and suspends the cyclic collector until the
+        run ends (reference counting still frees everything)."""
+        was_enabled = gc.isenabled()
+        if pause_gc:
+            gc.collect()
+            gc.disable()
+        try:
+            t0 = time.perf_counter()
+            i = 0
+            while i < len(arrivals) or not self.idle():
+                now = time.perf_counter() - t0
+                while i < len(arrivals) and arrivals[i][0] <= now:
+                    r = arrivals[i][1]
+                    r.t_arrive = t0 + arrivals[i][0]
+                    self.submit(r)
+                    i += 1
+                if not self.step():
+                    time.sleep(20e-6)
+                if now > max_seconds:
+                    raise TimeoutError("serving loop exceeded its time limit")
+            self.torch.cuda.synchronize()
+            return self.stats(time.perf_counter() - t0)
+        finally:
+            if pause_gc and was_enabled:
+                gc.enable()
 
     def stats(self, wall):
         lat = np.array([r.t_done - r.t_arrive for r in self.done]) * 1e3

@@ -36,3 +36,15 @@ def batch_levels(count, towers_lo, towers_hi, seed):
     """Levels l with l+1 uniform in [towers_lo, towers_hi]."""
     rng = np.random.default_rng(seed)
     return [int(t) - 1 for t in rng.integers(towers_lo, towers_hi + 1, count)]
+
+
+def uniform_limbs_device(moduli, n, seed, torch, lead=()):
+    """[*lead][len(moduli)][n] int32 tensor on the current GPU: limb r uniform
+    in [0, moduli[r]) (the same uint32 bits), drawn with torch's seeded device
+    generator as the residue of a uniform 62-bit integer (bias below 2^-32).
+    For large timing inputs (resident serving keys and request buffers)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    m = torch.tensor([int(x) for x in moduli], dtype=torch.int64, device="cuda").view(*([1] * len(lead)), -1, 1)
+    x = torch.randint(0, 1 << 62, (*lead, len(moduli), n), dtype=torch.int64, device="cuda", generator=g)
+    return (x % m).to(torch.int32)

@@ -50,3 +50,10 @@ def test_source_digest_ignores_comments_not_code(tmp_path):
     assert bench.kernel_source_digest(str(a)) == base
     f.write_text(text.replace("constexpr int kPad = 272;", "constexpr int kPad = 276;", 1))
     assert bench.kernel_source_digest(str(a)) != base
+
+
+def test_batch_bytes_count_the_shared_key_once():
+    n = 1 << 16
+    # 16 key switches sharing one key: 16 x (6 MiB in + 12 MiB out) + one 48 MiB key
+    assert bench.batch_alg_bytes(n, 24, 8, 3, 16) == 16 * (18 << 20) + (48 << 20)
+    assert bench.batch_alg_bytes(n, 24, 8, 3, 1) == bench.alg_bytes(n, 24, 8, 3)
