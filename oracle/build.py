@@ -8,7 +8,7 @@ LIB = os.path.join(HERE, "libks_oracle.so")
 
 def build(verbose=False):
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-           os.path.join(HERE, "ks_oracle.c"), "-o", LIB + ".tmp", "-lm"]
+           os.path.join(HERE, "ks_oracle.c"), os.path.join(HERE, "ks_oracle64.c"), "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -25,8 +25,8 @@ def lib():
     """Load (building once if absent) the oracle shared library."""
     global _lib
     if _lib is None:
-        src = os.path.join(os.path.dirname(LIB), "ks_oracle.c")
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src):
+        srcs = [os.path.join(os.path.dirname(LIB), f) for f in ("ks_oracle.c", "ks_oracle64.c", "ks_oracle.h")]
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in srcs):
             build()
         L = ctypes.CDLL(LIB)
         P = ctypes.POINTER(_Params)

@@ -135,6 +135,28 @@ void oracle_set_fault(int fault);
 /* Evaluation-key size in words for a parameter set (Sec. III-B P4 shape). */
 uint64_t oracle_evk_words(uint32_t log_n, uint32_t num_q, uint32_t num_p, uint32_t dnum);
 
+/* ---- 64-bit words (ks_oracle64.c): towers of ~60-bit primes in uint64
+ * words, every product an exact unsigned __int128 reduced with '%'.  Same
+ * layouts and conventions as above with uint64 residues; moduli
+ * 2^60 - t*2N + 1; psi the smallest x with x^N = -1 (mod q). */
+int oracle64_is_prime(uint64_t n);               /* Miller-Rabin, 12 prime bases */
+int oracle64_gen_primes(uint32_t log_n, uint32_t count, uint64_t *out);
+int oracle64_moduli(const oracle_params *p, uint64_t *out);
+uint64_t oracle64_min_psi(uint64_t q, uint32_t log_n);
+uint64_t oracle64_powmod(uint64_t b, uint64_t e, uint64_t q);
+uint64_t oracle64_invmod(uint64_t a, uint64_t q);
+void oracle64_ntt_direct(const uint64_t *a, uint64_t *out, uint32_t log_n, uint64_t q, uint64_t psi);
+void oracle64_ntt(uint64_t *a, uint32_t log_n, uint64_t q, uint64_t psi);
+void oracle64_intt(uint64_t *a, uint32_t log_n, uint64_t q, uint64_t psi);
+void oracle64_negacyclic_mul(const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t log_n, uint64_t q);
+void oracle64_bconv(const uint64_t *x, const uint64_t *src, uint32_t ns, uint64_t *y, const uint64_t *dst,
+                    uint32_t nt, uint32_t n);
+int oracle64_keyswitch(const oracle_params *p, const uint64_t *moduli, uint32_t level, const uint64_t *evk,
+                       const uint64_t *d, uint64_t *out);
+int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t seed, int8_t *s, int8_t *s2,
+                    uint64_t *evk);
+void oracle64_set_fault(int fault);
+
 #ifdef __cplusplus
 }
 #endif
