@@ -178,6 +178,26 @@ ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level,
                          const uint32_t *in, uint32_t *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ks_keyswitch without a workspace argument.  The intermediates live in a
+ * fixed device array of KS_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends (looked up when a plan is
+ * created on that GPU).  Runs the Output-Centric order (the plan's schedule
+ * must be OC or AUTO, else KS_ERR_UNSUPPORTED), and its output equals
+ * ks_keyswitch's under OC.  A call whose OC workspace (ks_workspace_size of
+ * the one level under OC) exceeds KS_NOALLOC_SCRATCH_BYTES returns
+ * KS_ERR_BUDGET before enqueuing anything; with kernel tracing on it returns
+ * KS_ERR_UNSUPPORTED (tracing creates events).  The call allocates nothing:
+ * no hipMalloc, hipFree or other allocating routine.  Every call on one GPU
+ * uses that GPU's one array, which keeps the last call's contents (every
+ * word a call reads from it was written earlier by the same call): calls
+ * that overlap on one GPU (other streams, other host threads) race and must
+ * be serialised by the caller.  in/out/evk rules as for ks_keyswitch. */
+#define KS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ks_status_t ks_keyswitch_noalloc(ks_plan_t plan, const uint32_t *evk, uint32_t level,
+                                 const uint32_t *in, uint32_t *out, void *stream);
+
 /* Many key switches at mixed levels (jobs is a host array of `count`
  * entries; the key may differ per job).  Each job's output equals
  * ks_keyswitch of that job alone.  Outputs must not overlap each other, any

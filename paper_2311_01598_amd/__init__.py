@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libks.so")
 
 KS_OK, KS_ERR_INVALID_ARG, KS_ERR_UNSUPPORTED, KS_ERR_NOMEM, KS_ERR_BUDGET, KS_ERR_DEVICE = range(6)
 KS_SCHED_AUTO, KS_SCHED_MP, KS_SCHED_DC, KS_SCHED_OC = range(4)
+# size of the library's fixed per-GPU array behind ks_keyswitch_noalloc (ks.h)
+KS_NOALLOC_SCRATCH_BYTES = 64 << 20
 SCHEDULES = {"auto": KS_SCHED_AUTO, "mp": KS_SCHED_MP, "dc": KS_SCHED_DC, "oc": KS_SCHED_OC}
 
 
@@ -82,6 +84,7 @@ _SIGS = {
     "ks_plan_resolve_config": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ks_config_t)]),
     "ks_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.POINTER(ctypes.c_size_t)]),
     "ks_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "ks_keyswitch_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
     "ks_keyswitch_batch": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ks_job_t), _VP, ctypes.c_size_t,
                                           _VP]),
     "ks_keyswitch_seeded": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP,
@@ -271,6 +274,11 @@ def ks_keyswitch(plan, evk, level, inp, out, workspace, workspace_bytes=None, st
     st = _lib.ks_keyswitch(plan, _ptr(evk), int(level), _ptr(inp), _ptr(out), _ptr(workspace),
                            int(workspace_bytes), _stream(stream))
     _check(st, "ks_keyswitch")
+
+
+def ks_keyswitch_noalloc(plan, evk, level, inp, out, stream=None):
+    st = _lib.ks_keyswitch_noalloc(plan, _ptr(evk), int(level), _ptr(inp), _ptr(out), _stream(stream))
+    _check(st, "ks_keyswitch_noalloc")
 
 
 def ks_keyswitch_batch(plan, jobs, workspace, workspace_bytes=None, stream=None):

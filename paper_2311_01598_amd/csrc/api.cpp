@@ -533,6 +533,9 @@ ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out) {
     delete pl;
     return st;
   }
+  // set-up of ks_keyswitch_noalloc on this device (the plan's, current
+  // here); a failure only makes that entry point return KS_ERR_DEVICE
+  (void)noalloc_scratch_init(pl->p.device);
   *out = pl;
   return KS_OK;
 }
@@ -777,6 +780,21 @@ extern "C" {
 ks_status_t ks_keyswitch(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in, uint32_t *out,
                          void *workspace, size_t workspace_bytes, void *stream) {
   return keyswitch_one(plan, Job{evk, 0, level, in, out}, OC_ROWS_PLAIN, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks_keyswitch_noalloc(ks_plan_t plan, const uint32_t *evk, uint32_t level, const uint32_t *in,
+                                 uint32_t *out, void *stream) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  const Plan &pl = plan->p;
+  if (pl.cfg.schedule != KS_SCHED_OC && pl.cfg.schedule != KS_SCHED_AUTO) return KS_ERR_UNSUPPORTED;
+  if (pl.trace.on) return KS_ERR_UNSUPPORTED;
+  if (level >= pl.num_q) return KS_ERR_INVALID_ARG;
+  if (ws_limbs(pl, KS_SCHED_OC, level) * limb_bytes(pl) > KS_NOALLOC_SCRATCH_BYTES) return KS_ERR_BUDGET;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl.device) return KS_ERR_INVALID_ARG;
+  void *ws = noalloc_scratch(dev);
+  if (!ws) return KS_ERR_DEVICE;
+  return keyswitch_one(plan, Job{evk, 0, level, in, out}, OC_ROWS_PLAIN, ws, KS_NOALLOC_SCRATCH_BYTES, stream, true);
 }
 
 ks_status_t ks_keyswitch_seeded(ks_plan_t plan, const uint32_t *evk_b, uint64_t a_seed, uint32_t level,

@@ -208,6 +208,11 @@ hipError_t launch_oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs,
 hipError_t launch_oc_persistent(const Plan &pl, const OcJob *jobs, const OcSeg *segs, uint32_t nsegs,
                                 uint32_t total, uint32_t count, uint32_t *ctl, uint32_t spin_limit, hipStream_t st);
 
+// The fixed device scratch of ks_keyswitch_noalloc (noalloc.hip): looked up
+// once per device with that device current (plan creation), then read.
+hipError_t noalloc_scratch_init(int dev);
+void *noalloc_scratch(int dev);  // nullptr until set up on `dev`
+
 template <int A>
 hipError_t oc_phases(const Plan &pl, const OcJob &one, const OcJob *jobs, uint32_t count, const uint32_t *max_tiles,
                      uint32_t tt, OcRowVariant rows, OcPart part, hipStream_t st);
