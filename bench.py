@@ -432,9 +432,21 @@ def bts_rate(ks, steps, np, torch, synth):
         ms = a.elapsed_time(b) / steps
         cur["oc_compressed_keys"] = {"ks_per_s": round(1e3 / ms, 1), "us_per_ks": round(ms * 1e3, 2)}
         del ws, keys_b
-        res[name] = cur
         del evks
         plan.close()
+        # 64-bit words (~60-bit towers), Max-Parallel order
+        p64 = ks.Plan64(log_n, num_q, dnum, num_p)
+        evk64, d64 = (synth.uniform_words64_device(p64.moduli, p64.n, synth.seed_for(31, 64), torch, lead=(dnum, 2)),
+                      synth.uniform_words64_device(p64.moduli[:num_q], p64.n, synth.seed_for(31, 65), torch))
+        out64 = torch.empty((2, num_q, p64.n), dtype=torch.int64, device="cuda")
+        ws64 = p64.workspace(level)
+        s64 = timed_calls(lambda r=0: p64.keyswitch(evk64, level, d64, out=out64, workspace=ws64), max(5, steps // 4),
+                          torch)
+        cur["mp_64bit_words"] = {"ks_per_s": round(1 / s64, 1), "us_per_ks": round(s64 * 1e6, 2),
+                                 "evk_mib": round(evk64.numel() * 8 / 2**20, 1)}
+        del evk64, d64, out64, ws64
+        p64.close()
+        res[name] = cur
     return res
 
 

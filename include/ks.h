@@ -435,6 +435,51 @@ ks_status_t ks_mlp_adam(uint32_t n, float *params, const float *grads, float *m,
 
 const char *ks_status_string(ks_status_t s);
 
+/* ------------------------------------------------------------------------
+ * 64-bit words.  The same key switch (Sec. III) on towers of ~60-bit primes
+ * held in uint64 words: Sec. II's word-size moduli (36 to 64 bits), the word
+ * size Table III's evk sizes count.  Moduli: primes 2^59 < m < 2^60 with
+ * m = 1 mod 2N; by default 2^60 - t*2N + 1, t = 1, 2, ..., the first K
+ * becoming p_0..p_{K-1} and the next L+1 q_0..q_L.  psi is the smallest x
+ * with x^N = -1 (mod m); the evaluation domain, evk layout, digits and
+ * output conventions are those above, with uint64 residues.  Runs the
+ * Max-Parallel order (Sec. IV-A): every stage over all towers, each stage's
+ * output in the workspace.  Parameter limits as for ks_params_t.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint32_t log_n;
+  uint32_t num_q;
+  uint32_t dnum;
+  uint32_t num_p;
+  const uint64_t *moduli; /* optional host array [num_q + num_p]; validated */
+} ks64_params_t;
+
+typedef struct ks64_plan *ks64_plan_t;
+
+/* Host only: the moduli of these parameters, host_out [num_q + num_p]. */
+ks_status_t ks64_params_moduli(const ks64_params_t *p, uint64_t *host_out);
+/* Host only: psi for q at ring degree 2^log_n, or 0 if q is not a prime
+ * = 1 mod 2N. */
+uint64_t ks64_root_of_unity(uint64_t q, uint32_t log_n);
+/* Plan on the current device (twiddles, conversion and ModDown tables). */
+ks_status_t ks64_plan_create(const ks64_params_t *p, ks64_plan_t *out);
+ks_status_t ks64_plan_destroy(ks64_plan_t plan);
+ks_status_t ks64_plan_moduli(ks64_plan_t plan, uint64_t *host_out);
+/* Workspace bytes of one key switch at `level`:
+ * 8 N (l+1 + d'(l+1+K) + 2(l+1+K) + 2K + 2(l+1)). */
+ks_status_t ks64_workspace_size(ks64_plan_t plan, uint32_t level, size_t *bytes);
+/* Key switch: in [level+1][N], out [2][level+1][N], evk [dnum][2][L+1+K][N]
+ * (device, uint64, 16-byte aligned; workspace 256-byte aligned, at least
+ * ks64_workspace_size bytes; out overlaps none of in, evk, workspace).
+ * Output canonical, evaluation domain. */
+ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level, const uint64_t *in,
+                           uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
+/* In-place forward (inverse = 0) or inverse NTT of `count` limbs of data
+ * [count][N]; limb c uses modulus number g[c] (host array, order q_0..q_L,
+ * p_0..p_{K-1}). */
+ks_status_t ks64_ntt(ks64_plan_t plan, uint32_t count, const uint32_t *g, int inverse, uint64_t *data,
+                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

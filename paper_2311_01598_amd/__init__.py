@@ -602,3 +602,120 @@ class Plan:
         except Exception:
             pass
 
+
+# ---------------------------------------------------------------- 64-bit words
+class ks64_params_t(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("num_q", ctypes.c_uint32), ("dnum", ctypes.c_uint32),
+                ("num_p", ctypes.c_uint32), ("moduli", ctypes.POINTER(ctypes.c_uint64))]
+
+
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_SIGS64 = {
+    "ks64_params_moduli": (ctypes.c_int, [ctypes.POINTER(ks64_params_t), _U64P]),
+    "ks64_root_of_unity": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint32]),
+    "ks64_plan_create": (ctypes.c_int, [ctypes.POINTER(ks64_params_t), ctypes.POINTER(_VP)]),
+    "ks64_plan_destroy": (ctypes.c_int, [_VP]),
+    "ks64_plan_moduli": (ctypes.c_int, [_VP, _U64P]),
+    "ks64_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ks64_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "ks64_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
+}
+for _name, (_res, _args) in _SIGS64.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+EXPORTS = EXPORTS + tuple(_SIGS64)
+
+
+def _params64(log_n, num_q, dnum, num_p=0, moduli=None):
+    p = ks64_params_t(log_n, num_q, dnum, num_p, None)
+    keep = None
+    if moduli is not None:
+        keep = (ctypes.c_uint64 * len(moduli))(*[int(m) for m in moduli])
+        p.moduli = ctypes.cast(keep, _U64P)
+    return p, keep
+
+
+def ks64_params_moduli(log_n, num_q, dnum, num_p=0, moduli=None):
+    p, keep = _params64(log_n, num_q, dnum, num_p, moduli)
+    alpha = -(-num_q // dnum)
+    out = (ctypes.c_uint64 * (num_q + (num_p or alpha)))()
+    _check(_lib.ks64_params_moduli(ctypes.byref(p), out), "ks64_params_moduli")
+    return list(out)
+
+
+def ks64_root_of_unity(q, log_n):
+    return int(_lib.ks64_root_of_unity(int(q), int(log_n)))
+
+
+def ks64_plan_create(log_n, num_q, dnum, num_p=0, moduli=None):
+    p, keep = _params64(log_n, num_q, dnum, num_p, moduli)
+    h = _VP()
+    _check(_lib.ks64_plan_create(ctypes.byref(p), ctypes.byref(h)), "ks64_plan_create")
+    return h.value
+
+
+def ks64_plan_destroy(plan):
+    _check(_lib.ks64_plan_destroy(plan), "ks64_plan_destroy")
+
+
+def ks64_workspace_size(plan, level):
+    b = ctypes.c_size_t()
+    _check(_lib.ks64_workspace_size(plan, int(level), ctypes.byref(b)), "ks64_workspace_size")
+    return b.value
+
+
+def ks64_keyswitch(plan, evk, level, inp, out, workspace, workspace_bytes=None, stream=None):
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    st = _lib.ks64_keyswitch(plan, _ptr(evk), int(level), _ptr(inp), _ptr(out), _ptr(workspace),
+                             int(workspace_bytes), _stream(stream))
+    _check(st, "ks64_keyswitch")
+
+
+def ks64_ntt(plan, g, inverse, data, stream=None):
+    g = list(g)
+    arr = (ctypes.c_uint32 * max(1, len(g)))(*g)
+    _check(_lib.ks64_ntt(plan, len(g), arr, 1 if inverse else 0, _ptr(data), _stream(stream)), "ks64_ntt")
+
+
+class Plan64:
+    """A 64-bit-word key-switching plan on the current device (uint64
+    residues travel in torch.int64 tensors, same bits)."""
+
+    def __init__(self, log_n, num_q, dnum, num_p=0, moduli=None):
+        self.log_n, self.num_q, self.dnum = log_n, num_q, dnum
+        self.alpha = -(-num_q // dnum)
+        self.num_p = num_p or self.alpha
+        self.n = 1 << log_n
+        self.handle = ks64_plan_create(log_n, num_q, dnum, num_p, moduli)
+        out = (ctypes.c_uint64 * (num_q + self.num_p))()
+        _check(_lib.ks64_plan_moduli(self.handle, out), "ks64_plan_moduli")
+        self.moduli = list(out)
+
+    def workspace(self, level, device="cuda"):
+        import torch
+        return torch.empty((ks64_workspace_size(self.handle, level) + 7) // 8, dtype=torch.int64, device=device)
+
+    def keyswitch(self, evk, level, d, out=None, workspace=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int64, device=d.device)
+        if workspace is None:
+            workspace = self.workspace(level, d.device)
+        ks64_keyswitch(self.handle, evk, level, d, out, workspace, stream=stream)
+        return out
+
+    def ntt(self, data, g, inverse=False, stream=None):
+        ks64_ntt(self.handle, g, inverse, data, stream)
+
+    def close(self):
+        if self.handle:
+            ks64_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

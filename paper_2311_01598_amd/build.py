@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libks.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "rates.hip", "mlp.hip", "noalloc.hip"] + ["oc_a%d.hip" % a for a in range(4, 10)]
+SOURCES = ["numtheory.cpp", "plan.cpp", "api.cpp", "kernels.hip", "rates.hip", "mlp.hip", "noalloc.hip", "ks64.hip"] + ["oc_a%d.hip" % a for a in range(4, 10)]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]

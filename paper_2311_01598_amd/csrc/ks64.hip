@@ -1,0 +1,655 @@
+// ks64.hip -- hybrid key switching with 64-bit words: towers of ~60-bit
+// primes (Sec. II word-size moduli, 36-64 bits; Table III's evk sizes count
+// 8-byte words), the Max-Parallel order of Sec. IV-A: every stage over all
+// towers, each stage's output in device memory.
+//
+// Arithmetic on uint64 residues below 2^60:
+//  - products with a constant (twiddles, conversion prescales, P^-1, N^-1):
+//    Shoup's method with the precomputed floor(w 2^64 / q), one 64-bit
+//    high product and two low products, result in [0, 2q) then one
+//    conditional subtraction;
+//  - sums of products (conversion, key multiply-accumulate): exact 128-bit
+//    accumulation of at most 16 products of canonical residues (each below
+//    2^60 m, so the sum stays below m 2^64), then one Montgomery reduction
+//    REDC(T) = (T + ((T mod 2^64)(-m^-1) mod 2^64) m) / 2^64 < 2m.  The
+//    2^-64 it leaves is cancelled by constants kept in Montgomery form
+//    (c 2^64 mod m), or by one Shoup product with 2^64 mod m.
+//  - every stage leaves canonical residues.
+// The forward transform is the Cooley-Tukey network that lists a(psi^(2
+// brv(j)+1)) at position j; the inverse is the Gentleman-Sande network and
+// N^-1.  A transform of N = R x 256 words is a column pass (stages with
+// butterfly distance >= 256) and a row pass (distance < 256), each staged
+// through LDS.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "ks.h"
+#include "numtheory.h"
+
+namespace ks64 {
+
+typedef unsigned __int128 u128;
+
+constexpr uint32_t kMaxTowers = 128;
+constexpr uint32_t kList = 96;  // towers per transform launch
+constexpr uint32_t kRowWords = 256;
+constexpr uint32_t kRowsPerTile = 4;
+constexpr uint32_t kColsPerTile = 8;
+
+struct Mod64 {
+  uint64_t q, qneg;   // modulus, -q^-1 mod 2^64
+  uint64_t r64, r64s; // 2^64 mod q and its Shoup companion
+  uint64_t ninv, ninvs;
+};
+
+// Device view of a plan.
+struct Dev64 {
+  uint32_t log_n, num_q, num_p, dnum, alpha, ntot;
+  const Mod64 *mods;      // [ntot], order q_0..q_L, p_0..p_{K-1}
+  const uint4 *tw_fwd;    // [ntot][N]: (w, w') as two little-endian uint64 per entry
+  const uint4 *tw_inv;
+  const uint64_t *up_pre; // [num_q][dnum][alpha][2]: [q^_{j,s}^-1]_{q_s} and Shoup companion
+  const uint64_t *up_cst; // [num_q][dnum][alpha][ntot]: [q^_{j,s}]_{m_g} 2^64 mod m_g
+  const uint64_t *dn_pre; // [K][2]: [p^_k^-1]_{p_k} and companion
+  const uint64_t *dn_cst; // [K][num_q]: [p^_k]_{q_i} 2^64 mod q_i
+  const uint64_t *pinv;   // [num_q][2]: [P^-1]_{q_i} and companion
+};
+
+struct List64 {
+  uint32_t count;
+  uint32_t src[kList];
+  uint32_t dst[kList];
+  uint16_t g[kList];
+};
+
+// ------------------------------------------------------------ arithmetic
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
+__device__ __forceinline__ uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+__device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+// a < 2^64, w < q < 2^62, ws = floor(w 2^64 / q): a w mod q, canonical
+__device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
+  const uint64_t h = __umul64hi(a, ws);
+  return csub(a * w - h * q, q);
+}
+struct Acc128 {
+  uint64_t lo = 0, hi = 0;
+  __device__ __forceinline__ void mac(uint64_t a, uint64_t b) {
+    const uint64_t l = a * b;
+    lo += l;
+    hi += __umul64hi(a, b) + (lo < l ? 1u : 0u);
+  }
+};
+// T < q 2^64: (T + m q) / 2^64 with m = T_lo (-q^-1) mod 2^64, canonical
+__device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
+  const uint64_t u = t.lo * m.qneg;
+  const uint64_t lo = t.lo + u * m.q;  // 0 mod 2^64 by the choice of u
+  return csub(t.hi + __umul64hi(u, m.q) + (lo < t.lo ? 1u : 0u), m.q);
+}
+
+__device__ __forceinline__ uint64_t tw(const uint4 *t, size_t i, uint64_t *comp) {
+  const uint4 v = t[i];
+  *comp = ((uint64_t)v.w << 32) | v.z;
+  return ((uint64_t)v.y << 32) | v.x;
+}
+
+// ------------------------------------------------------------ transforms
+// Row pass: tiles of kRowsPerTile rows of 256 words (a block reads its whole
+// tile before writing it, so src may equal dst).  Forward: stages with
+// butterfly distance t = 128 .. 1 (Cooley-Tukey); inverse: t = 1 .. 128
+// (Gentleman-Sande).  The twiddle of the butterfly (j, j + t) is entry
+// N / (2t) + j / (2t) of the table.
+template <bool INV>
+__global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
+  __shared__ uint64_t s[kRowsPerTile * kRowWords];
+  const uint32_t N = 1u << P.log_n, c = blockIdx.y;
+  const uint32_t g = L.g[c];
+  const Mod64 m = P.mods[g];
+  const uint4 *tab = (INV ? P.tw_inv : P.tw_fwd) + (size_t)g * N;
+  const size_t base = (size_t)blockIdx.x * kRowsPerTile * kRowWords;
+  const uint64_t *in = src + (size_t)L.src[c] * N + base;
+  uint64_t *out = dst + (size_t)L.dst[c] * N + base;
+  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) s[i] = in[i];
+  __syncthreads();
+  const uint32_t row0 = blockIdx.x * kRowsPerTile;
+  for (uint32_t st = 0; st < 8; st++) {
+    const uint32_t t = INV ? (1u << st) : (128u >> st);
+    for (uint32_t b = threadIdx.x; b < kRowsPerTile * 128; b += 256) {
+      const uint32_t rr = b >> 7, k = b & 127;
+      const uint32_t jj = (k / t) * 2 * t + (k % t);
+      const uint32_t j = (row0 + rr) * kRowWords + jj;
+      uint64_t ws;
+      const uint64_t w = tw(tab, N / (2 * t) + j / (2 * t), &ws);
+      uint64_t *a = s + rr * kRowWords + jj;
+      const uint64_t u = a[0], v = a[t];
+      if (!INV) {
+        const uint64_t vw = shoup(v, w, ws, m.q);
+        a[0] = add_mod(u, vw, m.q);
+        a[t] = sub_mod(u, vw, m.q);
+      } else {
+        a[0] = add_mod(u, v, m.q);
+        a[t] = shoup(sub_mod(u, v, m.q), w, ws, m.q);
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) out[i] = s[i];
+}
+
+// Column pass: tiles of kColsPerTile columns of R = N / 256 rows.  Forward:
+// row distance R/2 .. 1 (butterfly distance t = 256 x that); inverse: 1 ..
+// R/2, then N^-1.
+template <bool INV>
+__global__ __launch_bounds__(256) void k_col(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
+  __shared__ uint64_t s[512 * kColsPerTile];
+  const uint32_t N = 1u << P.log_n, R = N / kRowWords, c = blockIdx.y;
+  const uint32_t g = L.g[c];
+  const Mod64 m = P.mods[g];
+  const uint4 *tab = (INV ? P.tw_inv : P.tw_fwd) + (size_t)g * N;
+  const uint32_t col0 = blockIdx.x * kColsPerTile;
+  const uint64_t *in = src + (size_t)L.src[c] * N;
+  uint64_t *out = dst + (size_t)L.dst[c] * N;
+  for (uint32_t i = threadIdx.x; i < R * kColsPerTile; i += 256)
+    s[i] = in[(size_t)(i / kColsPerTile) * kRowWords + col0 + i % kColsPerTile];
+  __syncthreads();
+  const uint32_t a = P.log_n - 8;
+  for (uint32_t st = 0; st < a; st++) {
+    const uint32_t tr = INV ? (1u << st) : ((R >> 1) >> st);
+    for (uint32_t b = threadIdx.x; b < (R / 2) * kColsPerTile; b += 256) {
+      const uint32_t cc = b % kColsPerTile, k = b / kColsPerTile;
+      const uint32_t grp = k / tr, r = grp * 2 * tr + (k % tr);
+      uint64_t ws;
+      const uint64_t w = tw(tab, R / (2 * tr) + grp, &ws);
+      uint64_t *x = s + r * kColsPerTile + cc;
+      const uint64_t u = x[0], v = x[tr * kColsPerTile];
+      if (!INV) {
+        const uint64_t vw = shoup(v, w, ws, m.q);
+        x[0] = add_mod(u, vw, m.q);
+        x[tr * kColsPerTile] = sub_mod(u, vw, m.q);
+      } else {
+        x[0] = add_mod(u, v, m.q);
+        x[tr * kColsPerTile] = shoup(sub_mod(u, v, m.q), w, ws, m.q);
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < R * kColsPerTile; i += 256) {
+    uint64_t v = s[i];
+    if (INV) v = shoup(v, m.ninv, m.ninvs, m.q);
+    out[(size_t)(i / kColsPerTile) * kRowWords + col0 + i % kColsPerTile] = v;
+  }
+}
+
+// ------------------------------------------------------------ ModUp P2
+// Digit j of the input (X, coefficient domain) converted to every tower of
+// D_l outside the digit: y_{j,t} = sum_s [x_s q^_{j,s}^-1]_{q_s} [q^_{j,s}]_{m_t}.
+// grid (N / 256, digits); each thread one coefficient, all targets.
+__device__ __forceinline__ uint32_t gidx(const Dev64 &P, uint32_t level, uint32_t t) {
+  return t <= level ? t : P.num_q + (t - level - 1);
+}
+
+template <int MAXA>
+__global__ __launch_bounds__(256) void k_bconv_up(Dev64 P, uint32_t level, const uint64_t *__restrict__ X,
+                                                  uint64_t *__restrict__ Y) {
+  const uint32_t N = 1u << P.log_n, j = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, l1), ns = hi - lo;
+  const size_t cbase = ((size_t)level * P.dnum + j) * P.alpha;
+  uint64_t xs[MAXA];
+#pragma unroll
+  for (int s = 0; s < MAXA; s++) {
+    if ((uint32_t)s < ns) {
+      const uint64_t *pre = P.up_pre + (cbase + s) * 2;
+      xs[s] = shoup(X[(size_t)(lo + s) * N + c], pre[0], pre[1], P.mods[lo + s].q);
+    }
+  }
+  for (uint32_t t = 0; t < T; t++) {
+    if (t >= lo && t < hi) continue;
+    const uint32_t g = gidx(P, level, t);
+    const Mod64 m = P.mods[g];
+    uint64_t y = 0;
+#pragma unroll
+    for (int c0 = 0; c0 < MAXA; c0 += 16) {
+      if ((uint32_t)c0 < ns) {
+        Acc128 acc;
+#pragma unroll
+        for (int s = c0; s < c0 + 16 && s < MAXA; s++)
+          if ((uint32_t)s < ns) acc.mac(xs[s], P.up_cst[(cbase + s) * P.ntot + g]);
+        y = add_mod(y, redc(acc, m), m.q);
+      }
+    }
+    Y[((size_t)j * T + t) * N + c] = y;
+  }
+}
+
+// ------------------------------------------------------------ ModUp P4/P5
+// acc_s[t] = sum_j yhat_{j,t} evk[j][s][t] over the live digits, where
+// yhat_{j,t} is the input tower itself when t is one of digit j's own
+// towers (Sec. IV-C bypass: NTT(INTT(d_t)) = d_t).  grid (N / 256, T, 2).
+__global__ __launch_bounds__(256) void k_keymac(Dev64 P, uint32_t level, const uint64_t *__restrict__ d,
+                                                const uint64_t *__restrict__ Y, const uint64_t *__restrict__ evk,
+                                                uint64_t *__restrict__ acc) {
+  const uint32_t N = 1u << P.log_n, t = blockIdx.y, s = blockIdx.z, l1 = level + 1, T = l1 + P.num_p;
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t g = gidx(P, level, t), D = (l1 + P.alpha - 1) / P.alpha;
+  const Mod64 m = P.mods[g];
+  Acc128 a;
+  for (uint32_t j = 0; j < D; j++) {
+    const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, l1);
+    const uint64_t y = (t >= lo && t < hi) ? d[(size_t)t * N + c] : Y[((size_t)j * T + t) * N + c];
+    a.mac(y, evk[(((size_t)j * 2 + s) * P.ntot + g) * N + c]);
+  }
+  acc[((size_t)s * T + t) * N + c] = shoup(redc(a, m), m.r64, m.r64s, m.q);
+}
+
+// ------------------------------------------------------------ ModDown P2
+// w_{s,i} = sum_k [a_{s,k} p^_k^-1]_{p_k} [p^_k]_{q_i}, i <= level.
+// grid (N / 256, 2).
+template <int MAXK>
+__global__ __launch_bounds__(256) void k_bconv_down(Dev64 P, uint32_t level, const uint64_t *__restrict__ XP,
+                                                    uint64_t *__restrict__ W) {
+  const uint32_t N = 1u << P.log_n, s = blockIdx.y, K = P.num_p, l1 = level + 1;
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  uint64_t xs[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; k++)
+    if ((uint32_t)k < K)
+      xs[k] = shoup(XP[((size_t)s * K + k) * N + c], P.dn_pre[2 * k], P.dn_pre[2 * k + 1], P.mods[P.num_q + k].q);
+  for (uint32_t i = 0; i < l1; i++) {
+    const Mod64 m = P.mods[i];
+    uint64_t w = 0;
+#pragma unroll
+    for (int c0 = 0; c0 < MAXK; c0 += 16) {
+      if ((uint32_t)c0 < K) {
+        Acc128 acc;
+#pragma unroll
+        for (int k = c0; k < c0 + 16 && k < MAXK; k++)
+          if ((uint32_t)k < K) acc.mac(xs[k], P.dn_cst[(size_t)k * P.num_q + i]);
+        w = add_mod(w, redc(acc, m), m.q);
+      }
+    }
+    W[((size_t)s * l1 + i) * N + c] = w;
+  }
+}
+
+// ------------------------------------------------------------ ModDown P4
+// out_s[i] = (acc_s[i] - what_s[i]) [P^-1]_{q_i}.  grid (N / 256, l+1, 2).
+__global__ __launch_bounds__(256) void k_moddown_final(Dev64 P, uint32_t level, const uint64_t *__restrict__ acc,
+                                                       const uint64_t *__restrict__ W, uint64_t *__restrict__ out) {
+  const uint32_t N = 1u << P.log_n, i = blockIdx.y, s = blockIdx.z, l1 = level + 1, T = l1 + P.num_p;
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const Mod64 m = P.mods[i];
+  const uint64_t v = sub_mod(acc[((size_t)s * T + i) * N + c], W[((size_t)s * l1 + i) * N + c], m.q);
+  out[((size_t)s * l1 + i) * N + c] = shoup(v, P.pinv[2 * i], P.pinv[2 * i + 1], m.q);
+}
+
+// ------------------------------------------------------------ host side
+namespace {
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return ks::mulmod64(a, b, q); }
+uint64_t invmod(uint64_t a, uint64_t q) { return ks::invmod64(a, q); }
+uint64_t shoup_of(uint64_t w, uint64_t q) { return ks::shoup64(w, q); }
+uint64_t mont_of(uint64_t w, uint64_t q) { return ks::mont64(w, q); }
+
+uint32_t bitrev(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+ks_status_t default_moduli(uint32_t log_n, uint32_t num_q, uint32_t K, uint64_t *out) {
+  std::vector<uint64_t> pr(num_q + K);
+  if (ks::ntt_primes64(log_n, num_q + K, pr.data()) != 0) return KS_ERR_UNSUPPORTED;
+  for (uint32_t i = 0; i < num_q; i++) out[i] = pr[K + i];
+  for (uint32_t k = 0; k < K; k++) out[num_q + k] = pr[k];
+  return KS_OK;
+}
+
+ks_status_t validate(const ks64_params_t *p, uint32_t *K_out) {
+  if (!p) return KS_ERR_INVALID_ARG;
+  if (p->log_n < 12 || p->log_n > 17) return KS_ERR_UNSUPPORTED;
+  if (p->num_q == 0 || p->dnum == 0 || p->dnum > p->num_q) return KS_ERR_INVALID_ARG;
+  const uint32_t alpha = (p->num_q + p->dnum - 1) / p->dnum, K = p->num_p ? p->num_p : alpha;
+  if (p->num_q + K > kMaxTowers || alpha > 32 || K > 32 || p->dnum > 16) return KS_ERR_UNSUPPORTED;
+  if (p->moduli) {
+    const uint64_t two_n = 2ull << p->log_n;
+    for (uint32_t i = 0; i < p->num_q + K; i++) {
+      const uint64_t m = p->moduli[i];
+      if (m <= (1ull << 59) || m >= (1ull << 60) || m % two_n != 1 || !ks::is_prime64(m)) return KS_ERR_INVALID_ARG;
+      for (uint32_t j = 0; j < i; j++)
+        if (p->moduli[j] == m) return KS_ERR_INVALID_ARG;
+    }
+  }
+  *K_out = K;
+  return KS_OK;
+}
+
+}  // namespace
+}  // namespace ks64
+
+using namespace ks64;
+
+struct ks64_plan {
+  uint32_t log_n = 0, n = 0, num_q = 0, num_p = 0, dnum = 0, alpha = 0, ntot = 0;
+  int device = -1;
+  std::vector<uint64_t> mod;
+  Dev64 dev{};
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+template <class T>
+ks_status_t upload64(ks64_plan *pl, const std::vector<T> &h, const T **dst) {
+  void *p = nullptr;
+  const size_t bytes = std::max<size_t>(h.size() * sizeof(T), 256);
+  if (hipMalloc(&p, bytes) != hipSuccess) return KS_ERR_NOMEM;
+  pl->allocs.push_back(p);
+  if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return KS_ERR_DEVICE;
+  *dst = (const T *)p;
+  return KS_OK;
+}
+
+ks_status_t build(ks64_plan *pl, const ks64_params_t *p, uint32_t K) {
+  pl->log_n = p->log_n;
+  pl->n = 1u << p->log_n;
+  pl->num_q = p->num_q;
+  pl->num_p = K;
+  pl->dnum = p->dnum;
+  pl->alpha = (p->num_q + p->dnum - 1) / p->dnum;
+  pl->ntot = p->num_q + K;
+  if (hipGetDevice(&pl->device) != hipSuccess) return KS_ERR_DEVICE;
+  pl->mod.resize(pl->ntot);
+  if (p->moduli) std::copy(p->moduli, p->moduli + pl->ntot, pl->mod.begin());
+  else if (default_moduli(p->log_n, p->num_q, K, pl->mod.data()) != KS_OK) return KS_ERR_UNSUPPORTED;
+  const uint32_t N = pl->n, L1 = pl->num_q, T = pl->ntot, A = pl->alpha, D = pl->dnum;
+  std::vector<Mod64> mods(T);
+  std::vector<uint64_t> twf((size_t)T * N * 2), twi((size_t)T * N * 2);
+  for (uint32_t g = 0; g < T; g++) {
+    const uint64_t q = pl->mod[g];
+    uint64_t inv = 1;  // q^-1 mod 2^64 by Newton's iteration
+    for (int i = 0; i < 7; i++) inv *= 2 - q * inv;
+    Mod64 &m = mods[g];
+    m.q = q;
+    m.qneg = (uint64_t)0 - inv;
+    m.r64 = (uint64_t)(((u128)1 << 64) % q);
+    m.r64s = shoup_of(m.r64, q);
+    m.ninv = invmod(N % q, q);
+    m.ninvs = shoup_of(m.ninv, q);
+    const uint64_t psi = ks::min_root64(q, p->log_n), psi_inv = invmod(psi, q);
+    uint64_t pw = 1, pwi = 1;
+    std::vector<uint64_t> pows(N), powsi(N);
+    for (uint32_t i = 0; i < N; i++) {
+      pows[i] = pw;
+      powsi[i] = pwi;
+      pw = mulmod(pw, psi, q);
+      pwi = mulmod(pwi, psi_inv, q);
+    }
+    for (uint32_t k = 0; k < N; k++) {
+      const uint32_t e = bitrev(k, p->log_n);
+      twf[((size_t)g * N + k) * 2] = pows[e];
+      twf[((size_t)g * N + k) * 2 + 1] = shoup_of(pows[e], q);
+      twi[((size_t)g * N + k) * 2] = powsi[e];
+      twi[((size_t)g * N + k) * 2 + 1] = shoup_of(powsi[e], q);
+    }
+  }
+  // ModUp conversion constants per level (the last live digit is partial)
+  std::vector<uint64_t> up_pre((size_t)L1 * D * A * 2, 0), up_cst((size_t)L1 * D * A * T, 0);
+  for (uint32_t lv = 0; lv < L1; lv++)
+    for (uint32_t j = 0; j < D; j++) {
+      const uint32_t lo = j * A;
+      if (lo > lv) break;
+      const uint32_t hi = std::min(lo + A, lv + 1);
+      for (uint32_t s = lo; s < hi; s++) {
+        const size_t ix = ((size_t)lv * D + j) * A + (s - lo);
+        const uint64_t qs = pl->mod[s];
+        uint64_t qhat_s = 1;
+        for (uint32_t u = lo; u < hi; u++)
+          if (u != s) qhat_s = mulmod(qhat_s, pl->mod[u] % qs, qs);
+        up_pre[ix * 2] = invmod(qhat_s, qs);
+        up_pre[ix * 2 + 1] = shoup_of(up_pre[ix * 2], qs);
+        for (uint32_t g = 0; g < T; g++) {
+          const uint64_t mg = pl->mod[g];
+          uint64_t qh = 1;
+          for (uint32_t u = lo; u < hi; u++)
+            if (u != s) qh = mulmod(qh, pl->mod[u] % mg, mg);
+          up_cst[ix * T + g] = mont_of(qh, mg);
+        }
+      }
+    }
+  // ModDown constants
+  std::vector<uint64_t> dn_pre((size_t)K * 2), dn_cst((size_t)K * L1), pinv((size_t)L1 * 2);
+  for (uint32_t k = 0; k < K; k++) {
+    const uint64_t pk = pl->mod[L1 + k];
+    uint64_t ph = 1;
+    for (uint32_t u = 0; u < K; u++)
+      if (u != k) ph = mulmod(ph, pl->mod[L1 + u] % pk, pk);
+    dn_pre[2 * k] = invmod(ph, pk);
+    dn_pre[2 * k + 1] = shoup_of(dn_pre[2 * k], pk);
+    for (uint32_t i = 0; i < L1; i++) {
+      const uint64_t qi = pl->mod[i];
+      uint64_t h = 1;
+      for (uint32_t u = 0; u < K; u++)
+        if (u != k) h = mulmod(h, pl->mod[L1 + u] % qi, qi);
+      dn_cst[(size_t)k * L1 + i] = mont_of(h, qi);
+    }
+  }
+  for (uint32_t i = 0; i < L1; i++) {
+    const uint64_t qi = pl->mod[i];
+    uint64_t P = 1;
+    for (uint32_t k = 0; k < K; k++) P = mulmod(P, pl->mod[L1 + k] % qi, qi);
+    pinv[2 * i] = invmod(P, qi);
+    pinv[2 * i + 1] = shoup_of(pinv[2 * i], qi);
+  }
+  Dev64 &d = pl->dev;
+  d.log_n = pl->log_n;
+  d.num_q = L1;
+  d.num_p = K;
+  d.dnum = D;
+  d.alpha = A;
+  d.ntot = T;
+  ks_status_t st;
+  if ((st = upload64(pl, mods, &d.mods)) != KS_OK) return st;
+  const uint64_t *tf = nullptr, *ti = nullptr;
+  if ((st = upload64(pl, twf, &tf)) != KS_OK) return st;
+  if ((st = upload64(pl, twi, &ti)) != KS_OK) return st;
+  d.tw_fwd = (const uint4 *)tf;
+  d.tw_inv = (const uint4 *)ti;
+  if ((st = upload64(pl, up_pre, &d.up_pre)) != KS_OK) return st;
+  if ((st = upload64(pl, up_cst, &d.up_cst)) != KS_OK) return st;
+  if ((st = upload64(pl, dn_pre, &d.dn_pre)) != KS_OK) return st;
+  if ((st = upload64(pl, dn_cst, &d.dn_cst)) != KS_OK) return st;
+  if ((st = upload64(pl, pinv, &d.pinv)) != KS_OK) return st;
+  return KS_OK;
+}
+
+void free_plan(ks64_plan *pl) {
+  for (void *p : pl->allocs) (void)hipFree(p);
+  pl->allocs.clear();
+}
+
+// One pass direction over a list of towers, split into launches of kList.
+hipError_t transform(const ks64_plan *pl, bool inverse, const uint64_t *src, uint64_t *dst,
+                     const std::vector<uint32_t> &so, const std::vector<uint32_t> &dof,
+                     const std::vector<uint32_t> &g, hipStream_t st) {
+  const uint32_t N = pl->n, R = N / kRowWords;
+  for (size_t b = 0; b < so.size(); b += kList) {
+    List64 L{};
+    L.count = (uint32_t)std::min<size_t>(kList, so.size() - b);
+    for (uint32_t i = 0; i < L.count; i++) {
+      L.src[i] = so[b + i];
+      L.dst[i] = dof[b + i];
+      L.g[i] = (uint16_t)g[b + i];
+    }
+    const dim3 grow(R / kRowsPerTile, L.count), gcol(kRowWords / kColsPerTile, L.count);
+    if (!inverse) {  // column pass (large distances) first, in place into dst
+      hipLaunchKernelGGL(k_col<false>, gcol, dim3(256), 0, st, pl->dev, L, src, dst);
+      List64 L2 = L;
+      for (uint32_t i = 0; i < L.count; i++) L2.src[i] = L.dst[i];
+      hipLaunchKernelGGL(k_row<false>, grow, dim3(256), 0, st, pl->dev, L2, dst, dst);
+    } else {
+      hipLaunchKernelGGL(k_row<true>, grow, dim3(256), 0, st, pl->dev, L, src, dst);
+      List64 L2 = L;
+      for (uint32_t i = 0; i < L.count; i++) L2.src[i] = L.dst[i];
+      hipLaunchKernelGGL(k_col<true>, gcol, dim3(256), 0, st, pl->dev, L2, dst, dst);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t ws_words(const ks64_plan *pl, uint32_t level) {
+  const size_t L1 = level + 1, K = pl->num_p, T = L1 + K, D = (L1 + pl->alpha - 1) / pl->alpha;
+  return (L1 + D * T + 2 * T + 2 * K + 2 * L1) * (size_t)pl->n;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t ks64_root_of_unity(uint64_t q, uint32_t log_n) {
+  if (log_n < 1 || log_n > 20) return 0;
+  return ks::min_root64(q, log_n);
+}
+
+ks_status_t ks64_params_moduli(const ks64_params_t *p, uint64_t *host_out) {
+  uint32_t K = 0;
+  const ks_status_t st = validate(p, &K);
+  if (st != KS_OK) return st;
+  if (!host_out) return KS_ERR_INVALID_ARG;
+  if (p->moduli) {
+    std::copy(p->moduli, p->moduli + p->num_q + K, host_out);
+    return KS_OK;
+  }
+  return default_moduli(p->log_n, p->num_q, K, host_out);
+}
+
+ks_status_t ks64_plan_create(const ks64_params_t *p, ks64_plan_t *out) {
+  if (!out) return KS_ERR_INVALID_ARG;
+  *out = nullptr;
+  uint32_t K = 0;
+  ks_status_t st = validate(p, &K);
+  if (st != KS_OK) return st;
+  ks64_plan *pl = new (std::nothrow) ks64_plan();
+  if (!pl) return KS_ERR_NOMEM;
+  st = build(pl, p, K);
+  if (st != KS_OK) {
+    free_plan(pl);
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return KS_OK;
+}
+
+ks_status_t ks64_plan_destroy(ks64_plan_t plan) {
+  if (!plan) return KS_ERR_INVALID_ARG;
+  free_plan(plan);
+  delete plan;
+  return KS_OK;
+}
+
+ks_status_t ks64_plan_moduli(ks64_plan_t plan, uint64_t *host_out) {
+  if (!plan || !host_out) return KS_ERR_INVALID_ARG;
+  std::copy(plan->mod.begin(), plan->mod.end(), host_out);
+  return KS_OK;
+}
+
+ks_status_t ks64_workspace_size(ks64_plan_t plan, uint32_t level, size_t *bytes) {
+  if (!plan || !bytes || level >= plan->num_q) return KS_ERR_INVALID_ARG;
+  *bytes = ws_words(plan, level) * sizeof(uint64_t);
+  return KS_OK;
+}
+
+ks_status_t ks64_ntt(ks64_plan_t plan, uint32_t count, const uint32_t *g, int inverse, uint64_t *data,
+                     void *stream) {
+  if (!plan || (count && (!g || !data))) return KS_ERR_INVALID_ARG;
+  if ((uintptr_t)data & 15) return KS_ERR_INVALID_ARG;
+  std::vector<uint32_t> so(count), gg(count);
+  for (uint32_t i = 0; i < count; i++) {
+    if (g[i] >= plan->ntot) return KS_ERR_INVALID_ARG;
+    so[i] = i;
+    gg[i] = g[i];
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return KS_ERR_INVALID_ARG;
+  return transform(plan, inverse != 0, data, data, so, so, gg, (hipStream_t)stream) == hipSuccess ? KS_OK
+                                                                                                     : KS_ERR_DEVICE;
+}
+
+ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level, const uint64_t *in,
+                           uint64_t *out, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plan || !evk || !in || !out || !workspace) return KS_ERR_INVALID_ARG;
+  const ks64_plan *pl = plan;
+  if (level >= pl->num_q) return KS_ERR_INVALID_ARG;
+  if (((uintptr_t)evk | (uintptr_t)in | (uintptr_t)out) & 15) return KS_ERR_INVALID_ARG;
+  if ((uintptr_t)workspace & 255) return KS_ERR_INVALID_ARG;
+  const size_t need = ws_words(pl, level) * sizeof(uint64_t);
+  if (workspace_bytes < need) return KS_ERR_BUDGET;
+  const uint32_t N = pl->n, L1 = level + 1, K = pl->num_p, T = L1 + K, D = (L1 + pl->alpha - 1) / pl->alpha;
+  const size_t lb = (size_t)N * sizeof(uint64_t);
+  const size_t evk_b = (size_t)pl->dnum * 2 * pl->ntot * lb;
+  if (overlaps(out, 2 * L1 * lb, in, L1 * lb) || overlaps(out, 2 * L1 * lb, evk, evk_b) ||
+      overlaps(out, 2 * L1 * lb, workspace, workspace_bytes) || overlaps(workspace, workspace_bytes, in, L1 * lb) ||
+      overlaps(workspace, workspace_bytes, evk, evk_b))
+    return KS_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device) return KS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t *X = (uint64_t *)workspace, *Y = X + (size_t)L1 * N, *ACC = Y + (size_t)D * T * N;
+  uint64_t *XP = ACC + (size_t)2 * T * N, *W = XP + (size_t)2 * K * N;
+  const uint32_t blocks = N / 256;
+  std::vector<uint32_t> so, dof, g;
+  // ModUp P1: INTT of every input tower
+  for (uint32_t i = 0; i < L1; i++) { so.push_back(i); dof.push_back(i); g.push_back(i); }
+  if (transform(pl, true, in, X, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
+  // P2: every digit converted to the other towers of D_l
+  if (pl->alpha <= 8) hipLaunchKernelGGL(k_bconv_up<8>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
+  else if (pl->alpha <= 16) hipLaunchKernelGGL(k_bconv_up<16>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
+  else hipLaunchKernelGGL(k_bconv_up<32>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
+  if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
+  // P3: NTT of the converted towers (a digit's own towers are never read from Y)
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t j = 0; j < D; j++) {
+    const uint32_t lo = j * pl->alpha, hi = std::min(lo + pl->alpha, L1);
+    for (uint32_t t = 0; t < T; t++) {
+      if (t >= lo && t < hi) continue;
+      so.push_back(j * T + t); dof.push_back(j * T + t);
+      g.push_back(t <= level ? t : pl->num_q + (t - L1));
+    }
+  }
+  if (transform(pl, false, Y, Y, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
+  // P4/P5: key multiply-accumulate over the digits
+  hipLaunchKernelGGL(k_keymac, dim3(blocks, T, 2), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC);
+  if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
+  // ModDown P1: INTT of the K special towers of both polynomials
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl->num_q + k); }
+  if (transform(pl, true, ACC, XP, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
+  // P2: conversion P -> Q_l
+  if (K <= 8) hipLaunchKernelGGL(k_bconv_down<8>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
+  else if (K <= 16) hipLaunchKernelGGL(k_bconv_down<16>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
+  else hipLaunchKernelGGL(k_bconv_down<32>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
+  if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
+  // P3: NTT; P4: subtract, times P^-1
+  so.clear(); dof.clear(); g.clear();
+  for (uint32_t s = 0; s < 2; s++)
+    for (uint32_t i = 0; i < L1; i++) { so.push_back(s * L1 + i); dof.push_back(s * L1 + i); g.push_back(i); }
+  if (transform(pl, false, W, W, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
+  hipLaunchKernelGGL(k_moddown_final, dim3(blocks, L1, 2), dim3(256), 0, st, pl->dev, level, ACC, W, out);
+  return hipGetLastError() == hipSuccess ? KS_OK : KS_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,11 +1,8 @@
 // plan.cpp -- moduli, roots of unity and precomputed tables of a plan.
 //
 // Derivations used here (all exact integer arithmetic on the host):
-//  * primality: deterministic Miller-Rabin, bases {2, 7, 61} (exact for
-//    n < 4,759,123,141);
-//  * psi: from a generator c of Z_q^* (smallest c with c^((q-1)/f) != 1 for
-//    every prime f | q-1), psi_0 = c^((q-1)/2N) is a primitive 2N-th root;
-//    the primitive 2N-th roots are psi_0^k for odd k, the smallest is kept;
+//  * moduli and psi: numtheory.cpp (deterministic Miller-Rabin; psi from a
+//    generator of Z_q^*, the smallest of the primitive 2N-th roots);
 //  * twiddles: psi^brv(i) and psi^-brv(i) for i < N with Shoup companions;
 //  * basis-conversion constants of ModUp P2 and ModDown P2 (Sec. III-B/C),
 //    with N^-1 of the preceding inverse NTT folded into the per-source
@@ -22,17 +19,6 @@ static inline uint64_t mulm(uint64_t a, uint64_t b, uint64_t m) {
   return (uint64_t)((unsigned __int128)a * b % m);
 }
 
-uint32_t pow_mod(uint64_t b, uint64_t e, uint32_t q) {
-  uint64_t r = 1 % q;
-  b %= q;
-  while (e) {
-    if (e & 1) r = mulm(r, b, q);
-    b = mulm(b, b, q);
-    e >>= 1;
-  }
-  return (uint32_t)r;
-}
-
 static uint32_t inv_mod(uint32_t a, uint32_t q) {  // extended Euclid
   int64_t t = 0, nt = 1, r = q, nr = a % q;
   while (nr) {
@@ -42,61 +28,6 @@ static uint32_t inv_mod(uint32_t a, uint32_t q) {  // extended Euclid
   }
   if (t < 0) t += q;
   return (uint32_t)t;
-}
-
-bool is_prime_u64(uint64_t n) {
-  if (n < 2) return false;
-  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 61ull})
-    if (n % p == 0) return n == p;
-  uint64_t d = n - 1;
-  int s = 0;
-  while (!(d & 1)) { d >>= 1; s++; }
-  for (uint64_t a : {2ull, 7ull, 61ull}) {
-    uint64_t x = 1, b = a % n, e = d;
-    while (e) { if (e & 1) x = mulm(x, b, n); b = mulm(b, b, n); e >>= 1; }
-    if (x == 1 || x == n - 1) continue;
-    bool comp = true;
-    for (int i = 1; i < s; i++) {
-      x = mulm(x, x, n);
-      if (x == n - 1) { comp = false; break; }
-    }
-    if (comp) return false;
-  }
-  return true;
-}
-
-int ntt_primes(uint32_t log_n, uint32_t count, uint32_t *out) {
-  const uint64_t step = 2ull << log_n;
-  uint32_t k = 0;
-  for (uint64_t c = (1ull << 30) + 1 - step; k < count; c -= step) {
-    if (c <= (1ull << 29)) return -1;
-    if (is_prime_u64(c)) out[k++] = (uint32_t)c;
-  }
-  return 0;
-}
-
-uint32_t min_root_2n(uint32_t q, uint32_t log_n) {
-  const uint64_t two_n = 2ull << log_n;
-  if (!is_prime_u64(q) || (q - 1) % two_n) return 0;
-  std::vector<uint32_t> f;
-  uint32_t m = q - 1;
-  for (uint32_t p = 2; (uint64_t)p * p <= m; p++)
-    if (m % p == 0) { f.push_back(p); while (m % p == 0) m /= p; }
-  if (m > 1) f.push_back(m);
-  uint32_t gen = 0;
-  for (uint32_t c = 2; c < q && !gen; c++) {
-    bool ok = true;
-    for (uint32_t p : f) if (pow_mod(c, (q - 1) / p, q) == 1) { ok = false; break; }
-    if (ok) gen = c;
-  }
-  const uint32_t psi0 = pow_mod(gen, (q - 1) / two_n, q);
-  const uint32_t psi0_sq = (uint32_t)mulm(psi0, psi0, q);
-  uint32_t best = psi0, cur = psi0;
-  for (uint64_t k = 1; k < two_n / 2; k++) {  // psi0^(2k+1)
-    cur = (uint32_t)mulm(cur, psi0_sq, q);
-    best = std::min(best, cur);
-  }
-  return best;
 }
 
 static inline uint32_t shoup_of(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }

@@ -15,6 +15,7 @@
 
 #include "../../include/ks.h"
 #include "modarith.h"
+#include "numtheory.h"
 
 namespace ks {
 
@@ -146,11 +147,6 @@ bool trace_pair(const Plan &pl, const char *stage, hipEvent_t *start, hipEvent_t
       hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                    \
   } while (0)
 
-// Number theory used by the plan (independent of any test oracle).
-bool is_prime_u64(uint64_t n);
-int ntt_primes(uint32_t log_n, uint32_t count, uint32_t *out);
-uint32_t min_root_2n(uint32_t q, uint32_t log_n);
-uint32_t pow_mod(uint64_t b, uint64_t e, uint32_t q);
 
 ks_status_t plan_build(const ks_params_t *p, Plan *pl);
 void plan_free(Plan *pl);

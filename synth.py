@@ -48,3 +48,16 @@ def uniform_limbs_device(moduli, n, seed, torch, lead=()):
     m = torch.tensor([int(x) for x in moduli], dtype=torch.int64, device="cuda").view(*([1] * len(lead)), -1, 1)
     x = torch.randint(0, 1 << 62, (*lead, len(moduli), n), dtype=torch.int64, device="cuda", generator=g)
     return (x % m).to(torch.int32)
+
+
+def uniform_words64_device(moduli, n, seed, torch, lead=()):
+    """[*lead][len(moduli)][n] int64 tensor on the current GPU: limb r in
+    [0, moduli[r]) (moduli below 2^62; the same uint64 bits), the residue of
+    a uniform 63-bit integer.  Close to uniform, not exactly (for m near 2^60
+    the low residues are up to m / 2^63 more frequent): timing inputs for
+    64-bit-word plans, whose key switch is data-oblivious."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    m = torch.tensor([int(x) for x in moduli], dtype=torch.int64, device="cuda").view(*([1] * len(lead)), -1, 1)
+    x = torch.randint(0, (1 << 63) - 1, (*lead, len(moduli), n), dtype=torch.int64, device="cuda", generator=g)
+    return x % m

@@ -86,6 +86,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "ks_seeded_job_t": ["evk_b", "a_seed", "level", "in", "out"],
         "ks_config_t": ["schedule", "tile_towers", "batch_mode", "spin_limit", "batch_order"],
         "ks_params_t": ["log_n", "num_q", "dnum", "num_p", "moduli"],
+        "ks64_params_t": ["log_n", "num_q", "dnum", "num_p", "moduli"],
         "ks_rotation_t": ["evk", "galois", "out"],
         "ks_seeded_rotation_t": ["evk_b", "a_seed", "galois", "out"],
         "ks_rotation_term_t": ["evk", "galois", "diag"],
@@ -120,3 +121,19 @@ def test_galois_rotation_matches_oracle():
         for r in (0, 1, 2, 5, -1, -7, (1 << log_n) // 2 - 1):
             assert ks.galois_rotation(log_n, r) == core.galois_rotation(log_n, r)
     assert ks.galois_rotation(12, 1) == 5
+
+
+@pytest.mark.parametrize("shape", [(12, 4, 2, 2), (17, 45, 3, 15), (16, 24, 3, 8)])
+def test_moduli64_and_roots_match_the_64bit_oracle(shape):
+    """Host-only 64-bit-word calls: the library's moduli and psi equal the
+    64-bit oracle's (derived independently: generator method in the
+    library, quadratic non-residue in the oracle)."""
+    from oracle import core64 as o64
+    log_n, num_q, dnum, num_p = shape
+    mods = ks.ks64_params_moduli(log_n, num_q, dnum, num_p)
+    assert mods == [int(v) for v in o64.moduli(oracle.Params(log_n, num_q, dnum, num_p))]
+    for q in (mods[0], mods[-1]):
+        assert ks.ks64_root_of_unity(q, log_n) == o64.min_psi(q, log_n)
+    assert ks.ks64_root_of_unity(mods[0] + 2, log_n) == 0
+    with pytest.raises(ks.KsError):
+        ks.ks64_params_moduli(log_n, num_q, dnum, num_p, moduli=[(1 << 30) + 1] * (num_q + (num_p or num_q)))

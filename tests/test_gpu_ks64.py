@@ -1,0 +1,183 @@
+"""GPU parity of the 64-bit-word key switch (towers of ~60-bit primes,
+Sec. II word-size moduli; the word size of Table III's evk sizes) against
+the 64-bit oracle, every output word (tolerance 0: exact modular
+arithmetic).  Cases: the NTT per limb for N = 2^12..2^17; the plain
+workload at every level with real keys (decrypted); partial digits,
+dnum = 1, K != alpha, alpha = 1; the longest sums (dnum 16, alpha = K = 32)
+with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17, full
+size; error paths.
+"""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import core64 as o64
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_01598_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def uniform64(mods, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, int(q), n, dtype=np.uint64) for q in mods])
+
+
+def uniform_evk64(mods, dnum, n, seed):
+    rng = np.random.default_rng(seed)
+    out = np.empty((dnum, 2, len(mods), n), np.uint64)
+    for r, m in enumerate(mods):
+        out[:, :, r, :] = rng.integers(0, int(m), (dnum, 2, n), dtype=np.uint64)
+    return out
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16, 17])
+def test_ntt64_matches_oracle(ks, log_n):
+    say(f"[ntt64] log_n={log_n}")
+    plan = ks.Plan64(log_n, 2, 1, 1)
+    mods = plan.moduli
+    assert mods == [int(v) for v in o64.moduli(oracle.Params(log_n, 2, 1, 1))]
+    a = uniform64(mods, plan.n, log_n)
+    d = dev(a)
+    plan.ntt(d, range(len(mods)), inverse=False)
+    torch.cuda.synchronize()
+    got = host(d)
+    for r, q in enumerate(mods):
+        assert np.array_equal(got[r], o64.ntt(a[r], q)), (log_n, r)
+    plan.ntt(d, range(len(mods)), inverse=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(d), a)
+    plan.close()
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_plain_workload_every_level_decrypts(ks, level):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = o64.moduli(p)
+    s, s2, evk, h = o64.keygen(p, mods, seed=1234)
+    d = uniform64(mods[:level + 1], p.n, 50 + level)
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(12, 4, 2, 2)
+    say(f"[ks64 plain] level={level}")
+    got = host(plan.keyswitch(dev(evk), level, dev(d)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+    r = o64.decrypt_residual(p, mods, level, d, got, s, s2)
+    assert max(abs(v) for v in r) <= oracle.noise_bound(p, mods, level, h)
+    plan.close()
+
+
+SHAPES = [(13, 10, 3, 0, 9), (13, 10, 3, 0, 5), (14, 8, 1, 0, 7), (13, 9, 3, 2, 8), (12, 7, 7, 1, 6),
+          (12, 12, 2, 4, 11)]
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", SHAPES)
+def test_shapes(ks, log_n, num_q, dnum, num_p, level):
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    evk = uniform_evk64(mods, dnum, p.n, 7 + num_q)
+    d = uniform64(mods[:level + 1], p.n, 3 + level)
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(log_n, num_q, dnum, num_p)
+    say(f"[ks64 shape] {log_n} {num_q} {dnum} {num_p} level={level}")
+    got = host(plan.keyswitch(dev(evk), level, dev(d)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+    plan.close()
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p", [(13, 32, 16, 2), (13, 64, 2, 32)])
+def test_longest_sums_every_word_at_m_minus_1(ks, log_n, num_q, dnum, num_p):
+    """Input and key words at m - 1: the key sum over 16 digits and the
+    conversion sums over 32 sources and 32 special towers at their largest."""
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    evk = np.empty((dnum, 2, len(mods), p.n), np.uint64)
+    for r, m in enumerate(mods):
+        evk[:, :, r, :] = int(m) - 1
+    d = np.stack([np.full(p.n, int(m) - 1, np.uint64) for m in mods[:num_q]])
+    want = o64.keyswitch(p, mods, num_q - 1, evk, d)
+    plan = ks.Plan64(log_n, num_q, dnum, num_p)
+    say(f"[ks64 edge] {log_n} {num_q} {dnum} {num_p}")
+    got = host(plan.keyswitch(dev(evk), num_q - 1, dev(d)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want)
+    plan.close()
+
+
+BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+
+
+@pytest.fixture(scope="module")
+def bts_cases():
+    """Inputs and oracle outputs of Table III's three bootstrapping sets at
+    full size (the three oracle runs in threads: the C oracle releases the
+    GIL)."""
+    cases = {}
+    for name, (log_n, num_q, dnum, num_p) in BTS.items():
+        p = oracle.Params(log_n, num_q, dnum, num_p)
+        mods = o64.moduli(p)
+        cases[name] = (p, mods, uniform_evk64(mods, dnum, p.n, 900 + num_q),
+                       uniform64(mods[:num_q], p.n, 901 + num_q))
+    say("[ks64 bts] computing three oracle key switches at N=2^17")
+    with ThreadPoolExecutor(max_workers=3) as ex:
+        wants = dict(zip(cases, ex.map(lambda c: o64.keyswitch(c[0], c[1], c[0].num_q - 1, c[2], c[3]),
+                                       cases.values())))
+    return {k: v + (wants[k],) for k, v in cases.items()}
+
+
+@pytest.mark.parametrize("name", list(BTS))
+def test_bts_full_size(ks, bts_cases, name):
+    p, mods, evk, d, want = bts_cases[name]
+    plan = ks.Plan64(p.log_n, p.num_q, p.dnum, p.num_p)
+    say(f"[ks64 bts] {name}")
+    got = host(plan.keyswitch(dev(evk), p.num_q - 1, dev(d)))
+    torch.cuda.synchronize()
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (name, bad[:5], len(bad))
+    plan.close()
+
+
+def test_error_paths(ks):
+    plan = ks.Plan64(12, 4, 2, 2)
+    n = plan.n
+    evk = torch.zeros((2, 2, 6, n), dtype=torch.int64, device="cuda")
+    d = torch.zeros((4, n), dtype=torch.int64, device="cuda")
+    out = torch.empty((2, 4, n), dtype=torch.int64, device="cuda")
+    ws = plan.workspace(3)
+    for args, status in (((evk, 4, d, out, ws), ks.KS_ERR_INVALID_ARG),     # level > L
+                         ((evk, 3, d, d, ws), ks.KS_ERR_INVALID_ARG),       # out aliases in
+                         ((None, 3, d, out, ws), ks.KS_ERR_INVALID_ARG)):
+        with pytest.raises(ks.KsError) as e:
+            ks.ks64_keyswitch(plan.handle, *args)
+        assert e.value.status == status
+    with pytest.raises(ks.KsError) as e:
+        ks.ks64_keyswitch(plan.handle, evk, 3, d, out, ws, workspace_bytes=64)
+    assert e.value.status == ks.KS_ERR_BUDGET
+    plan.close()
+    with pytest.raises(ks.KsError) as e:
+        ks.Plan64(12, 4, 2, 2, moduli=[(1 << 60) - 1] * 6)
+    assert e.value.status == ks.KS_ERR_INVALID_ARG
