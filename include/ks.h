@@ -136,9 +136,11 @@ uint32_t ks_root_of_unity(uint32_t q, uint32_t log_n);
  * twiddle, basis-conversion and ModDown tables (Sec. III-B/C) and upload
  * them.  *out owns them until ks_plan_destroy.  The plan starts with the
  * configuration {OC, tile_towers 2, col_width 16, row_block 8, batch_mode 1,
- * graph 2, spin_limit 0, batch_order 1}: two targets per conversion tile (one where a column
- * holds 32 elements per thread, N = 2^13 and 2^17) equal one target for a
- * single key switch and are faster for batches. */
+ * graph 2, spin_limit 0, batch_order 1}: two targets per conversion tile
+ * equal one target for a single key switch and are faster for batches.
+ * Where a column holds 32 elements per thread the tiles take one target at
+ * N = 2^13, and at N = 2^17 when the launch's largest job has fewer than
+ * 17 towers (two from 17 towers up). */
 ks_status_t ks_plan_create(const ks_params_t *p, ks_plan_t *out);
 ks_status_t ks_plan_destroy(ks_plan_t plan);
 /* Moduli of the plan, host_out [num_q + num_p]. */

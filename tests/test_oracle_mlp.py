@@ -40,3 +40,20 @@ def test_relu_layers_are_piecewise_linear():
     y1, _, _ = mlp.forward(p0, X, F, H)
     y3, _, _ = mlp.forward(p0, 3 * X, F, H)
     assert np.allclose(3 * y1, y3)
+
+
+def test_forward_value_of_a_hand_computed_network():
+    """F = 2, H = 2, worked by hand (W1[f][h] input f to unit h):
+    W1 = [[1, -1], [2, 1]], b1 = [0.5, -1], W2 = [[1, -2], [-1, 1]],
+    b2 = [0, 0.5], W3 = [3, -2], b3 = 0.25.
+    x = (2, 1):  z1 = (4.5, -2) -> h1 = (4.5, 0); z2 = (4.5, -8.5) -> h2 = (4.5, 0);
+                 y = 13.5 + 0.25 = 13.75  (without the first ReLU 19.75,
+                 without the second 30.75, with W1 transposed -2.75).
+    x = (-1, 1): z1 = (1.5, 1) -> h1 = (1.5, 1); z2 = (0.5, -1.5) -> h2 = (0.5, 0);
+                 y = 1.5 + 0.25 = 1.75."""
+    p = np.array([1, -1, 2, 1, 0.5, -1, 1, -2, -1, 1, 0, 0.5, 3, -2, 0.25], np.float64)
+    assert mlp.param_count(2, 2) == p.size
+    y, h1, h2 = mlp.forward(p, np.array([[2.0, 1.0], [-1.0, 1.0]]), 2, 2)
+    assert np.array_equal(y, [13.75, 1.75])
+    assert np.array_equal(h1, [[4.5, 0.0], [1.5, 1.0]])
+    assert np.array_equal(h2, [[4.5, 0.0], [0.5, 0.0]])
