@@ -69,6 +69,12 @@ __device__ __forceinline__ uint32_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t vo
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
   __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
 }
+// The same store with the non-temporal cache policy (bit 1 of the buffer
+// instruction's cache-policy operand), for data written once and read once
+// by a later launch: the basis-conversion outputs.
+__device__ __forceinline__ void buf_st_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 2);
+}
 // Streaming variants for data touched once per key switch (the key words,
 // the output): non-temporal hints, so that they do not push the reused
 // tables and intermediates out of the caches.

@@ -269,6 +269,9 @@ __device__ __forceinline__ void tile_intt_col(const DevPlan &P, const OcJob &J, 
 // Targets of a tile share one LDS exchange region (transformed one after the
 // other), so that two-target tiles are not held to 4 per CU by their LDS.
 constexpr bool kConvSharedLds = true;
+// Conversion tiles with at most 16 elements per thread keep the next
+// source's loads in flight during the current source's products.
+constexpr bool kConvPrefetch = true;
 template <int TT>
 constexpr int conv_lds_regions() { return kConvSharedLds ? 1 : TT; }
 
@@ -320,10 +323,6 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
     for (int e = 0; e < TT; e++)
 #pragma unroll
       for (int u = 0; u < E; u++) acc[e][u] = 0;
-    // One register buffer per source: prefetching the next source into a
-    // second buffer was measured no faster, and the lower register count
-    // (71 instead of 103 VGPRs with one target) lets 7 waves share a SIMD,
-    // which hides the load latency instead.
     auto macc = [&](const uint32_t (&xv)[E], uint32_t i) {
       uint32_t c[TT];
 #pragma unroll
@@ -334,9 +333,25 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
         for (int e = 0; e < TT; e++) acc[e][u] = mad64(xv[u], c[e], acc[e][u]);
     };
     uint32_t xa[E];
-    for (uint32_t i = i0; i < i1; i++) {
-      load_src(xa, i);
-      macc(xa, i);
+    if constexpr (kConvPrefetch && E <= 16) {
+      // two source buffers: the next source's loads are in flight while
+      // this one's products run (loads past the last source read 0)
+      uint32_t xb[E];
+      load_src(xa, i0);
+      for (uint32_t i = i0; i < i1; i += 2) {
+        const bool two = i + 1 < i1;
+        if (two) load_src(xb, i + 1);
+        macc(xa, i);
+        if (two) {
+          if (i + 2 < i1) load_src(xa, i + 2);
+          macc(xb, i + 1);
+        }
+      }
+    } else {
+      for (uint32_t i = i0; i < i1; i++) {
+        load_src(xa, i);
+        macc(xa, i);
+      }
     }
 #pragma unroll
     for (int e = 0; e < TT; e++)
@@ -361,7 +376,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
       ct_group<A, 1 + R1, R2>(x, gg, 1u, tw, mq[e].q);
       const uint32_t vb = ((uint32_t)Ph2::base(gg) * 256u + c0 + w) * 4u;
 #pragma unroll
-      for (int u = 0; u < (1 << R2); u++) buf_st(rt, vb, (uint32_t)u << (Ph2::LOB + 10), x[u]);
+      for (int u = 0; u < (1 << R2); u++) buf_st_nt(rt, vb, (uint32_t)u << (Ph2::LOB + 10), x[u]);
     }
   };
   constexpr bool SHARED = R2 > 0 && conv_lds_regions<TT>() == 1 && TT > 1;
@@ -378,7 +393,7 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
         const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tout[e], (uint32_t)(N * 4));
         const uint32_t vb = ((uint32_t)Ph1::base(tig) * 256u + c0 + w) * 4u;
 #pragma unroll
-        for (int u = 0; u < E; u++) buf_st(rt, vb, (uint32_t)u << (LOB + 10), y[e][u]);
+        for (int u = 0; u < E; u++) buf_st_nt(rt, vb, (uint32_t)u << (LOB + 10), y[e][u]);
       }
     }
     if constexpr (SHARED) {  // this target's phase 2 before the next one's phase 1 overwrites the region
