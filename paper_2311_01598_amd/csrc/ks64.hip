@@ -8,12 +8,17 @@
 //    Shoup's method with the precomputed floor(w 2^64 / q), one 64-bit
 //    high product and two low products, result in [0, 2q) then one
 //    conditional subtraction;
-//  - sums of products (conversion, key multiply-accumulate): exact 128-bit
+//  - sums of products (conversion, key multiply-accumulate): exact
 //    accumulation of at most 16 products of canonical residues (each below
 //    2^60 m, so the sum stays below m 2^64), then one Montgomery reduction
 //    REDC(T) = (T + ((T mod 2^64)(-m^-1) mod 2^64) m) / 2^64 < 2m.  The
 //    2^-64 it leaves is cancelled by constants kept in Montgomery form
-//    (c 2^64 mod m), or by one Shoup product with 2^64 mod m.
+//    (c 2^64 mod m), or by one Shoup product with 2^64 mod m.  Each operand
+//    is split into 30-bit halves, a = a1 2^30 + a0, so a product is four
+//    32 x 32 -> 64-bit products a1 b1 2^60 + (a1 b0 + a0 b1) 2^30 + a0 b0,
+//    each below 2^60: four 64-bit sums (one multiply-add per partial
+//    product) hold 16 products without overflow, and are combined into
+//    the 128-bit sum once per chunk.
 //  - every stage leaves canonical residues.
 // The forward transform is the Cooley-Tukey network that lists a(psi^(2
 // brv(j)+1)) at position j; the inverse is the Gentleman-Sande network and
@@ -54,9 +59,9 @@ struct Dev64 {
   const uint4 *tw_fwd;    // [ntot][N]: (w, w') as two little-endian uint64 per entry
   const uint4 *tw_inv;
   const uint64_t *up_pre; // [num_q][dnum][alpha][2]: [q^_{j,s}^-1]_{q_s} and Shoup companion
-  const uint64_t *up_cst; // [num_q][dnum][alpha][ntot]: [q^_{j,s}]_{m_g} 2^64 mod m_g
+  const uint64_t *up_cst; // [num_q][dnum][ntot][alpha] + 32 zero words: [q^_{j,s}]_{m_g} 2^64 mod m_g
   const uint64_t *dn_pre; // [K][2]: [p^_k^-1]_{p_k} and companion
-  const uint64_t *dn_cst; // [K][num_q]: [p^_k]_{q_i} 2^64 mod q_i
+  const uint64_t *dn_cst; // [num_q][K] + 32 zero words: [p^_k]_{q_i} 2^64 mod q_i
   const uint64_t *pinv;   // [num_q][2]: [P^-1]_{q_i} and companion
 };
 
@@ -78,34 +83,152 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, u
 }
 struct Acc128 {
   uint64_t lo = 0, hi = 0;
-  __device__ __forceinline__ void mac(uint64_t a, uint64_t b) {
-    const uint64_t l = a * b;
-    lo += l;
-    hi += __umul64hi(a, b) + (lo < l ? 1u : 0u);
-  }
 };
 // T < q 2^64: (T + m q) / 2^64 with m = T_lo (-q^-1) mod 2^64, canonical
+// Sum of at most 16 products of values below 2^60 as 30-bit halves.
+constexpr uint64_t kLo30 = (1ull << 30) - 1;
+struct Acc4 {
+  uint64_t s0 = 0, s1a = 0, s1b = 0, s2 = 0;
+  __device__ __forceinline__ void mac(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
+    s0 += (uint64_t)a0 * b0;
+    s1a += (uint64_t)a1 * b0;
+    s1b += (uint64_t)a0 * b1;
+    s2 += (uint64_t)a1 * b1;
+  }
+  __device__ __forceinline__ void mac(uint32_t a0, uint32_t a1, uint64_t b) {
+    mac(a0, a1, (uint32_t)(b & kLo30), (uint32_t)(b >> 30));
+  }
+  __device__ __forceinline__ Acc128 sum() const {
+    const u128 t = (u128)s0 + ((u128)s1a << 30) + ((u128)s1b << 30) + ((u128)s2 << 60);
+    Acc128 r;
+    r.lo = (uint64_t)t;
+    r.hi = (uint64_t)(t >> 64);
+    return r;
+  }
+};
 __device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
   const uint64_t u = t.lo * m.qneg;
   const uint64_t lo = t.lo + u * m.q;  // 0 mod 2^64 by the choice of u
   return csub(t.hi + __umul64hi(u, m.q) + (lo < t.lo ? 1u : 0u), m.q);
 }
 
-__device__ __forceinline__ uint64_t tw(const uint4 *t, size_t i, uint64_t *comp) {
-  const uint4 v = t[i];
-  *comp = ((uint64_t)v.w << 32) | v.z;
-  return ((uint64_t)v.y << 32) | v.x;
+// ------------------------------------------------------------ transforms
+// The twiddle of the butterfly (j, j + t) is entry N / (2t) + j / (2t) of the
+// table.  A pass transforms sequences of M words (M = 256 in the row pass,
+// M = R = N / 256 in the column pass) held in LDS; within a sequence the
+// butterflies at distance t come in h = M / (2t) groups, and group k takes
+// the twiddle the tile stages at [h + k] (one round of loads per tile, so
+// the stages read no global memory).  Stages run two at a time (radix 4:
+// four words per thread, one LDS round trip and one barrier per two
+// stages); an odd stage count ends with one radix-2 stage.
+
+__device__ __forceinline__ void tw_of(const uint4 v, uint64_t *w, uint64_t *ws) {
+  *w = ((uint64_t)v.y << 32) | v.x;
+  *ws = ((uint64_t)v.w << 32) | v.z;
+}
+// Cooley-Tukey butterfly (a, b) -> (a + b w, a - b w)
+__device__ __forceinline__ void ct(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
+  uint64_t w, ws;
+  tw_of(tv, &w, &ws);
+  const uint64_t v = shoup(b, w, ws, q);
+  b = sub_mod(a, v, q);
+  a = add_mod(a, v, q);
+}
+// Gentleman-Sande butterfly (a, b) -> (a + b, (a - b) w)
+__device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
+  uint64_t w, ws;
+  tw_of(tv, &w, &ws);
+  const uint64_t d = sub_mod(a, b, q);
+  a = add_mod(a, b, q);
+  b = shoup(d, w, ws, q);
 }
 
-// ------------------------------------------------------------ transforms
+// One step over `nseq` sequences of M words in LDS (word p of sequence c
+// at s[p * ps + c * cs]) with twiddles at tw + c * ts.  Forward: the
+// stages at distances t and t / 2 (t >= 2), or t alone when R2; inverse:
+// distances t and 2t, or t alone when R2.  Consecutive threads take
+// consecutive units of one sequence when SEQ (rows: contiguous words), of
+// consecutive sequences otherwise (columns: words of a row are adjacent).
+template <bool INV, bool R2, bool SEQ>
+__device__ __forceinline__ void nstep(uint64_t *s, const uint4 *tw, uint32_t M, uint32_t nseq, uint32_t ps,
+                                      uint32_t cs, uint32_t ts, uint32_t t, uint64_t q) {
+  const uint32_t per = R2 ? M / 2 : M / 4;
+  for (uint32_t u = threadIdx.x; u < per * nseq; u += 256) {
+    const uint32_t c = SEQ ? u / per : u % nseq, k = SEQ ? u % per : u / nseq;
+    uint64_t *x = s + c * cs;
+    const uint4 *w = tw + c * ts;
+    if (R2) {
+      const uint32_t grp = k / t, p0 = grp * 2 * t + k % t;
+      uint64_t a = x[p0 * ps], b = x[(p0 + t) * ps];
+      if (!INV) ct(a, b, w[M / (2 * t) + grp], q);
+      else gs(a, b, w[M / (2 * t) + grp], q);
+      x[p0 * ps] = a;
+      x[(p0 + t) * ps] = b;
+    } else if (!INV) {
+      const uint32_t half = t / 2, grp = k / half, p0 = grp * 2 * t + k % half, h1 = M / (2 * t);
+      uint64_t x0 = x[p0 * ps], x1 = x[(p0 + half) * ps], x2 = x[(p0 + t) * ps], x3 = x[(p0 + t + half) * ps];
+      const uint4 w1 = w[h1 + grp];
+      ct(x0, x2, w1, q);
+      ct(x1, x3, w1, q);
+      ct(x0, x1, w[2 * h1 + 2 * grp], q);
+      ct(x2, x3, w[2 * h1 + 2 * grp + 1], q);
+      x[p0 * ps] = x0;
+      x[(p0 + half) * ps] = x1;
+      x[(p0 + t) * ps] = x2;
+      x[(p0 + t + half) * ps] = x3;
+    } else {
+      const uint32_t grp = k / t, p0 = grp * 4 * t + k % t, h1 = M / (2 * t);
+      uint64_t x0 = x[p0 * ps], x1 = x[(p0 + t) * ps], x2 = x[(p0 + 2 * t) * ps], x3 = x[(p0 + 3 * t) * ps];
+      gs(x0, x1, w[h1 + 2 * grp], q);
+      gs(x2, x3, w[h1 + 2 * grp + 1], q);
+      const uint4 w2 = w[h1 / 2 + grp];
+      gs(x0, x2, w2, q);
+      gs(x1, x3, w2, q);
+      x[p0 * ps] = x0;
+      x[(p0 + t) * ps] = x1;
+      x[(p0 + 2 * t) * ps] = x2;
+      x[(p0 + 3 * t) * ps] = x3;
+    }
+  }
+}
+
+// All stages of a pass over sequences of M = 2^lm words.
+template <bool INV, bool SEQ>
+__device__ __forceinline__ void npass(uint64_t *s, const uint4 *tw, uint32_t lm, uint32_t nseq, uint32_t ps,
+                                      uint32_t cs, uint32_t ts, uint64_t q) {
+  const uint32_t M = 1u << lm;
+  if (!INV) {
+    uint32_t t = M / 2;
+    for (; t >= 2; t /= 4) {
+      nstep<false, false, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      __syncthreads();
+    }
+    if (t == 1) {
+      nstep<false, true, SEQ>(s, tw, M, nseq, ps, cs, ts, 1, q);
+      __syncthreads();
+    }
+  } else {
+    uint32_t t = 1;
+    for (; 2 * t < M; t *= 4) {
+      nstep<true, false, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      __syncthreads();
+    }
+    if (t < M) {
+      nstep<true, true, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      __syncthreads();
+    }
+  }
+}
+
 // Row pass: tiles of kRowsPerTile rows of 256 words (a block reads its whole
 // tile before writing it, so src may equal dst).  Forward: stages with
 // butterfly distance t = 128 .. 1 (Cooley-Tukey); inverse: t = 1 .. 128
-// (Gentleman-Sande).  The twiddle of the butterfly (j, j + t) is entry
-// N / (2t) + j / (2t) of the table.
+// (Gentleman-Sande).  Row r at distance t (h = 128 / t groups) uses table
+// entries h (N / 256 + r) + k, k < h, kept at [row][h + k].
 template <bool INV>
 __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
   __shared__ uint64_t s[kRowsPerTile * kRowWords];
+  __shared__ uint4 tws[kRowsPerTile * kRowWords];
   const uint32_t N = 1u << P.log_n, c = blockIdx.y;
   const uint32_t g = L.g[c];
   const Mod64 m = P.mods[g];
@@ -113,70 +236,41 @@ __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *
   const size_t base = (size_t)blockIdx.x * kRowsPerTile * kRowWords;
   const uint64_t *in = src + (size_t)L.src[c] * N + base;
   uint64_t *out = dst + (size_t)L.dst[c] * N + base;
-  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) s[i] = in[i];
-  __syncthreads();
   const uint32_t row0 = blockIdx.x * kRowsPerTile;
-  for (uint32_t st = 0; st < 8; st++) {
-    const uint32_t t = INV ? (1u << st) : (128u >> st);
-    for (uint32_t b = threadIdx.x; b < kRowsPerTile * 128; b += 256) {
-      const uint32_t rr = b >> 7, k = b & 127;
-      const uint32_t jj = (k / t) * 2 * t + (k % t);
-      const uint32_t j = (row0 + rr) * kRowWords + jj;
-      uint64_t ws;
-      const uint64_t w = tw(tab, N / (2 * t) + j / (2 * t), &ws);
-      uint64_t *a = s + rr * kRowWords + jj;
-      const uint64_t u = a[0], v = a[t];
-      if (!INV) {
-        const uint64_t vw = shoup(v, w, ws, m.q);
-        a[0] = add_mod(u, vw, m.q);
-        a[t] = sub_mod(u, vw, m.q);
-      } else {
-        a[0] = add_mod(u, v, m.q);
-        a[t] = shoup(sub_mod(u, v, m.q), w, ws, m.q);
-      }
-    }
-    __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) s[i] = in[i];
+  for (uint32_t e = threadIdx.x; e < kRowsPerTile * kRowWords; e += 256) {
+    const uint32_t rr = e / kRowWords, k = e % kRowWords;
+    if (k == 0) continue;
+    const uint32_t h = 1u << (31 - __clz(k));
+    tws[e] = tab[(size_t)h * (N / kRowWords + row0 + rr) + (k - h)];
   }
+  __syncthreads();
+  npass<INV, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, m.q);
   for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) out[i] = s[i];
 }
 
 // Column pass: tiles of kColsPerTile columns of R = N / 256 rows.  Forward:
 // row distance R/2 .. 1 (butterfly distance t = 256 x that); inverse: 1 ..
-// R/2, then N^-1.
+// R/2, then N^-1.  Every stage uses entries [1, R) of the table, staged
+// once per tile.  Blocks are dealt to the 8 XCDs in turn; block x takes the
+// column tile (x % 8) * 4 + x / 8, so each XCD's L2 holds 32 whole
+// columns (256-byte row segments) of the limb.
 template <bool INV>
 __global__ __launch_bounds__(256) void k_col(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
   __shared__ uint64_t s[512 * kColsPerTile];
+  __shared__ uint4 tws[512];
   const uint32_t N = 1u << P.log_n, R = N / kRowWords, c = blockIdx.y;
   const uint32_t g = L.g[c];
   const Mod64 m = P.mods[g];
   const uint4 *tab = (INV ? P.tw_inv : P.tw_fwd) + (size_t)g * N;
-  const uint32_t col0 = blockIdx.x * kColsPerTile;
+  const uint32_t x = blockIdx.x, col0 = ((x % 8) * (gridDim.x / 8) + x / 8) * kColsPerTile;
   const uint64_t *in = src + (size_t)L.src[c] * N;
   uint64_t *out = dst + (size_t)L.dst[c] * N;
   for (uint32_t i = threadIdx.x; i < R * kColsPerTile; i += 256)
     s[i] = in[(size_t)(i / kColsPerTile) * kRowWords + col0 + i % kColsPerTile];
+  for (uint32_t e = threadIdx.x; e < R; e += 256) tws[e] = tab[e];
   __syncthreads();
-  const uint32_t a = P.log_n - 8;
-  for (uint32_t st = 0; st < a; st++) {
-    const uint32_t tr = INV ? (1u << st) : ((R >> 1) >> st);
-    for (uint32_t b = threadIdx.x; b < (R / 2) * kColsPerTile; b += 256) {
-      const uint32_t cc = b % kColsPerTile, k = b / kColsPerTile;
-      const uint32_t grp = k / tr, r = grp * 2 * tr + (k % tr);
-      uint64_t ws;
-      const uint64_t w = tw(tab, R / (2 * tr) + grp, &ws);
-      uint64_t *x = s + r * kColsPerTile + cc;
-      const uint64_t u = x[0], v = x[tr * kColsPerTile];
-      if (!INV) {
-        const uint64_t vw = shoup(v, w, ws, m.q);
-        x[0] = add_mod(u, vw, m.q);
-        x[tr * kColsPerTile] = sub_mod(u, vw, m.q);
-      } else {
-        x[0] = add_mod(u, v, m.q);
-        x[tr * kColsPerTile] = shoup(sub_mod(u, v, m.q), w, ws, m.q);
-      }
-    }
-    __syncthreads();
-  }
+  npass<INV, false>(s, tws, P.log_n - 8, kColsPerTile, kColsPerTile, 1, 0, m.q);
   for (uint32_t i = threadIdx.x; i < R * kColsPerTile; i += 256) {
     uint64_t v = s[i];
     if (INV) v = shoup(v, m.ninv, m.ninvs, m.q);
@@ -187,9 +281,42 @@ __global__ __launch_bounds__(256) void k_col(Dev64 P, List64 L, const uint64_t *
 // ------------------------------------------------------------ ModUp P2
 // Digit j of the input (X, coefficient domain) converted to every tower of
 // D_l outside the digit: y_{j,t} = sum_s [x_s q^_{j,s}^-1]_{q_s} [q^_{j,s}]_{m_t}.
-// grid (N / 256, digits); each thread one coefficient, all targets.
+// grid (N / 256, digits, target groups of kTgtGroup towers); each thread one
+// coefficient.
 __device__ __forceinline__ uint32_t gidx(const Dev64 &P, uint32_t level, uint32_t t) {
   return t <= level ? t : P.num_q + (t - level - 1);
+}
+
+// Each block converts 256 coefficients of one digit to one group of
+// kTgtGroup consecutive towers of D_l (grid z), two targets at a time so
+// that the two 128-bit sums are independent chains.
+constexpr uint32_t kTgtGroup = 8;
+
+// sum_{s < ns} x[s] c[s] reduced mod m for two targets, the sources as
+// 30-bit halves (x0, x1) and zero from ns on: chunks of 16 products, each
+// chunk one REDC (its 2^-64 cancelled by constants in Montgomery form).
+// The constants of a chunk are read without a bound (the tables are padded
+// by 32 entries), so they load as wide scalar reads.
+template <int MAXS>
+__device__ __forceinline__ void conv2(const uint32_t (&x0)[MAXS], const uint32_t (&x1)[MAXS], uint32_t ns,
+                                      const uint64_t *c0, const uint64_t *c1, const Mod64 &m0, const Mod64 &m1,
+                                      uint64_t *y0, uint64_t *y1) {
+  uint64_t r0 = 0, r1 = 0;
+#pragma unroll
+  for (int k0 = 0; k0 < MAXS; k0 += 16) {
+    if ((uint32_t)k0 < ns) {
+      Acc4 a0, a1;
+#pragma unroll
+      for (int k = k0; k < k0 + 16 && k < MAXS; k++) {
+        a0.mac(x0[k], x1[k], c0[k]);
+        a1.mac(x0[k], x1[k], c1[k]);
+      }
+      r0 = add_mod(r0, redc(a0.sum(), m0), m0.q);
+      r1 = add_mod(r1, redc(a1.sum(), m1), m1.q);
+    }
+  }
+  *y0 = r0;
+  *y1 = r1;
 }
 
 template <int MAXA>
@@ -198,81 +325,84 @@ __global__ __launch_bounds__(256) void k_bconv_up(Dev64 P, uint32_t level, const
   const uint32_t N = 1u << P.log_n, j = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, l1), ns = hi - lo;
-  const size_t cbase = ((size_t)level * P.dnum + j) * P.alpha;
-  uint64_t xs[MAXA];
+  const uint32_t t0 = blockIdx.z * kTgtGroup, t1 = min(t0 + kTgtGroup, T);
+  const size_t crow = (size_t)level * P.dnum + j, cbase = crow * P.alpha;
+  uint32_t x0[MAXA], x1[MAXA];
 #pragma unroll
   for (int s = 0; s < MAXA; s++) {
+    x0[s] = x1[s] = 0;
     if ((uint32_t)s < ns) {
       const uint64_t *pre = P.up_pre + (cbase + s) * 2;
-      xs[s] = shoup(X[(size_t)(lo + s) * N + c], pre[0], pre[1], P.mods[lo + s].q);
+      const uint64_t v = shoup(X[(size_t)(lo + s) * N + c], pre[0], pre[1], P.mods[lo + s].q);
+      x0[s] = (uint32_t)(v & kLo30);
+      x1[s] = (uint32_t)(v >> 30);
     }
   }
-  for (uint32_t t = 0; t < T; t++) {
-    if (t >= lo && t < hi) continue;
-    const uint32_t g = gidx(P, level, t);
-    const Mod64 m = P.mods[g];
-    uint64_t y = 0;
-#pragma unroll
-    for (int c0 = 0; c0 < MAXA; c0 += 16) {
-      if ((uint32_t)c0 < ns) {
-        Acc128 acc;
-#pragma unroll
-        for (int s = c0; s < c0 + 16 && s < MAXA; s++)
-          if ((uint32_t)s < ns) acc.mac(xs[s], P.up_cst[(cbase + s) * P.ntot + g]);
-        y = add_mod(y, redc(acc, m), m.q);
-      }
-    }
-    Y[((size_t)j * T + t) * N + c] = y;
+  // the group's targets outside the digit, in pairs (an odd count repeats
+  // the last target, written twice with the same value)
+  auto skip = [&](uint32_t t) { return (t >= lo && t < hi) ? hi : t; };
+  for (uint32_t t = skip(t0); t < t1;) {
+    const uint32_t tn = skip(t + 1), ta = t, tb = tn < t1 ? tn : t;
+    t = tn < t1 ? skip(tn + 1) : t1;
+    const uint32_t ga = gidx(P, level, ta), gb = gidx(P, level, tb);
+    uint64_t ya, yb;
+    conv2<MAXA>(x0, x1, ns, P.up_cst + (crow * P.ntot + ga) * P.alpha, P.up_cst + (crow * P.ntot + gb) * P.alpha,
+                P.mods[ga], P.mods[gb], &ya, &yb);
+    Y[((size_t)j * T + ta) * N + c] = ya;
+    Y[((size_t)j * T + tb) * N + c] = yb;
   }
 }
 
 // ------------------------------------------------------------ ModUp P4/P5
 // acc_s[t] = sum_j yhat_{j,t} evk[j][s][t] over the live digits, where
 // yhat_{j,t} is the input tower itself when t is one of digit j's own
-// towers (Sec. IV-C bypass: NTT(INTT(d_t)) = d_t).  grid (N / 256, T, 2).
+// towers (Sec. IV-C bypass: NTT(INTT(d_t)) = d_t).  grid (N / 256, T); each
+// thread reads its digit words once for both halves of the key.
 __global__ __launch_bounds__(256) void k_keymac(Dev64 P, uint32_t level, const uint64_t *__restrict__ d,
                                                 const uint64_t *__restrict__ Y, const uint64_t *__restrict__ evk,
                                                 uint64_t *__restrict__ acc) {
-  const uint32_t N = 1u << P.log_n, t = blockIdx.y, s = blockIdx.z, l1 = level + 1, T = l1 + P.num_p;
+  const uint32_t N = 1u << P.log_n, t = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t g = gidx(P, level, t), D = (l1 + P.alpha - 1) / P.alpha;
   const Mod64 m = P.mods[g];
-  Acc128 a;
+  Acc4 a0, a1;
   for (uint32_t j = 0; j < D; j++) {
     const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, l1);
     const uint64_t y = (t >= lo && t < hi) ? d[(size_t)t * N + c] : Y[((size_t)j * T + t) * N + c];
-    a.mac(y, evk[(((size_t)j * 2 + s) * P.ntot + g) * N + c]);
+    const uint32_t y0 = (uint32_t)(y & kLo30), y1 = (uint32_t)(y >> 30);
+    a0.mac(y0, y1, evk[(((size_t)j * 2 + 0) * P.ntot + g) * N + c]);
+    a1.mac(y0, y1, evk[(((size_t)j * 2 + 1) * P.ntot + g) * N + c]);
   }
-  acc[((size_t)s * T + t) * N + c] = shoup(redc(a, m), m.r64, m.r64s, m.q);
+  acc[((size_t)0 * T + t) * N + c] = shoup(redc(a0.sum(), m), m.r64, m.r64s, m.q);
+  acc[((size_t)1 * T + t) * N + c] = shoup(redc(a1.sum(), m), m.r64, m.r64s, m.q);
 }
 
 // ------------------------------------------------------------ ModDown P2
 // w_{s,i} = sum_k [a_{s,k} p^_k^-1]_{p_k} [p^_k]_{q_i}, i <= level.
-// grid (N / 256, 2).
+// grid (N / 256, 2, target groups of kTgtGroup towers).
 template <int MAXK>
 __global__ __launch_bounds__(256) void k_bconv_down(Dev64 P, uint32_t level, const uint64_t *__restrict__ XP,
                                                     uint64_t *__restrict__ W) {
   const uint32_t N = 1u << P.log_n, s = blockIdx.y, K = P.num_p, l1 = level + 1;
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-  uint64_t xs[MAXK];
+  const uint32_t i0 = blockIdx.z * kTgtGroup, i1 = min(i0 + kTgtGroup, l1);
+  uint32_t x0[MAXK], x1[MAXK];
 #pragma unroll
-  for (int k = 0; k < MAXK; k++)
-    if ((uint32_t)k < K)
-      xs[k] = shoup(XP[((size_t)s * K + k) * N + c], P.dn_pre[2 * k], P.dn_pre[2 * k + 1], P.mods[P.num_q + k].q);
-  for (uint32_t i = 0; i < l1; i++) {
-    const Mod64 m = P.mods[i];
-    uint64_t w = 0;
-#pragma unroll
-    for (int c0 = 0; c0 < MAXK; c0 += 16) {
-      if ((uint32_t)c0 < K) {
-        Acc128 acc;
-#pragma unroll
-        for (int k = c0; k < c0 + 16 && k < MAXK; k++)
-          if ((uint32_t)k < K) acc.mac(xs[k], P.dn_cst[(size_t)k * P.num_q + i]);
-        w = add_mod(w, redc(acc, m), m.q);
-      }
+  for (int k = 0; k < MAXK; k++) {
+    x0[k] = x1[k] = 0;
+    if ((uint32_t)k < K) {
+      const uint64_t v =
+          shoup(XP[((size_t)s * K + k) * N + c], P.dn_pre[2 * k], P.dn_pre[2 * k + 1], P.mods[P.num_q + k].q);
+      x0[k] = (uint32_t)(v & kLo30);
+      x1[k] = (uint32_t)(v >> 30);
     }
-    W[((size_t)s * l1 + i) * N + c] = w;
+  }
+  for (uint32_t i = i0; i < i1; i += 2) {
+    const uint32_t ia = i, ib = min(i + 1, i1 - 1);
+    uint64_t wa, wb;
+    conv2<MAXK>(x0, x1, K, P.dn_cst + (size_t)ia * K, P.dn_cst + (size_t)ib * K, P.mods[ia], P.mods[ib], &wa, &wb);
+    W[((size_t)s * l1 + ia) * N + c] = wa;
+    W[((size_t)s * l1 + ib) * N + c] = wb;
   }
 }
 
@@ -399,7 +529,7 @@ ks_status_t build(ks64_plan *pl, const ks64_params_t *p, uint32_t K) {
     }
   }
   // ModUp conversion constants per level (the last live digit is partial)
-  std::vector<uint64_t> up_pre((size_t)L1 * D * A * 2, 0), up_cst((size_t)L1 * D * A * T, 0);
+  std::vector<uint64_t> up_pre((size_t)L1 * D * A * 2, 0), up_cst((size_t)L1 * D * A * T + 32, 0);
   for (uint32_t lv = 0; lv < L1; lv++)
     for (uint32_t j = 0; j < D; j++) {
       const uint32_t lo = j * A;
@@ -418,12 +548,12 @@ ks_status_t build(ks64_plan *pl, const ks64_params_t *p, uint32_t K) {
           uint64_t qh = 1;
           for (uint32_t u = lo; u < hi; u++)
             if (u != s) qh = mulmod(qh, pl->mod[u] % mg, mg);
-          up_cst[ix * T + g] = mont_of(qh, mg);
+          up_cst[(((size_t)lv * D + j) * T + g) * A + (s - lo)] = mont_of(qh, mg);
         }
       }
     }
   // ModDown constants
-  std::vector<uint64_t> dn_pre((size_t)K * 2), dn_cst((size_t)K * L1), pinv((size_t)L1 * 2);
+  std::vector<uint64_t> dn_pre((size_t)K * 2), dn_cst((size_t)K * L1 + 32, 0), pinv((size_t)L1 * 2);
   for (uint32_t k = 0; k < K; k++) {
     const uint64_t pk = pl->mod[L1 + k];
     uint64_t ph = 1;
@@ -436,7 +566,7 @@ ks_status_t build(ks64_plan *pl, const ks64_params_t *p, uint32_t K) {
       uint64_t h = 1;
       for (uint32_t u = 0; u < K; u++)
         if (u != k) h = mulmod(h, pl->mod[L1 + u] % qi, qi);
-      dn_cst[(size_t)k * L1 + i] = mont_of(h, qi);
+      dn_cst[(size_t)i * K + k] = mont_of(h, qi);
     }
   }
   for (uint32_t i = 0; i < L1; i++) {
@@ -615,9 +745,11 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   for (uint32_t i = 0; i < L1; i++) { so.push_back(i); dof.push_back(i); g.push_back(i); }
   if (transform(pl, true, in, X, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
   // P2: every digit converted to the other towers of D_l
-  if (pl->alpha <= 8) hipLaunchKernelGGL(k_bconv_up<8>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
-  else if (pl->alpha <= 16) hipLaunchKernelGGL(k_bconv_up<16>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
-  else hipLaunchKernelGGL(k_bconv_up<32>, dim3(blocks, D), dim3(256), 0, st, pl->dev, level, X, Y);
+  const dim3 gup(blocks, D, (T + kTgtGroup - 1) / kTgtGroup);
+  if (pl->alpha <= 8) hipLaunchKernelGGL(k_bconv_up<8>, gup, dim3(256), 0, st, pl->dev, level, X, Y);
+  else if (pl->alpha <= 16) hipLaunchKernelGGL(k_bconv_up<16>, gup, dim3(256), 0, st, pl->dev, level, X, Y);
+  else if (pl->alpha <= 24) hipLaunchKernelGGL(k_bconv_up<24>, gup, dim3(256), 0, st, pl->dev, level, X, Y);
+  else hipLaunchKernelGGL(k_bconv_up<32>, gup, dim3(256), 0, st, pl->dev, level, X, Y);
   if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
   // P3: NTT of the converted towers (a digit's own towers are never read from Y)
   so.clear(); dof.clear(); g.clear();
@@ -631,7 +763,7 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   }
   if (transform(pl, false, Y, Y, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
   // P4/P5: key multiply-accumulate over the digits
-  hipLaunchKernelGGL(k_keymac, dim3(blocks, T, 2), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC);
+  hipLaunchKernelGGL(k_keymac, dim3(blocks, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC);
   if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
   // ModDown P1: INTT of the K special towers of both polynomials
   so.clear(); dof.clear(); g.clear();
@@ -639,9 +771,11 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
     for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl->num_q + k); }
   if (transform(pl, true, ACC, XP, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
   // P2: conversion P -> Q_l
-  if (K <= 8) hipLaunchKernelGGL(k_bconv_down<8>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
-  else if (K <= 16) hipLaunchKernelGGL(k_bconv_down<16>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
-  else hipLaunchKernelGGL(k_bconv_down<32>, dim3(blocks, 2), dim3(256), 0, st, pl->dev, level, XP, W);
+  const dim3 gdn(blocks, 2, (L1 + kTgtGroup - 1) / kTgtGroup);
+  if (K <= 8) hipLaunchKernelGGL(k_bconv_down<8>, gdn, dim3(256), 0, st, pl->dev, level, XP, W);
+  else if (K <= 16) hipLaunchKernelGGL(k_bconv_down<16>, gdn, dim3(256), 0, st, pl->dev, level, XP, W);
+  else if (K <= 24) hipLaunchKernelGGL(k_bconv_down<24>, gdn, dim3(256), 0, st, pl->dev, level, XP, W);
+  else hipLaunchKernelGGL(k_bconv_down<32>, gdn, dim3(256), 0, st, pl->dev, level, XP, W);
   if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
   // P3: NTT; P4: subtract, times P^-1
   so.clear(); dof.clear(); g.clear();
