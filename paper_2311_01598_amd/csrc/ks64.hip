@@ -76,15 +76,19 @@ struct List64 {
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
 __device__ __forceinline__ uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
 __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
-// a < 2^64, w < q < 2^62, ws = floor(w 2^64 / q): a w mod q, canonical
-__device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
+// a < 2^64, w < q < 2^62, ws = floor(w 2^64 / q): a w mod q in [0, 2q)
+__device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
   const uint64_t h = __umul64hi(a, ws);
-  return csub(a * w - h * q, q);
+  return a * w - h * q;
 }
+// the same, canonical
+__device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
+  return csub(shoup_lazy(a, w, ws, q), q);
+}
+// A 128-bit value, (hi, lo).
 struct Acc128 {
   uint64_t lo = 0, hi = 0;
 };
-// T < q 2^64: (T + m q) / 2^64 with m = T_lo (-q^-1) mod 2^64, canonical
 // Sum of at most 16 products of values below 2^60 as 30-bit halves.
 constexpr uint64_t kLo30 = (1ull << 30) - 1;
 struct Acc4 {
@@ -106,6 +110,7 @@ struct Acc4 {
     return r;
   }
 };
+// T < q 2^64: (T + m q) / 2^64 with m = T_lo (-q^-1) mod 2^64, canonical
 __device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
   const uint64_t u = t.lo * m.qneg;
   const uint64_t lo = t.lo + u * m.q;  // 0 mod 2^64 by the choice of u
@@ -126,21 +131,24 @@ __device__ __forceinline__ void tw_of(const uint4 v, uint64_t *w, uint64_t *ws) 
   *w = ((uint64_t)v.y << 32) | v.x;
   *ws = ((uint64_t)v.w << 32) | v.z;
 }
-// Cooley-Tukey butterfly (a, b) -> (a + b w, a - b w)
+// Harvey's lazy butterflies (q < 2^60, so 4q fits a word).  Cooley-Tukey
+// (a, b) -> (a + b w, a - b w) on inputs in [0, 4q), outputs in [0, 4q):
+// one conditional subtraction of 2q per butterfly.
 __device__ __forceinline__ void ct(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
-  const uint64_t v = shoup(b, w, ws, q);
-  b = sub_mod(a, v, q);
-  a = add_mod(a, v, q);
+  const uint64_t q2 = 2 * q, x = csub(a, q2), v = shoup_lazy(b, w, ws, q);
+  a = x + v;
+  b = x - v + q2;
 }
-// Gentleman-Sande butterfly (a, b) -> (a + b, (a - b) w)
+// Gentleman-Sande (a, b) -> (a + b, (a - b) w) on inputs in [0, 2q),
+// outputs in [0, 2q).
 __device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
-  const uint64_t d = sub_mod(a, b, q);
-  a = add_mod(a, b, q);
-  b = shoup(d, w, ws, q);
+  const uint64_t q2 = 2 * q, d = a - b + q2;
+  a = csub(a + b, q2);
+  b = shoup_lazy(d, w, ws, q);
 }
 
 // One step over `nseq` sequences of M words in LDS (word p of sequence c
@@ -246,7 +254,10 @@ __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *
   }
   __syncthreads();
   npass<INV, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, m.q);
-  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) out[i] = s[i];
+  // forward: the transform's last pass, words [0, 4q) -> canonical; inverse:
+  // the first pass, words left in [0, 2q) for the column pass
+  for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256)
+    out[i] = INV ? s[i] : csub(csub(s[i], 2 * m.q), m.q);
 }
 
 // Column pass: tiles of kColsPerTile columns of R = N / 256 rows.  Forward:
