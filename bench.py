@@ -151,14 +151,24 @@ def stage_bytes(log_n, l1, k, alpha):
     }
 
 
+# Compile units of the library that hold none of the 32-bit key switch's
+# kernels or their launches: the 64-bit-word path, the cost-model MLP, the
+# rate probes and the no-allocation scratch array.
+DIGEST_EXCLUDE = ("ks64.hip", "mlp.hip", "rates.hip", "noalloc.hip")
+
+
 def kernel_source_digest(csrc=None):
-    """Digest of the library sources with comments and blank space removed:
-    the traffic counters stay valid across comment edits, not code edits."""
+    """Digest of the library sources that build the 32-bit key switch, with
+    comments and blank space removed: the traffic counters stay valid across
+    comment edits and edits of the other compile units, not code edits of
+    these."""
     import hashlib
     import re
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2311_01598_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f in DIGEST_EXCLUDE:
+            continue
         text = open(os.path.join(csrc, f), encoding="utf-8").read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
@@ -447,6 +457,22 @@ def bts_rate(ks, steps, np, torch, synth):
         del evk64, d64, out64, ws64
         p64.close()
         res[name] = cur
+    # the modulus of BTS3's 60-bit towers (45 + 15) in 30-bit towers: 90 + 30,
+    # dnum 3 (alpha = K = 30), OC; BTS1/BTS2 would need alpha > 32
+    log_n, num_q, dnum, num_p = 17, 90, 3, 30
+    plan = ks.Plan(log_n, num_q, dnum, num_p)
+    n, mods, level = plan.n, plan.moduli, num_q - 1
+    evk = torch.from_numpy(synth.uniform_evk(mods, dnum, n, synth.seed_for(31, 90)).view(np.int32)).cuda()
+    d = torch.from_numpy(synth.uniform_limbs(mods[:num_q], n, synth.seed_for(31, 91)).view(np.int32)).cuda()
+    out = torch.empty((2, num_q, n), dtype=torch.int32, device="cuda")
+    plan.configure("oc")
+    ws = plan.workspace([level])
+    s30 = timed_calls(lambda r=0: plan.keyswitch(evk, level, d, out=out, workspace=ws), max(5, steps // 4), torch)
+    res["bts3"]["oc_30bit_towers_same_modulus"] = {"towers": "90 + 30, dnum 3", "ks_per_s": round(1 / s30, 1),
+                                                   "us_per_ks": round(s30 * 1e6, 2),
+                                                   "evk_mib": round(evk.numel() * 4 / 2**20, 1)}
+    del evk, d, out, ws
+    plan.close()
     return res
 
 

@@ -50,6 +50,11 @@ def test_source_digest_ignores_comments_not_code(tmp_path):
     assert bench.kernel_source_digest(str(a)) == base
     f.write_text(text.replace("constexpr int kPad = 272;", "constexpr int kPad = 276;", 1))
     assert bench.kernel_source_digest(str(a)) != base
+    f.write_text(text)
+    # a code edit in a compile unit outside the 32-bit key switch leaves it
+    g = a / "ks64.hip"
+    g.write_text(g.read_text().replace("constexpr uint32_t kList = 96;", "constexpr uint32_t kList = 64;", 1))
+    assert bench.kernel_source_digest(str(a)) == base
 
 
 def test_batch_bytes_count_the_shared_key_once():

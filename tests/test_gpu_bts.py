@@ -6,7 +6,8 @@ full size with every output element compared against the oracle.  These stress t
 (512 x 256), conversions with more than 16 source towers (alpha 28 and 20,
 and K = 28 / 20 for ModDown, accumulated in chunks of 16 products), and
 the single-digit case where ModUp has no Q target.  BTS3 also runs with a
-compressed key, BTS2 also with the Max-Parallel schedule.
+compressed key, BTS2 also with the Max-Parallel schedule.  BTS3's modulus
+in 30-bit towers (90 + 30, 120 towers, alpha = K = 30) runs the OC order.
 """
 import sys
 
@@ -22,7 +23,10 @@ torch = pytest.importorskip("torch")
 
 BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15),
        # the serving workload's largest plan: N = 2^17, 48 towers, dnum 3, K = alpha = 16
-       "serve17": (17, 48, 3, 0)}
+       "serve17": (17, 48, 3, 0),
+       # BTS3's modulus (45 + 15 towers of 60 bits) in 30-bit towers: 90 + 30,
+       # alpha = K = 30, 120 towers (the bench times it beside the 64-bit path)
+       "bts3_30bit": (17, 90, 3, 30)}
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +45,7 @@ def host(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-@pytest.mark.parametrize("name", ["bts1", "bts2", "bts3", "serve17"])
+@pytest.mark.parametrize("name", ["bts1", "bts2", "bts3", "serve17", "bts3_30bit"])
 def test_bts_full_size(ks, name):
     log_n, num_q, dnum, num_p = BTS[name]
     p = oracle.Params(log_n, num_q, dnum, num_p)
