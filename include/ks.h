@@ -446,7 +446,9 @@ const char *ks_status_string(ks_status_t s);
  * with x^N = -1 (mod m); the evaluation domain, evk layout, digits and
  * output conventions are those above, with uint64 residues.  Runs the
  * Max-Parallel order (Sec. IV-A): every stage over all towers, each stage's
- * output in the workspace.  Parameter limits as for ks_params_t.
+ * output in the workspace, with the row pass of a transform fused into the
+ * key multiply-accumulate or the ModDown epilogue it feeds.  Parameter
+ * limits as for ks_params_t.
  * ------------------------------------------------------------------------ */
 typedef struct {
   uint32_t log_n;

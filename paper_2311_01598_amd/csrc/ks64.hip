@@ -24,7 +24,11 @@
 // brv(j)+1)) at position j; the inverse is the Gentleman-Sande network and
 // N^-1.  A transform of N = R x 256 words is a column pass (stages with
 // butterfly distance >= 256) and a row pass (distance < 256), each staged
-// through LDS.
+// through LDS.  Where a transform feeds an element-wise step, its row pass
+// runs inside that step's kernel: the forward row pass of the converted
+// towers with the key multiply-accumulate (and, for the special towers, the
+// inverse row pass of ModDown), the forward row pass of ModDown's converted
+// towers with the final subtraction and P^-1.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -159,12 +163,12 @@ __device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uin
 // consecutive sequences otherwise (columns: words of a row are adjacent).
 template <bool INV, bool R2, bool SEQ>
 __device__ __forceinline__ void nstep(uint64_t *s, const uint4 *tw, uint32_t M, uint32_t nseq, uint32_t ps,
-                                      uint32_t cs, uint32_t ts, uint32_t t, uint64_t q) {
+                                      uint32_t cs, uint32_t ts, uint32_t tmask, uint32_t t, uint64_t q) {
   const uint32_t per = R2 ? M / 2 : M / 4;
   for (uint32_t u = threadIdx.x; u < per * nseq; u += 256) {
     const uint32_t c = SEQ ? u / per : u % nseq, k = SEQ ? u % per : u / nseq;
     uint64_t *x = s + c * cs;
-    const uint4 *w = tw + c * ts;
+    const uint4 *w = tw + (c & tmask) * ts;
     if (R2) {
       const uint32_t grp = k / t, p0 = grp * 2 * t + k % t;
       uint64_t a = x[p0 * ps], b = x[(p0 + t) * ps];
@@ -200,29 +204,30 @@ __device__ __forceinline__ void nstep(uint64_t *s, const uint4 *tw, uint32_t M, 
   }
 }
 
-// All stages of a pass over sequences of M = 2^lm words.
+// All stages of a pass over sequences of M = 2^lm words; sequence c takes
+// the twiddles of sequence c & tmask.
 template <bool INV, bool SEQ>
 __device__ __forceinline__ void npass(uint64_t *s, const uint4 *tw, uint32_t lm, uint32_t nseq, uint32_t ps,
-                                      uint32_t cs, uint32_t ts, uint64_t q) {
+                                      uint32_t cs, uint32_t ts, uint32_t tmask, uint64_t q) {
   const uint32_t M = 1u << lm;
   if (!INV) {
     uint32_t t = M / 2;
     for (; t >= 2; t /= 4) {
-      nstep<false, false, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      nstep<false, false, SEQ>(s, tw, M, nseq, ps, cs, ts, tmask, t, q);
       __syncthreads();
     }
     if (t == 1) {
-      nstep<false, true, SEQ>(s, tw, M, nseq, ps, cs, ts, 1, q);
+      nstep<false, true, SEQ>(s, tw, M, nseq, ps, cs, ts, tmask, 1, q);
       __syncthreads();
     }
   } else {
     uint32_t t = 1;
     for (; 2 * t < M; t *= 4) {
-      nstep<true, false, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      nstep<true, false, SEQ>(s, tw, M, nseq, ps, cs, ts, tmask, t, q);
       __syncthreads();
     }
     if (t < M) {
-      nstep<true, true, SEQ>(s, tw, M, nseq, ps, cs, ts, t, q);
+      nstep<true, true, SEQ>(s, tw, M, nseq, ps, cs, ts, tmask, t, q);
       __syncthreads();
     }
   }
@@ -233,6 +238,15 @@ __device__ __forceinline__ void npass(uint64_t *s, const uint4 *tw, uint32_t lm,
 // butterfly distance t = 128 .. 1 (Cooley-Tukey); inverse: t = 1 .. 128
 // (Gentleman-Sande).  Row r at distance t (h = 128 / t groups) uses table
 // entries h (N / 256 + r) + k, k < h, kept at [row][h + k].
+__device__ __forceinline__ void stage_row_tw(uint4 *tws, const uint4 *tab, uint32_t N, uint32_t row0) {
+  for (uint32_t e = threadIdx.x; e < kRowsPerTile * kRowWords; e += 256) {
+    const uint32_t rr = e / kRowWords, k = e % kRowWords;
+    if (k == 0) continue;
+    const uint32_t h = 1u << (31 - __clz(k));
+    tws[e] = tab[(size_t)h * (N / kRowWords + row0 + rr) + (k - h)];
+  }
+}
+
 template <bool INV>
 __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
   __shared__ uint64_t s[kRowsPerTile * kRowWords];
@@ -246,14 +260,9 @@ __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *
   uint64_t *out = dst + (size_t)L.dst[c] * N + base;
   const uint32_t row0 = blockIdx.x * kRowsPerTile;
   for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256) s[i] = in[i];
-  for (uint32_t e = threadIdx.x; e < kRowsPerTile * kRowWords; e += 256) {
-    const uint32_t rr = e / kRowWords, k = e % kRowWords;
-    if (k == 0) continue;
-    const uint32_t h = 1u << (31 - __clz(k));
-    tws[e] = tab[(size_t)h * (N / kRowWords + row0 + rr) + (k - h)];
-  }
+  stage_row_tw(tws, tab, N, row0);
   __syncthreads();
-  npass<INV, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, m.q);
+  npass<INV, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, ~0u, m.q);
   // forward: the transform's last pass, words [0, 4q) -> canonical; inverse:
   // the first pass, words left in [0, 2q) for the column pass
   for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256)
@@ -281,7 +290,7 @@ __global__ __launch_bounds__(256) void k_col(Dev64 P, List64 L, const uint64_t *
     s[i] = in[(size_t)(i / kColsPerTile) * kRowWords + col0 + i % kColsPerTile];
   for (uint32_t e = threadIdx.x; e < R; e += 256) tws[e] = tab[e];
   __syncthreads();
-  npass<INV, false>(s, tws, P.log_n - 8, kColsPerTile, kColsPerTile, 1, 0, m.q);
+  npass<INV, false>(s, tws, P.log_n - 8, kColsPerTile, kColsPerTile, 1, 0, 0, m.q);
   for (uint32_t i = threadIdx.x; i < R * kColsPerTile; i += 256) {
     uint64_t v = s[i];
     if (INV) v = shoup(v, m.ninv, m.ninvs, m.q);
@@ -364,28 +373,81 @@ __global__ __launch_bounds__(256) void k_bconv_up(Dev64 P, uint32_t level, const
   }
 }
 
-// ------------------------------------------------------------ ModUp P4/P5
-// acc_s[t] = sum_j yhat_{j,t} evk[j][s][t] over the live digits, where
-// yhat_{j,t} is the input tower itself when t is one of digit j's own
-// towers (Sec. IV-C bypass: NTT(INTT(d_t)) = d_t).  grid (N / 256, T); each
-// thread reads its digit words once for both halves of the key.
-__global__ __launch_bounds__(256) void k_keymac(Dev64 P, uint32_t level, const uint64_t *__restrict__ d,
-                                                const uint64_t *__restrict__ Y, const uint64_t *__restrict__ evk,
-                                                uint64_t *__restrict__ acc) {
+// ------------------------------------------------------------ ModUp P3-P5
+// For target tower t of D_l and a tile of kRowsPerTile rows: the forward
+// row pass of every digit's converted tower (its column pass done before),
+// then acc_s[t] = sum_j yhat_{j,t} evk[j][s][t] over the live digits, where
+// yhat_{j,t} is the input tower itself when t is one of digit j's own towers
+// (Sec. IV-C bypass: NTT(INTT(d_t)) = d_t).  Q targets write acc_s[t]; for a
+// P target the inverse row pass of both accumulators follows (ModDown P1,
+// first pass), written to XP[s][t - l - 1] for the inverse column pass.
+// grid (R / kRowsPerTile, T); each thread owns kRowWords * kRowsPerTile /
+// 256 words of the tile.
+constexpr uint32_t kTileWords = kRowsPerTile * kRowWords, kPerThread = kTileWords / 256;
+__global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const uint64_t *__restrict__ d,
+                                                 const uint64_t *__restrict__ Y, const uint64_t *__restrict__ evk,
+                                                 uint64_t *__restrict__ acc, uint64_t *__restrict__ XP) {
+  __shared__ uint64_t s[2 * kTileWords];
+  __shared__ uint4 tws[kTileWords];
   const uint32_t N = 1u << P.log_n, t = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
-  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t g = gidx(P, level, t), D = (l1 + P.alpha - 1) / P.alpha;
   const Mod64 m = P.mods[g];
-  Acc4 a0, a1;
+  const uint32_t row0 = blockIdx.x * kRowsPerTile;
+  const size_t base = (size_t)row0 * kRowWords;
+  stage_row_tw(tws, P.tw_fwd + (size_t)g * N, N, row0);
+  Acc4 a0[kPerThread], a1[kPerThread];
   for (uint32_t j = 0; j < D; j++) {
     const uint32_t lo = j * P.alpha, hi = min(lo + P.alpha, l1);
-    const uint64_t y = (t >= lo && t < hi) ? d[(size_t)t * N + c] : Y[((size_t)j * T + t) * N + c];
-    const uint32_t y0 = (uint32_t)(y & kLo30), y1 = (uint32_t)(y >> 30);
-    a0.mac(y0, y1, evk[(((size_t)j * 2 + 0) * P.ntot + g) * N + c]);
-    a1.mac(y0, y1, evk[(((size_t)j * 2 + 1) * P.ntot + g) * N + c]);
+    uint64_t y[kPerThread];
+    if (t >= lo && t < hi) {  // the own digit: the input tower
+#pragma unroll
+      for (uint32_t i = 0; i < kPerThread; i++) y[i] = d[(size_t)t * N + base + threadIdx.x + 256 * i];
+    } else {
+      const uint64_t *src = Y + ((size_t)j * T + t) * N + base;
+      __syncthreads();  // the previous digit's words are read
+      for (uint32_t e = threadIdx.x; e < kTileWords; e += 256) s[e] = src[e];
+      __syncthreads();
+      npass<false, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, ~0u, m.q);
+#pragma unroll
+      for (uint32_t i = 0; i < kPerThread; i++) y[i] = csub(csub(s[threadIdx.x + 256 * i], 2 * m.q), m.q);
+    }
+    const uint64_t *e0 = evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + base;
+    const uint64_t *e1 = evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + base;
+#pragma unroll
+    for (uint32_t i = 0; i < kPerThread; i++) {
+      const uint32_t y0 = (uint32_t)(y[i] & kLo30), y1 = (uint32_t)(y[i] >> 30);
+      a0[i].mac(y0, y1, e0[threadIdx.x + 256 * i]);
+      a1[i].mac(y0, y1, e1[threadIdx.x + 256 * i]);
+    }
   }
-  acc[((size_t)0 * T + t) * N + c] = shoup(redc(a0.sum(), m), m.r64, m.r64s, m.q);
-  acc[((size_t)1 * T + t) * N + c] = shoup(redc(a1.sum(), m), m.r64, m.r64s, m.q);
+  uint64_t v0[kPerThread], v1[kPerThread];
+#pragma unroll
+  for (uint32_t i = 0; i < kPerThread; i++) {
+    v0[i] = shoup(redc(a0[i].sum(), m), m.r64, m.r64s, m.q);
+    v1[i] = shoup(redc(a1[i].sum(), m), m.r64, m.r64s, m.q);
+  }
+  if (t < l1) {
+#pragma unroll
+    for (uint32_t i = 0; i < kPerThread; i++) {
+      acc[((size_t)0 * T + t) * N + base + threadIdx.x + 256 * i] = v0[i];
+      acc[((size_t)1 * T + t) * N + base + threadIdx.x + 256 * i] = v1[i];
+    }
+    return;
+  }
+  __syncthreads();  // every read of s and of the forward twiddles is done
+#pragma unroll
+  for (uint32_t i = 0; i < kPerThread; i++) {
+    s[threadIdx.x + 256 * i] = v0[i];
+    s[kTileWords + threadIdx.x + 256 * i] = v1[i];
+  }
+  stage_row_tw(tws, P.tw_inv + (size_t)g * N, N, row0);
+  __syncthreads();
+  npass<true, true>(s, tws, 8, 2 * kRowsPerTile, 1, kRowWords, kRowWords, kRowsPerTile - 1, m.q);
+  const uint32_t k = t - l1, K = P.num_p;
+  for (uint32_t e = threadIdx.x; e < 2 * kTileWords; e += 256) {
+    const uint32_t h = e / kTileWords;
+    XP[((size_t)h * K + k) * N + base + (e - h * kTileWords)] = s[e];  // [0, 2q): the column pass finishes
+  }
 }
 
 // ------------------------------------------------------------ ModDown P2
@@ -417,15 +479,32 @@ __global__ __launch_bounds__(256) void k_bconv_down(Dev64 P, uint32_t level, con
   }
 }
 
-// ------------------------------------------------------------ ModDown P4
-// out_s[i] = (acc_s[i] - what_s[i]) [P^-1]_{q_i}.  grid (N / 256, l+1, 2).
-__global__ __launch_bounds__(256) void k_moddown_final(Dev64 P, uint32_t level, const uint64_t *__restrict__ acc,
-                                                       const uint64_t *__restrict__ W, uint64_t *__restrict__ out) {
-  const uint32_t N = 1u << P.log_n, i = blockIdx.y, s = blockIdx.z, l1 = level + 1, T = l1 + P.num_p;
-  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+// ------------------------------------------------------------ ModDown P3-P4
+// For Q tower i and a tile of rows: the forward row pass of both converted
+// polynomials w_s (column pass done before), then
+// out_s[i] = (acc_s[i] - w_s[i]) [P^-1]_{q_i}.  grid (R / kRowsPerTile, l+1).
+__global__ __launch_bounds__(256) void k_row_moddown(Dev64 P, uint32_t level, const uint64_t *__restrict__ acc,
+                                                     const uint64_t *__restrict__ W, uint64_t *__restrict__ out) {
+  __shared__ uint64_t s[2 * kTileWords];
+  __shared__ uint4 tws[kTileWords];
+  const uint32_t N = 1u << P.log_n, i = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
   const Mod64 m = P.mods[i];
-  const uint64_t v = sub_mod(acc[((size_t)s * T + i) * N + c], W[((size_t)s * l1 + i) * N + c], m.q);
-  out[((size_t)s * l1 + i) * N + c] = shoup(v, P.pinv[2 * i], P.pinv[2 * i + 1], m.q);
+  const uint32_t row0 = blockIdx.x * kRowsPerTile;
+  const size_t base = (size_t)row0 * kRowWords;
+  stage_row_tw(tws, P.tw_fwd + (size_t)i * N, N, row0);
+  for (uint32_t e = threadIdx.x; e < 2 * kTileWords; e += 256) {
+    const uint32_t h = e / kTileWords;
+    s[e] = W[((size_t)h * l1 + i) * N + base + (e - h * kTileWords)];
+  }
+  __syncthreads();
+  npass<false, true>(s, tws, 8, 2 * kRowsPerTile, 1, kRowWords, kRowWords, kRowsPerTile - 1, m.q);
+  const uint64_t pi = P.pinv[2 * i], pis = P.pinv[2 * i + 1];
+  for (uint32_t e = threadIdx.x; e < 2 * kTileWords; e += 256) {
+    const uint32_t h = e / kTileWords;
+    const size_t o = base + (e - h * kTileWords);
+    const uint64_t w = csub(csub(s[e], 2 * m.q), m.q);
+    out[((size_t)h * l1 + i) * N + o] = shoup(sub_mod(acc[((size_t)h * T + i) * N + o], w, m.q), pi, pis, m.q);
+  }
 }
 
 // ------------------------------------------------------------ host side
@@ -614,10 +693,13 @@ void free_plan(ks64_plan *pl) {
   pl->allocs.clear();
 }
 
-// One pass direction over a list of towers, split into launches of kList.
+// One transform direction over a list of towers, split into launches of
+// kList.  col_only: the column pass alone (forward: its first pass, words
+// left in [0, 4q) for a fused row pass; inverse: its second pass, reading
+// words in [0, 2q) that a fused row pass wrote).
 hipError_t transform(const ks64_plan *pl, bool inverse, const uint64_t *src, uint64_t *dst,
                      const std::vector<uint32_t> &so, const std::vector<uint32_t> &dof,
-                     const std::vector<uint32_t> &g, hipStream_t st) {
+                     const std::vector<uint32_t> &g, hipStream_t st, bool col_only = false) {
   const uint32_t N = pl->n, R = N / kRowWords;
   for (size_t b = 0; b < so.size(); b += kList) {
     List64 L{};
@@ -628,7 +710,10 @@ hipError_t transform(const ks64_plan *pl, bool inverse, const uint64_t *src, uin
       L.g[i] = (uint16_t)g[b + i];
     }
     const dim3 grow(R / kRowsPerTile, L.count), gcol(kRowWords / kColsPerTile, L.count);
-    if (!inverse) {  // column pass (large distances) first, in place into dst
+    if (col_only) {
+      if (!inverse) hipLaunchKernelGGL(k_col<false>, gcol, dim3(256), 0, st, pl->dev, L, src, dst);
+      else hipLaunchKernelGGL(k_col<true>, gcol, dim3(256), 0, st, pl->dev, L, src, dst);
+    } else if (!inverse) {  // column pass (large distances) first, in place into dst
       hipLaunchKernelGGL(k_col<false>, gcol, dim3(256), 0, st, pl->dev, L, src, dst);
       List64 L2 = L;
       for (uint32_t i = 0; i < L.count; i++) L2.src[i] = L.dst[i];
@@ -772,15 +857,17 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
       g.push_back(t <= level ? t : pl->num_q + (t - L1));
     }
   }
-  if (transform(pl, false, Y, Y, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
-  // P4/P5: key multiply-accumulate over the digits
-  hipLaunchKernelGGL(k_keymac, dim3(blocks, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC);
+  if (transform(pl, false, Y, Y, so, dof, g, st, true) != hipSuccess) return KS_ERR_DEVICE;
+  // P3 row pass, P4/P5 key multiply-accumulate over the digits; for the K
+  // special towers also ModDown P1's inverse row pass (into XP)
+  const uint32_t rtiles = N / kRowWords / kRowsPerTile;
+  hipLaunchKernelGGL(k_row_mac, dim3(rtiles, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC, XP);
   if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
-  // ModDown P1: INTT of the K special towers of both polynomials
+  // ModDown P1: the inverse column pass of the K special towers of both polynomials
   so.clear(); dof.clear(); g.clear();
   for (uint32_t s = 0; s < 2; s++)
-    for (uint32_t k = 0; k < K; k++) { so.push_back(s * T + L1 + k); dof.push_back(s * K + k); g.push_back(pl->num_q + k); }
-  if (transform(pl, true, ACC, XP, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
+    for (uint32_t k = 0; k < K; k++) { so.push_back(s * K + k); dof.push_back(s * K + k); g.push_back(pl->num_q + k); }
+  if (transform(pl, true, XP, XP, so, dof, g, st, true) != hipSuccess) return KS_ERR_DEVICE;
   // P2: conversion P -> Q_l
   const dim3 gdn(blocks, 2, (L1 + kTgtGroup - 1) / kTgtGroup);
   if (K <= 8) hipLaunchKernelGGL(k_bconv_down<8>, gdn, dim3(256), 0, st, pl->dev, level, XP, W);
@@ -792,8 +879,8 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   so.clear(); dof.clear(); g.clear();
   for (uint32_t s = 0; s < 2; s++)
     for (uint32_t i = 0; i < L1; i++) { so.push_back(s * L1 + i); dof.push_back(s * L1 + i); g.push_back(i); }
-  if (transform(pl, false, W, W, so, dof, g, st) != hipSuccess) return KS_ERR_DEVICE;
-  hipLaunchKernelGGL(k_moddown_final, dim3(blocks, L1, 2), dim3(256), 0, st, pl->dev, level, ACC, W, out);
+  if (transform(pl, false, W, W, so, dof, g, st, true) != hipSuccess) return KS_ERR_DEVICE;
+  hipLaunchKernelGGL(k_row_moddown, dim3(rtiles, L1), dim3(256), 0, st, pl->dev, level, ACC, W, out);
   return hipGetLastError() == hipSuccess ? KS_OK : KS_ERR_DEVICE;
 }
 
