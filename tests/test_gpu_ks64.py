@@ -5,7 +5,8 @@ arithmetic).  Cases: the NTT per limb for N = 2^12..2^17; the plain
 workload at every level with real keys (decrypted); partial digits,
 dnum = 1, K != alpha, alpha = 1; the longest sums (dnum 16, alpha = K = 32)
 with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17, full
-size; error paths.
+size, and BTS3 below its top level (a partial digit at N = 2^17); error
+paths.
 """
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -147,6 +148,27 @@ def bts_cases():
         wants = dict(zip(cases, ex.map(lambda c: o64.keyswitch(c[0], c[1], c[0].num_q - 1, c[2], c[3]),
                                        cases.values())))
     return {k: v + (wants[k],) for k, v in cases.items()}
+
+
+def test_bts3_below_the_top_level(ks):
+    """BTS3 at l+1 = 41: the last digit partial (15, 15, 11 towers), so the
+    conversion and the fused row passes see a digit shorter than alpha at
+    N = 2^17."""
+    log_n, num_q, dnum, num_p = BTS["bts3"]
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    level = 40
+    evk = uniform_evk64(mods, dnum, p.n, 977)
+    d = uniform64(mods[:level + 1], p.n, 978)
+    say("[ks64 bts3 l+1=41] oracle")
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(log_n, num_q, dnum, num_p)
+    say("[ks64 bts3 l+1=41] gpu")
+    got = host(plan.keyswitch(dev(evk), level, dev(d)))
+    torch.cuda.synchronize()
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (bad[:5], len(bad))
+    plan.close()
 
 
 @pytest.mark.parametrize("name", list(BTS))
