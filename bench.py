@@ -793,7 +793,7 @@ def main():
                               "stage_bytes_frac": round(tot_bytes * ks_per_s / (HBM_PEAK_GBS * 1e9), 4)}
     res["stages"] = stages
     if args.batch:
-        res["batched"] = batched_rate(ks, tune, tuner, plan, evks, mods, args.batch, max(5, args.steps // 20), np,
+        res["batched"] = batched_rate(ks, tune, tuner, plan, evks, mods, args.batch, max(20, args.steps // 10), np,
                                       torch, synth)
         bk = res["batched"]["ks_per_s"]
         # HBM rates of the batched run: compulsory bytes (every input and
@@ -816,7 +816,7 @@ def main():
     if args.mixed:
         res["mixed_batches"] = {}
         for dn in (2, 3, 4):
-            res["mixed_batches"][f"dnum{dn}"] = mixed_rate(ks, tune, tuner, dn, max(3, args.steps // 20), np, torch,
+            res["mixed_batches"][f"dnum{dn}"] = mixed_rate(ks, tune, tuner, dn, max(10, args.steps // 20), np, torch,
                                                            synth)
     if args.serve_requests:
         res["serving"] = serving_rate(ks, tune, tuner, args.serve_requests, np, torch, synth)
