@@ -92,7 +92,12 @@ def test_plain_workload_every_level_decrypts(ks, level):
 
 
 SHAPES = [(13, 10, 3, 0, 9), (13, 10, 3, 0, 5), (14, 8, 1, 0, 7), (13, 9, 3, 2, 8), (12, 7, 7, 1, 6),
-          (12, 12, 2, 4, 11)]
+          (12, 12, 2, 4, 11),
+          # K > alpha: more ModDown sources than digit towers; a level with a
+          # one-tower last digit
+          (13, 8, 4, 6, 7), (13, 8, 4, 6, 4),
+          # N = 2^15 and 2^16 (column passes of 128 and 256 rows)
+          (15, 6, 2, 3, 5), (16, 6, 3, 2, 4)]
 
 
 @pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", SHAPES)
