@@ -82,7 +82,7 @@ def _cpu_run(count):
 
 def cpu_baseline(sample, per=2):
     """The oracle, untuned, on the host cores: one thread, then one process
-    per core of the machine's CPU share (at most 16), each running `per` key
+    per core of the host's CPU share (at most 16), each running `per` key
     switches of the same workload."""
     import multiprocessing as mp
     _cpu_prepare()

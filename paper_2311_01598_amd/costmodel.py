@@ -4,7 +4,7 @@ configuration, trained on the GPU by the library's own kernels
 (ks_mlp_forward / ks_mlp_mse_grad / ks_mlp_backward / ks_mlp_adam).
 
 Pruned search: rank every configuration by predicted time and time only the
-top M; exhaustive search (tune.exhaustive) stays as fallback and judge.
+top M; exhaustive search (tune.exhaustive) stays as fallback and arbiter.
 `default_model()` loads the weights trained on the timing database of this
 GPU (data/costmodel.npz, written by `tune train`), which the live tuner
 uses to prune.

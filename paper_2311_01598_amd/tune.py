@@ -12,7 +12,7 @@ against.  `Tuner` puts the result in the live path: it records the choice in
 the plan (ks_plan_set_tuned) and sets the plan's schedule to AUTO, so every
 later call of that shape runs with it.
 
-Command line (on a GPU machine):
+Command line (on a machine with the GPU):
     python -m paper_2311_01598_amd.tune collect --out timings.jsonl [--quick]
     python -m paper_2311_01598_amd.tune experiment --db timings.jsonl --out result.json
     python -m paper_2311_01598_amd.tune train --db timings.jsonl   # weights of the live tuner
@@ -161,7 +161,7 @@ class Tuner:
     """The autotuner in the live path.  tune(plan, level, count) returns the
     configuration for that call shape: the cached choice; else, with a cost
     model, the fastest of the model's top-M configurations timed on the GPU;
-    else (no model, or verify=True as the judge) every configuration timed.
+    else (no model, or verify=True as the arbiter) every configuration timed.
     The choice is recorded in the plan (install) and in the cache."""
 
     def __init__(self, cache=None, model=None, top_m=3, reps=5, device="gpu0", verify=False):
@@ -295,7 +295,7 @@ def report(rows, exp, commands=()):
         f"final standardised training loss {s['final_train_loss']:.2e}.", "",
         "Top-1 regret on the held-out workloads (time of the chosen configuration / exhaustive best - 1):", "",
         "| method | timings per workload | regret |", "|---|---|---|",
-        f"| exhaustive search (judge) | {s['configs']} | 0 |",
+        f"| exhaustive search (arbiter) | {s['configs']} | 0 |",
         f"| model pick (no timing) | 0 | {f(s['regret_model_pick'])} |",
         f"| model top-{s['top_m']}, timed | {s['top_m']} | {f(s['regret_pruned_top_m'])} |",
         f"| {s['top_m']} random configurations, timed | {s['top_m']} | {f(s['regret_random_top_m'])} |",

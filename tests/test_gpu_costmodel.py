@@ -163,7 +163,7 @@ def test_auto_resolves_tuned_entries(ks):
 
 
 def test_auto_runs_the_tuned_pick(ks, tmp_path):
-    """The tuner (exhaustive here, as the judge) records its pick in the plan;
+    """The tuner (exhaustive here, as the arbiter) records its pick in the plan;
     with the schedule AUTO a call of that shape resolves to the pick, launches
     that schedule's kernels, and returns the same words as the pick run
     explicitly and as the oracle.  Calls that run the OC order only
