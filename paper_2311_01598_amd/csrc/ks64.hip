@@ -48,7 +48,7 @@ constexpr uint32_t kMaxTowers = 128;
 constexpr uint32_t kList = 96;  // towers per transform launch
 constexpr uint32_t kRowWords = 256;
 constexpr uint32_t kRowsPerTile = 4;
-constexpr uint32_t kColsPerTile = 8;
+constexpr uint32_t kColsPerTile = 4;
 
 struct Mod64 {
   uint64_t q, qneg;   // modulus, -q^-1 mod 2^64
@@ -272,9 +272,11 @@ __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *
 // Column pass: tiles of kColsPerTile columns of R = N / 256 rows.  Forward:
 // row distance R/2 .. 1 (butterfly distance t = 256 x that); inverse: 1 ..
 // R/2, then N^-1.  Every stage uses entries [1, R) of the table, staged
-// once per tile.  Blocks are dealt to the 8 XCDs in turn; block x takes the
-// column tile (x % 8) * 4 + x / 8, so each XCD's L2 holds 32 whole
-// columns (256-byte row segments) of the limb.
+// once per tile.  Blocks are dealt to the 8 XCDs in turn; block x of the
+// B = 256 / kColsPerTile column tiles takes tile (x % 8) * (B / 8) + x / 8,
+// so each XCD's L2 holds 32 whole columns (256-byte row segments) of the
+// limb.  Four columns per tile (32-byte segments, 24 KB of LDS, six blocks
+// per CU) ran faster than two, eight or sixteen.
 template <bool INV>
 __global__ __launch_bounds__(256) void k_col(Dev64 P, List64 L, const uint64_t *src, uint64_t *dst) {
   __shared__ uint64_t s[512 * kColsPerTile];
