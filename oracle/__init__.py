@@ -9,7 +9,7 @@ Contents:
   * ``ks_oracle.c``   plain C (uint64 ``%`` arithmetic) key switching, NTT,
     basis conversion, key generation for 30-bit towers in 32-bit words;
   * ``ks_oracle64.c`` the same for ~60-bit towers in 64-bit words (exact
-    unsigned __int128 products reduced with ``%``);
+    unsigned __int128 products reduced with ``%``), with compressed keys;
   * ``core.py``       ctypes wrappers of the 32-bit oracle and exact
     big-integer checks (CRT, decryption noise bound) using Python integers;
   * ``core64.py``     ctypes wrappers of the 64-bit oracle;

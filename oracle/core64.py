@@ -35,6 +35,9 @@ def lib():
                                       ctypes.c_uint32]),
             "oracle64_keyswitch": (ctypes.c_int, [P, _U64P, ctypes.c_uint32, _U64P, _U64P, _U64P]),
             "oracle64_keygen": (ctypes.c_int, [P, _U64P, ctypes.c_uint64, _I8P, _I8P, _U64P]),
+            "oracle64_seeded_a": (ctypes.c_int, [P, _U64P, ctypes.c_uint64, _U64P]),
+            "oracle64_keygen_seeded": (ctypes.c_int, [P, _U64P, ctypes.c_uint64, ctypes.c_uint64, _I8P, _I8P,
+                                                      _U64P]),
             "oracle64_set_fault": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -138,6 +141,30 @@ def keygen(p, mods, seed):
     evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint64)
     h = lib().oracle64_keygen(ctypes.byref(p.c()), pm, int(seed), s.ctypes.data_as(_I8P),
                               s2.ctypes.data_as(_I8P), evk.ctypes.data_as(_U64P))
+    if h < 0:
+        raise ValueError("bad parameters")
+    return s, s2, evk, h
+
+
+def seeded_a(p, mods, a_seed):
+    """Key compression (Sec. IV-D): evk-shaped array whose a halves ([:, 1])
+    are regenerated from a_seed (x 2^-64 mod m of SplitMix64 at the word's
+    counter); the b halves are zero."""
+    mods_a, pm = _u64(np.array(mods, dtype=np.uint64))
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint64)
+    if lib().oracle64_seeded_a(ctypes.byref(p.c()), pm, int(a_seed), evk.ctypes.data_as(_U64P)) != 0:
+        raise ValueError("bad parameters")
+    return evk
+
+
+def keygen_seeded(p, mods, seed, a_seed):
+    """keygen with the a halves of seeded_a(a_seed): (s, s2, evk, h)."""
+    mods_a, pm = _u64(np.array(mods, dtype=np.uint64))
+    s = np.zeros(p.n, np.int8)
+    s2 = np.zeros(p.n, np.int8)
+    evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint64)
+    h = lib().oracle64_keygen_seeded(ctypes.byref(p.c()), pm, int(seed), int(a_seed), s.ctypes.data_as(_I8P),
+                                     s2.ctypes.data_as(_I8P), evk.ctypes.data_as(_U64P))
     if h < 0:
         raise ValueError("bad parameters")
     return s, s2, evk, h

@@ -155,6 +155,13 @@ int oracle64_keyswitch(const oracle_params *p, const uint64_t *moduli, uint32_t 
                        const uint64_t *d, uint64_t *out);
 int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t seed, int8_t *s, int8_t *s2,
                     uint64_t *evk);
+/* Key compression (Sec. IV-D) with 64-bit words: the a halves are
+ * x 2^-64 mod m_g for the SplitMix64 output x at the counter of
+ * oracle_seeded_a (t = (j (L+1+K) + g) N + k); keygen_seeded computes the b
+ * halves from them. */
+int oracle64_seeded_a(const oracle_params *p, const uint64_t *moduli, uint64_t a_seed, uint64_t *evk);
+int oracle64_keygen_seeded(const oracle_params *p, const uint64_t *moduli, uint64_t seed, uint64_t a_seed,
+                           int8_t *s, int8_t *s2, uint64_t *evk);
 void oracle64_set_fault(int fault);
 
 #ifdef __cplusplus

@@ -385,8 +385,9 @@ static uint64_t signed_mod64(int32_t v, uint64_t m) { return v >= 0 ? (uint64_t)
 /* s, s2 ternary; evk[j] = (b_j, a_j) with b_j = e_j - a_j s + g_j s2, g_j =
  * [P]_m on digit j's own q-limbs and 0 elsewhere (evaluation domain).
  * Returns h = the Hamming weight of s. */
-int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t seed, int8_t *s, int8_t *s2,
-                    uint64_t *evk) {
+/* seeded: the a halves already hold the generator's words (oracle64_seeded_a) */
+static int keygen64_impl(const oracle_params *p, const uint64_t *moduli, uint64_t seed, int seeded, int8_t *s,
+                         int8_t *s2, uint64_t *evk) {
   ks64_ctx c;
   if (ctx64_init(&c, p, moduli, p->num_q - 1) != 0) return -1;
   const uint32_t n = c.n, EL = c.L1 + c.K;
@@ -419,11 +420,41 @@ int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t see
       uint64_t *b = evk + (((size_t)j * 2 + 0) * EL + g) * n;
       uint64_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
       for (uint32_t z = 0; z < n; z++) {
-        a[z] = rng64_below(&r, m);
+        if (!seeded) a[z] = rng64_below(&r, m);
         b[z] = addmod64(submod64(eh[z], mulmod64(a[z], sh[z], m), m), mulmod64(gad, s2h[z], m), m);
       }
     }
   }
   free(sh); free(s2h); free(eh); free(e);
   return h;
+}
+
+int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t seed, int8_t *s, int8_t *s2,
+                    uint64_t *evk) {
+  return keygen64_impl(p, moduli, seed, 0, s, s2, evk);
+}
+
+/* Key compression (Sec. IV-D) with 64-bit words: word (j, g, k) of the a
+ * halves is x 2^-64 mod m_g for the SplitMix64 output x at counter
+ * t = (j (L+1+K) + g) N + k (oracle_splitmix_at, the 32-bit oracle's
+ * generator): computed here as (x mod m) times the inverse of 2^64 mod m. */
+int oracle64_seeded_a(const oracle_params *p, const uint64_t *moduli, uint64_t a_seed, uint64_t *evk) {
+  if (!p || !moduli || !evk || p->num_q == 0 || p->dnum == 0 || p->num_p == 0) return -1;
+  const uint32_t n = 1u << p->log_n, EL = p->num_q + p->num_p;
+  for (uint32_t g = 0; g < EL; g++) {
+    const uint64_t m = moduli[g];
+    const uint64_t r64 = (uint64_t)(((u128)1 << 64) % m), inv = oracle64_invmod(r64, m);
+    for (uint32_t j = 0; j < p->dnum; j++) {
+      uint64_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
+      for (uint32_t k = 0; k < n; k++)
+        a[k] = mulmod64(oracle_splitmix_at(a_seed, ((uint64_t)j * EL + g) * n + k) % m, inv, m);
+    }
+  }
+  return 0;
+}
+
+int oracle64_keygen_seeded(const oracle_params *p, const uint64_t *moduli, uint64_t seed, uint64_t a_seed,
+                           int8_t *s, int8_t *s2, uint64_t *evk) {
+  if (oracle64_seeded_a(p, moduli, a_seed, evk) != 0) return -1;
+  return keygen64_impl(p, moduli, seed, 1, s, s2, evk);
 }

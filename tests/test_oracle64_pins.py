@@ -17,13 +17,16 @@ itself:
 - ModDown: the big-integer identity out = (C - [C]_P)/P - v, v in [0, K);
 - the key switch: decryption within the bound derived in
   test_oracle_keyswitch.py (it holds for any word size), d = 0 gives 0, and
-  planted mistakes break the bound.
+  planted mistakes break the bound;
+- compressed keys (Sec. IV-D): every a-half word satisfies a 2^64 = x
+  (mod m) for the generator's output x at its counter, the words are
+  uniform, and a key built on them decrypts within the bound.
 """
 import numpy as np
 import pytest
 
 import oracle
-from oracle import core64 as o64
+from oracle import core, core64 as o64
 
 
 def _sieve(limit):
@@ -255,3 +258,52 @@ def test_planted_mistakes_break_the_bound(fault):
         o64.set_fault(0)
     r = o64.decrypt_residual(p, mods, 3, d, out, s, s2)
     assert max(abs(v) for v in r) > oracle.noise_bound(p, mods, 3, h)
+
+
+# ---- key compression with 64-bit words (Sec. IV-D) -------------------------
+# Word (j, g, k) of the a halves is x 2^-64 mod m_g for the SplitMix64 output
+# x at counter (j (L+1+K) + g) N + k: pinned by the defining property
+# a 2^64 = x (mod m_g) on every word (the generator itself is pinned against
+# its published outputs in test_oracle_seeded.py), uniformity, and
+# decryption of a key switch with a key built on them.
+
+def test_seeded_a64_words_satisfy_the_defining_property():
+    p = oracle.Params(6, 3, 2, 2)
+    mods = [int(v) for v in o64.moduli(p)]
+    ev = o64.seeded_a(p, mods, 0x5eed)
+    EL = p.num_q + p.num_p
+    for j in range(p.dnum):
+        for g in range(EL):
+            m = mods[g]
+            for k in range(p.n):
+                x = core.splitmix_at(0x5eed, (j * EL + g) * p.n + k)
+                a = int(ev[j, 1, g, k])
+                assert a < m and (a * (1 << 64) - x) % m == 0, (j, g, k)
+    assert not ev[:, 0].any()
+
+
+def test_seeded_a64_is_uniform():
+    p = oracle.Params(12, 4, 2, 2)
+    mods = [int(v) for v in o64.moduli(p)]
+    ev = o64.seeded_a(p, mods, 91)
+    for g in range(p.num_q + p.num_p):
+        m = mods[g]
+        for j in range(p.dnum):
+            a = ev[j, 1, g].astype(np.float64)
+            counts = np.bincount((a * 16 / m).astype(np.int64), minlength=16)
+            exp = p.n / 16
+            chi2 = float(((counts - exp) ** 2 / exp).sum())
+            assert chi2 < 45.0, (g, j, chi2)  # 15 dof: p < 1e-4 under uniformity
+    assert np.mean(ev[:, 1] == o64.seeded_a(p, mods, 92)[:, 1]) < 1e-3
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", [(10, 4, 2, 2, 3), (9, 9, 3, 2, 5)])
+def test_seeded_key64_decrypts_within_bound(log_n, num_q, dnum, num_p, level):
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    s, s2, evk, h = o64.keygen_seeded(p, mods, 17, 4242)
+    assert np.array_equal(evk[:, 1], o64.seeded_a(p, mods, 4242)[:, 1])
+    d = _uniform64(mods[:level + 1], p.n, 5)
+    out = o64.keyswitch(p, mods, level, evk, d)
+    r = o64.decrypt_residual(p, mods, level, d, out, s, s2)
+    assert max(abs(v) for v in r) <= oracle.noise_bound(p, mods, level, h)
