@@ -478,6 +478,16 @@ ks_status_t ks64_workspace_size(ks64_plan_t plan, uint32_t level, size_t *bytes)
  * Output canonical, evaluation domain. */
 ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level, const uint64_t *in,
                            uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
+/* Key switch with a compressed key (Sec. IV-D): evk_b holds the b halves
+ * only, [dnum][L+1+K][N] (device, uint64, 16-byte aligned); the a half of
+ * digit j's key row g is regenerated on the device, word k being x 2^-64
+ * mod m_g for the SplitMix64 output x (Steele, Lea and Flood 2014) of
+ * a_seed at counter t = (j (L+1+K) + g) N + k.  Everything else, including
+ * the workspace and the errors, as ks64_keyswitch; out overlaps neither
+ * evk_b nor the workspace. */
+ks_status_t ks64_keyswitch_seeded(ks64_plan_t plan, const uint64_t *evk_b, uint64_t a_seed, uint32_t level,
+                                  const uint64_t *in, uint64_t *out, void *workspace, size_t workspace_bytes,
+                                  void *stream);
 /* In-place forward (inverse = 0) or inverse NTT of `count` limbs of data
  * [count][N]; limb c uses modulus number g[c] (host array, order q_0..q_L,
  * p_0..p_{K-1}). */

@@ -619,6 +619,8 @@ _SIGS64 = {
     "ks64_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "ks64_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "ks64_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
+    "ks64_keyswitch_seeded": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP,
+                                             ctypes.c_size_t, _VP]),
 }
 for _name, (_res, _args) in _SIGS64.items():
     _f = getattr(_lib, _name)
@@ -673,6 +675,14 @@ def ks64_keyswitch(plan, evk, level, inp, out, workspace, workspace_bytes=None, 
     _check(st, "ks64_keyswitch")
 
 
+def ks64_keyswitch_seeded(plan, evk_b, a_seed, level, inp, out, workspace, workspace_bytes=None, stream=None):
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    st = _lib.ks64_keyswitch_seeded(plan, _ptr(evk_b), int(a_seed) & 0xFFFFFFFFFFFFFFFF, int(level), _ptr(inp),
+                                    _ptr(out), _ptr(workspace), int(workspace_bytes), _stream(stream))
+    _check(st, "ks64_keyswitch_seeded")
+
+
 def ks64_ntt(plan, g, inverse, data, stream=None):
     g = list(g)
     arr = (ctypes.c_uint32 * max(1, len(g)))(*g)
@@ -704,6 +714,17 @@ class Plan64:
         if workspace is None:
             workspace = self.workspace(level, d.device)
         ks64_keyswitch(self.handle, evk, level, d, out, workspace, stream=stream)
+        return out
+
+    def keyswitch_seeded(self, evk_b, a_seed, level, d, out=None, workspace=None, stream=None):
+        """Key switch with a compressed key: evk_b [dnum][L+1+K][N] holds the b
+        halves, the a halves are regenerated from a_seed on the device."""
+        import torch
+        if out is None:
+            out = torch.empty((2, level + 1, self.n), dtype=torch.int64, device=d.device)
+        if workspace is None:
+            workspace = self.workspace(level, d.device)
+        ks64_keyswitch_seeded(self.handle, evk_b, a_seed, level, d, out, workspace, stream=stream)
         return out
 
     def ntt(self, data, g, inverse=False, stream=None):

@@ -121,6 +121,21 @@ __device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
   return csub(t.hi + __umul64hi(u, m.q) + (lo < t.lo ? 1u : 0u), m.q);
 }
 
+// Compressed keys (Sec. IV-D): the a half of digit j's key row g is
+// regenerated where it is consumed.  Word k is x 2^-64 mod m for the
+// SplitMix64 output x (Steele, Lea and Flood 2014) at counter
+// t = (j ntot + g) N + k: the mix of seed + (t + 1) gamma, then one
+// Montgomery reduction of x (below 2^64 < m 2^64), canonical.
+__device__ __forceinline__ uint64_t seeded_a64(uint64_t seed, uint64_t t, const Mod64 &m) {
+  uint64_t z = seed + (t + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  Acc128 x;
+  x.lo = z;
+  return redc(x, m);
+}
+
 // ------------------------------------------------------------ transforms
 // The twiddle of the butterfly (j, j + t) is entry N / (2t) + j / (2t) of the
 // table.  A pass transforms sequences of M words (M = 256 in the row pass,
@@ -388,9 +403,13 @@ __global__ __launch_bounds__(256) void k_bconv_up(Dev64 P, uint32_t level, const
 // grid (R / kRowsPerTile, T); each thread owns kRowWords * kRowsPerTile /
 // 256 words of the tile.
 constexpr uint32_t kTileWords = kRowsPerTile * kRowWords, kPerThread = kTileWords / 256;
+// SEEDED: evk holds the b halves only, [dnum][ntot][N], and the a halves are
+// regenerated from a_seed (seeded_a64).
+template <bool SEEDED>
 __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const uint64_t *__restrict__ d,
                                                  const uint64_t *__restrict__ Y, const uint64_t *__restrict__ evk,
-                                                 uint64_t *__restrict__ acc, uint64_t *__restrict__ XP) {
+                                                 uint64_t a_seed, uint64_t *__restrict__ acc,
+                                                 uint64_t *__restrict__ XP) {
   __shared__ uint64_t s[2 * kTileWords];
   __shared__ uint4 tws[kTileWords];
   const uint32_t N = 1u << P.log_n, t = blockIdx.y, l1 = level + 1, T = l1 + P.num_p;
@@ -415,13 +434,16 @@ __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const 
 #pragma unroll
       for (uint32_t i = 0; i < kPerThread; i++) y[i] = csub(csub(s[threadIdx.x + 256 * i], 2 * m.q), m.q);
     }
-    const uint64_t *e0 = evk + (((size_t)j * 2 + 0) * P.ntot + g) * N + base;
-    const uint64_t *e1 = evk + (((size_t)j * 2 + 1) * P.ntot + g) * N + base;
+    const size_t row = (size_t)j * (SEEDED ? 1 : 2) * P.ntot + g;  // b half of digit j, key row g
+    const uint64_t *e0 = evk + row * N + base;
+    const uint64_t *e1 = evk + (row + P.ntot) * N + base;  // a half (full keys)
 #pragma unroll
     for (uint32_t i = 0; i < kPerThread; i++) {
       const uint32_t y0 = (uint32_t)(y[i] & kLo30), y1 = (uint32_t)(y[i] >> 30);
+      const uint64_t ak = SEEDED ? seeded_a64(a_seed, ((size_t)j * P.ntot + g) * N + base + threadIdx.x + 256 * i, m)
+                                 : e1[threadIdx.x + 256 * i];
       a0[i].mac(y0, y1, e0[threadIdx.x + 256 * i]);
-      a1[i].mac(y0, y1, e1[threadIdx.x + 256 * i]);
+      a1[i].mac(y0, y1, ak);
     }
   }
   uint64_t v0[kPerThread], v1[kPerThread];
@@ -818,8 +840,15 @@ ks_status_t ks64_ntt(ks64_plan_t plan, uint32_t count, const uint32_t *g, int in
                                                                                                      : KS_ERR_DEVICE;
 }
 
-ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level, const uint64_t *in,
-                           uint64_t *out, void *workspace, size_t workspace_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// The key switch with a full key (seeded = false, evk [dnum][2][L+1+K][N])
+// or a compressed one (evk the b halves [dnum][L+1+K][N], a halves from
+// a_seed).
+ks_status_t keyswitch64(ks64_plan_t plan, const uint64_t *evk, bool seeded, uint64_t a_seed, uint32_t level,
+                        const uint64_t *in, uint64_t *out, void *workspace, size_t workspace_bytes, void *stream) {
   if (!plan || !evk || !in || !out || !workspace) return KS_ERR_INVALID_ARG;
   const ks64_plan *pl = plan;
   if (level >= pl->num_q) return KS_ERR_INVALID_ARG;
@@ -829,7 +858,7 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   if (workspace_bytes < need) return KS_ERR_BUDGET;
   const uint32_t N = pl->n, L1 = level + 1, K = pl->num_p, T = L1 + K, D = (L1 + pl->alpha - 1) / pl->alpha;
   const size_t lb = (size_t)N * sizeof(uint64_t);
-  const size_t evk_b = (size_t)pl->dnum * 2 * pl->ntot * lb;
+  const size_t evk_b = (size_t)pl->dnum * (seeded ? 1 : 2) * pl->ntot * lb;
   if (overlaps(out, 2 * L1 * lb, in, L1 * lb) || overlaps(out, 2 * L1 * lb, evk, evk_b) ||
       overlaps(out, 2 * L1 * lb, workspace, workspace_bytes) || overlaps(workspace, workspace_bytes, in, L1 * lb) ||
       overlaps(workspace, workspace_bytes, evk, evk_b))
@@ -865,7 +894,11 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   // P3 row pass, P4/P5 key multiply-accumulate over the digits; for the K
   // special towers also ModDown P1's inverse row pass (into XP)
   const uint32_t rtiles = N / kRowWords / kRowsPerTile;
-  hipLaunchKernelGGL(k_row_mac, dim3(rtiles, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, ACC, XP);
+  if (seeded)
+    hipLaunchKernelGGL(k_row_mac<true>, dim3(rtiles, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, a_seed, ACC, XP);
+  else
+    hipLaunchKernelGGL(k_row_mac<false>, dim3(rtiles, T), dim3(256), 0, st, pl->dev, level, in, Y, evk, a_seed, ACC,
+                       XP);
   if (hipGetLastError() != hipSuccess) return KS_ERR_DEVICE;
   // ModDown P1: the inverse column pass of the K special towers of both polynomials
   so.clear(); dof.clear(); g.clear();
@@ -886,6 +919,21 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
   if (transform(pl, false, W, W, so, dof, g, st, true) != hipSuccess) return KS_ERR_DEVICE;
   hipLaunchKernelGGL(k_row_moddown, dim3(rtiles, L1), dim3(256), 0, st, pl->dev, level, ACC, W, out);
   return hipGetLastError() == hipSuccess ? KS_OK : KS_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level, const uint64_t *in,
+                           uint64_t *out, void *workspace, size_t workspace_bytes, void *stream) {
+  return keyswitch64(plan, evk, false, 0, level, in, out, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks64_keyswitch_seeded(ks64_plan_t plan, const uint64_t *evk_b, uint64_t a_seed, uint32_t level,
+                                  const uint64_t *in, uint64_t *out, void *workspace, size_t workspace_bytes,
+                                  void *stream) {
+  return keyswitch64(plan, evk_b, true, a_seed, level, in, out, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

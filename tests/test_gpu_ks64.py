@@ -5,8 +5,10 @@ arithmetic).  Cases: the NTT per limb for N = 2^12..2^17; the plain
 workload at every level with real keys (decrypted); partial digits,
 dnum = 1, K != alpha, alpha = 1; the longest sums (dnum 16, alpha = K = 32)
 with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17, full
-size, and BTS3 below its top level (a partial digit at N = 2^17); error
-paths.
+size, and BTS3 below its top level (a partial digit at N = 2^17); compressed
+keys (the a halves regenerated from a seed) with real seeded keys at every
+level (decrypted), against the expanded key for several shapes and BTS3 at
+full size; error paths.
 """
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -208,3 +210,58 @@ def test_error_paths(ks):
     with pytest.raises(ks.KsError) as e:
         ks.Plan64(12, 4, 2, 2, moduli=[(1 << 60) - 1] * 6)
     assert e.value.status == ks.KS_ERR_INVALID_ARG
+
+
+# ---- compressed keys (Sec. IV-D): b halves in memory, a halves from a seed --
+@pytest.mark.parametrize("level", [0, 2, 3])
+def test_seeded_real_keys_every_level_decrypts(ks, level):
+    p = oracle.Params(12, 4, 2, 2)
+    mods = o64.moduli(p)
+    s, s2, evk, h = o64.keygen_seeded(p, mods, seed=88, a_seed=0xA5EED)
+    d = uniform64(mods[:level + 1], p.n, 60 + level)
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(12, 4, 2, 2)
+    say(f"[ks64 seeded] level={level}")
+    got = host(plan.keyswitch_seeded(dev(np.ascontiguousarray(evk[:, 0])), 0xA5EED, level, dev(d)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+    r = o64.decrypt_residual(p, mods, level, d, got, s, s2)
+    assert max(abs(v) for v in r) <= oracle.noise_bound(p, mods, level, h)
+    plan.close()
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", [(13, 10, 3, 0, 9), (13, 8, 4, 6, 4), (12, 7, 7, 1, 6),
+                                                          (17, 45, 3, 15, 44)])
+def test_seeded_equals_the_expanded_key(ks, log_n, num_q, dnum, num_p, level):
+    """Uniform b halves with the a halves of a seed: the seeded key switch
+    equals the oracle's with the expanded key, every word (BTS3 at full
+    size included)."""
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    a_seed = 0x1234_5678_9abc_def0 + num_q
+    evk = o64.seeded_a(p, mods, a_seed)
+    evk[:, 0] = uniform_evk64(mods, dnum, p.n, 41 + num_q)[:, 0]
+    d = uniform64(mods[:level + 1], p.n, 42 + level)
+    say(f"[ks64 seeded] {log_n} {num_q} {dnum} {num_p} level={level} oracle")
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(log_n, num_q, dnum, num_p)
+    say(f"[ks64 seeded] {log_n} {num_q} {dnum} {num_p} level={level} gpu")
+    got = host(plan.keyswitch_seeded(dev(np.ascontiguousarray(evk[:, 0])), a_seed, level, dev(d)))
+    torch.cuda.synchronize()
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (bad[:5], len(bad))
+    plan.close()
+
+
+def test_seeded_error_paths(ks):
+    plan = ks.Plan64(12, 4, 2, 2)
+    n = plan.n
+    evk_b = torch.zeros((2, 6, n), dtype=torch.int64, device="cuda")
+    d = torch.zeros((4, n), dtype=torch.int64, device="cuda")
+    out = torch.empty((2, 4, n), dtype=torch.int64, device="cuda")
+    ws = plan.workspace(3)
+    for args in ((None, 1, 3, d, out, ws), (evk_b, 1, 4, d, out, ws), (evk_b, 1, 3, d, evk_b, ws)):
+        with pytest.raises(ks.KsError) as e:
+            ks.ks64_keyswitch_seeded(plan.handle, *args)
+        assert e.value.status == ks.KS_ERR_INVALID_ARG
+    plan.close()
