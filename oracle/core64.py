@@ -148,8 +148,9 @@ def keygen(p, mods, seed):
 
 def seeded_a(p, mods, a_seed):
     """Key compression (Sec. IV-D): evk-shaped array whose a halves ([:, 1])
-    are regenerated from a_seed (x 2^-64 mod m of SplitMix64 at the word's
-    counter); the b halves are zero."""
+    are regenerated from a_seed (X 2^-64 mod m for the 123-bit X formed by
+    the SplitMix64 outputs at counters 2t and 2t + 1 of the word's counter
+    t); the b halves are zero."""
     mods_a, pm = _u64(np.array(mods, dtype=np.uint64))
     evk = np.zeros((p.dnum, 2, p.num_q + p.num_p, p.n), np.uint64)
     if lib().oracle64_seeded_a(ctypes.byref(p.c()), pm, int(a_seed), evk.ctypes.data_as(_U64P)) != 0:

@@ -435,9 +435,12 @@ int oracle64_keygen(const oracle_params *p, const uint64_t *moduli, uint64_t see
 }
 
 /* Key compression (Sec. IV-D) with 64-bit words: word (j, g, k) of the a
- * halves is x 2^-64 mod m_g for the SplitMix64 output x at counter
- * t = (j (L+1+K) + g) N + k (oracle_splitmix_at, the 32-bit oracle's
- * generator): computed here as (x mod m) times the inverse of 2^64 mod m. */
+ * halves is X 2^-64 mod m_g for the 123-bit integer X = (x1 >> 5) 2^64 + x0,
+ * where x0 and x1 are the SplitMix64 outputs (oracle_splitmix_at, the 32-bit
+ * oracle's generator) at counters 2t and 2t + 1, t = (j (L+1+K) + g) N + k.
+ * One 64-bit output reduced mod a 60-bit prime would sit up to 2^-6 from
+ * uniform; X, uniform on [0, 2^123), sits below m / 2^125 < 2^-65.  Computed
+ * here as (X mod m) times the inverse of 2^64 mod m. */
 int oracle64_seeded_a(const oracle_params *p, const uint64_t *moduli, uint64_t a_seed, uint64_t *evk) {
   if (!p || !moduli || !evk || p->num_q == 0 || p->dnum == 0 || p->num_p == 0) return -1;
   const uint32_t n = 1u << p->log_n, EL = p->num_q + p->num_p;
@@ -446,8 +449,11 @@ int oracle64_seeded_a(const oracle_params *p, const uint64_t *moduli, uint64_t a
     const uint64_t r64 = (uint64_t)(((u128)1 << 64) % m), inv = oracle64_invmod(r64, m);
     for (uint32_t j = 0; j < p->dnum; j++) {
       uint64_t *a = evk + (((size_t)j * 2 + 1) * EL + g) * n;
-      for (uint32_t k = 0; k < n; k++)
-        a[k] = mulmod64(oracle_splitmix_at(a_seed, ((uint64_t)j * EL + g) * n + k) % m, inv, m);
+      for (uint32_t k = 0; k < n; k++) {
+        const uint64_t t = ((uint64_t)j * EL + g) * n + k;
+        const u128 X = ((u128)(oracle_splitmix_at(a_seed, 2 * t + 1) >> 5) << 64) | oracle_splitmix_at(a_seed, 2 * t);
+        a[k] = mulmod64((uint64_t)(X % m), inv, m);
+      }
     }
   }
   return 0;

@@ -261,11 +261,14 @@ def test_planted_mistakes_break_the_bound(fault):
 
 
 # ---- key compression with 64-bit words (Sec. IV-D) -------------------------
-# Word (j, g, k) of the a halves is x 2^-64 mod m_g for the SplitMix64 output
-# x at counter (j (L+1+K) + g) N + k: pinned by the defining property
-# a 2^64 = x (mod m_g) on every word (the generator itself is pinned against
-# its published outputs in test_oracle_seeded.py), uniformity, and
-# decryption of a key switch with a key built on them.
+# Word (j, g, k) of the a halves is X 2^-64 mod m_g, X = (x1 >> 5) 2^64 + x0
+# for the SplitMix64 outputs x0, x1 at counters 2t, 2t + 1 of the word's
+# counter t = (j (L+1+K) + g) N + k (123 bits, so the words sit below 2^-65
+# from uniform, where one 64-bit output mod a 60-bit prime would sit up to
+# 2^-6 away): pinned by the defining property a 2^64 = X (mod m_g) on every
+# word (the generator itself is pinned against its published outputs in
+# test_oracle_seeded.py), uniformity, and decryption of a key switch with a
+# key built on them.
 
 def test_seeded_a64_words_satisfy_the_defining_property():
     p = oracle.Params(6, 3, 2, 2)
@@ -276,7 +279,8 @@ def test_seeded_a64_words_satisfy_the_defining_property():
         for g in range(EL):
             m = mods[g]
             for k in range(p.n):
-                x = core.splitmix_at(0x5eed, (j * EL + g) * p.n + k)
+                t = (j * EL + g) * p.n + k
+                x = ((core.splitmix_at(0x5eed, 2 * t + 1) >> 5) << 64) + core.splitmix_at(0x5eed, 2 * t)
                 a = int(ev[j, 1, g, k])
                 assert a < m and (a * (1 << 64) - x) % m == 0, (j, g, k)
     assert not ev[:, 0].any()
