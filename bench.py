@@ -457,7 +457,13 @@ def bts_rate(ks, steps, np, torch, synth):
                           torch)
         cur["mp_64bit_words"] = {"ks_per_s": round(1 / s64, 1), "us_per_ks": round(s64 * 1e6, 2),
                                  "evk_mib": round(evk64.numel() * 8 / 2**20, 1)}
-        del evk64, d64, out64, ws64
+        # the same with compressed keys (b halves plus a seed)
+        evk64_b = evk64[:, 0].contiguous()
+        s64c = timed_calls(lambda r=0: p64.keyswitch_seeded(evk64_b, 78, level, d64, out=out64, workspace=ws64),
+                           max(5, steps // 4), torch)
+        cur["mp_64bit_words_compressed_keys"] = {"ks_per_s": round(1 / s64c, 1), "us_per_ks": round(s64c * 1e6, 2),
+                                                 "evk_mib": round(evk64_b.numel() * 8 / 2**20, 1)}
+        del evk64, evk64_b, d64, out64, ws64
         p64.close()
         res[name] = cur
     # the modulus of BTS3's 60-bit towers (45 + 15) in 30-bit towers: 90 + 30,

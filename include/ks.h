@@ -480,9 +480,11 @@ ks_status_t ks64_keyswitch(ks64_plan_t plan, const uint64_t *evk, uint32_t level
                            uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
 /* Key switch with a compressed key (Sec. IV-D): evk_b holds the b halves
  * only, [dnum][L+1+K][N] (device, uint64, 16-byte aligned); the a half of
- * digit j's key row g is regenerated on the device, word k being x 2^-64
- * mod m_g for the SplitMix64 output x (Steele, Lea and Flood 2014) of
- * a_seed at counter t = (j (L+1+K) + g) N + k.  Everything else, including
+ * digit j's key row g is regenerated on the device, word k being X 2^-64
+ * mod m_g for X = (x1 >> 5) 2^64 + x0, x0 and x1 the SplitMix64 outputs
+ * (Steele, Lea and Flood 2014) of a_seed at counters 2t and 2t + 1,
+ * t = (j (L+1+K) + g) N + k (123 bits: below 2^-65 from uniform mod a
+ * 60-bit prime).  Everything else, including
  * the workspace and the errors, as ks64_keyswitch; out overlaps neither
  * evk_b nor the workspace. */
 ks_status_t ks64_keyswitch_seeded(ks64_plan_t plan, const uint64_t *evk_b, uint64_t a_seed, uint32_t level,

@@ -122,17 +122,27 @@ __device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
 }
 
 // Compressed keys (Sec. IV-D): the a half of digit j's key row g is
-// regenerated where it is consumed.  Word k is x 2^-64 mod m for the
-// SplitMix64 output x (Steele, Lea and Flood 2014) at counter
-// t = (j ntot + g) N + k: the mix of seed + (t + 1) gamma, then one
-// Montgomery reduction of x (below 2^64 < m 2^64), canonical.
-__device__ __forceinline__ uint64_t seeded_a64(uint64_t seed, uint64_t t, const Mod64 &m) {
-  uint64_t z = seed + (t + 1) * 0x9e3779b97f4a7c15ull;
+// regenerated where it is consumed.  Word k is X 2^-64 mod m for the 123-bit
+// integer X = (x1 >> 5) 2^64 + x0, x0 and x1 the SplitMix64 outputs
+// (Steele, Lea and Flood 2014) at counters 2t and 2t + 1 of the word's
+// counter t = (j ntot + g) N + k; output c of seed s is the mix of
+// s + (c + 1) gamma.  X is below 2^123 < m 2^64, so one Montgomery reduction
+// gives the canonical residue; X's 123 bits keep the words below 2^-65 from
+// uniform (one 64-bit output would leave up to 2^-6 for a 60-bit prime).
+// The pre-mix state of output c is s + (c + 1) gamma, so consecutive
+// outputs step it by gamma and a thread's words (counters 512 apart) by
+// 512 gamma: no counter multiplies per word.
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
   z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  z ^= z >> 31;
+  return z ^ (z >> 31);
+}
+// z0: the state of output 2t, seed + (2t + 1) gamma.
+__device__ __forceinline__ uint64_t seeded_a64(uint64_t z0, const Mod64 &m) {
   Acc128 x;
-  x.lo = z;
+  x.lo = splitmix_mix(z0);
+  x.hi = splitmix_mix(z0 + kGamma) >> 5;
   return redc(x, m);
 }
 
@@ -437,11 +447,12 @@ __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const 
     const size_t row = (size_t)j * (SEEDED ? 1 : 2) * P.ntot + g;  // b half of digit j, key row g
     const uint64_t *e0 = evk + row * N + base;
     const uint64_t *e1 = evk + (row + P.ntot) * N + base;  // a half (full keys)
+    // generator state of word (j, g, base + threadIdx.x), compressed keys
+    const uint64_t z0 = a_seed + (2 * (((uint64_t)j * P.ntot + g) * N + base + threadIdx.x) + 1) * kGamma;
 #pragma unroll
     for (uint32_t i = 0; i < kPerThread; i++) {
       const uint32_t y0 = (uint32_t)(y[i] & kLo30), y1 = (uint32_t)(y[i] >> 30);
-      const uint64_t ak = SEEDED ? seeded_a64(a_seed, ((size_t)j * P.ntot + g) * N + base + threadIdx.x + 256 * i, m)
-                                 : e1[threadIdx.x + 256 * i];
+      const uint64_t ak = SEEDED ? seeded_a64(z0 + (uint64_t)(512 * i) * kGamma, m) : e1[threadIdx.x + 256 * i];
       a0[i].mac(y0, y1, e0[threadIdx.x + 256 * i]);
       a1[i].mac(y0, y1, ak);
     }
