@@ -397,13 +397,16 @@ def rotation_rate(ks, plan, evks, steps, np, torch, synth):
     return res
 
 
-BTS_SETS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+BTS_SETS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15),
+            "ark": (16, 24, 4, 6), "dprive": (16, 26, 3, 7)}
 
 
 def bts_rate(ks, steps, np, torch, synth):
-    """Key switches per second at the bootstrapping-scale parameter sets of
-    Table III (N = 2^17, 30-bit towers), one ciphertext at the top level per
-    call, keys rotating over 4 copies; OC and MP."""
+    """Key switches per second at the parameter sets of Table III (BTS1/2/3
+    at N = 2^17, ARK and DPRIVE at N = 2^16; tower counts as there), one
+    ciphertext at the top level per call, keys rotating over 4 copies: OC,
+    MP and DC with 30-bit towers, OC with compressed keys, and the 64-bit
+    path with full and compressed keys."""
     res = {}
     for name, (log_n, num_q, dnum, num_p) in BTS_SETS.items():
         plan = ks.Plan(log_n, num_q, dnum, num_p)
@@ -413,7 +416,7 @@ def bts_rate(ks, steps, np, torch, synth):
         d = torch.from_numpy(synth.uniform_limbs(mods[:num_q], n, synth.seed_for(31, 9)).view(np.int32)).cuda()
         out = torch.empty((2, num_q, n), dtype=torch.int32, device="cuda")
         cur = {"evk_mib": round(evks[0].numel() * 4 / 2**20, 1)}
-        for sched in ("oc", "mp"):
+        for sched in ("oc", "mp", "dc"):
             plan.configure(sched)
             ws = plan.workspace([level])
             for i in range(5):
@@ -429,6 +432,7 @@ def bts_rate(ks, steps, np, torch, synth):
             cur[sched] = {"ks_per_s": round(1e3 / ms, 1), "us_per_ks": round(ms * 1e3, 2)}
             del ws
         cur["oc_over_mp"] = round(cur["oc"]["ks_per_s"] / cur["mp"]["ks_per_s"], 3)
+        cur["oc_over_dc"] = round(cur["oc"]["ks_per_s"] / cur["dc"]["ks_per_s"], 3)
         # compressed keys (b halves of the same keys plus a seed)
         keys_b = [e[:, 0].contiguous() for e in evks]
         plan.configure("oc")

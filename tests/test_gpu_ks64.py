@@ -4,8 +4,8 @@ the 64-bit oracle, every output word (tolerance 0: exact modular
 arithmetic).  Cases: the NTT per limb for N = 2^12..2^17; the plain
 workload at every level with real keys (decrypted); partial digits,
 dnum = 1, K != alpha, alpha = 1; the longest sums (dnum 16, alpha = K = 32)
-with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17, full
-size, and BTS3 below its top level (a partial digit at N = 2^17); compressed
+with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17 and
+ARK/DPRIVE at N = 2^16, full size, and BTS3 below its top level (a partial digit at N = 2^17); compressed
 keys (the a halves regenerated from a seed) with real seeded keys at every
 level (decrypted), against the expanded key for several shapes and BTS3 at
 full size; error paths.
@@ -136,22 +136,22 @@ def test_longest_sums_every_word_at_m_minus_1(ks, log_n, num_q, dnum, num_p):
     plan.close()
 
 
-BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15)}
+BTS = {"bts1": (17, 28, 1, 28), "bts2": (17, 40, 2, 20), "bts3": (17, 45, 3, 15),
+       "ark": (16, 24, 4, 6), "dprive": (16, 26, 3, 7)}
 
 
 @pytest.fixture(scope="module")
 def bts_cases():
-    """Inputs and oracle outputs of Table III's three bootstrapping sets at
-    full size (the three oracle runs in threads: the C oracle releases the
-    GIL)."""
+    """Inputs and oracle outputs of Table III's five sets at full size (the
+    oracle runs in threads: the C oracle releases the GIL)."""
     cases = {}
     for name, (log_n, num_q, dnum, num_p) in BTS.items():
         p = oracle.Params(log_n, num_q, dnum, num_p)
         mods = o64.moduli(p)
         cases[name] = (p, mods, uniform_evk64(mods, dnum, p.n, 900 + num_q),
                        uniform64(mods[:num_q], p.n, 901 + num_q))
-    say("[ks64 bts] computing three oracle key switches at N=2^17")
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    say("[ks64 bts] computing five oracle key switches (N = 2^17 and 2^16)")
+    with ThreadPoolExecutor(max_workers=5) as ex:
         wants = dict(zip(cases, ex.map(lambda c: o64.keyswitch(c[0], c[1], c[0].num_q - 1, c[2], c[3]),
                                        cases.values())))
     return {k: v + (wants[k],) for k, v in cases.items()}
