@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const 
     }
     const size_t row = (size_t)j * (SEEDED ? 1 : 2) * P.ntot + g;  // b half of digit j, key row g
     const uint64_t *e0 = evk + row * N + base;
-    const uint64_t *e1 = evk + (row + P.ntot) * N + base;  // a half (full keys)
+    const uint64_t *e1 = SEEDED ? nullptr : evk + (row + P.ntot) * N + base;  // a half (full keys)
     // generator state of word (j, g, base + threadIdx.x), compressed keys
     const uint64_t z0 = a_seed + (2 * (((uint64_t)j * P.ntot + g) * N + base + threadIdx.x) + 1) * kGamma;
 #pragma unroll
