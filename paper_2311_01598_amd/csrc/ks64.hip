@@ -4,10 +4,11 @@
 // towers, each stage's output in device memory.
 //
 // Arithmetic on uint64 residues below 2^60:
-//  - products with a constant (twiddles, conversion prescales, P^-1, N^-1):
-//    Shoup's method with the precomputed floor(w 2^64 / q), one 64-bit
-//    high product and two low products, result in [0, 2q) then one
-//    conditional subtraction;
+//  - products with a constant (conversion prescales, P^-1, N^-1): Shoup's
+//    method with the precomputed floor(w 2^64 / q), one 64-bit high product
+//    and two low products, result in [0, 2q) then one conditional
+//    subtraction; the transforms' twiddle products take the high product
+//    without its lowest partial product and carries, result in [0, 4q);
 //  - sums of products (conversion, key multiply-accumulate): exact
 //    accumulation of at most 16 products of canonical residues (each below
 //    2^60 m, so the sum stays below m 2^64), then one Montgomery reduction
@@ -89,6 +90,18 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t 
 __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
   return csub(shoup_lazy(a, w, ws, q), q);
 }
+// Shoup's product with an estimate of the quotient h = floor(a ws / 2^64):
+// with a = a1 2^32 + a0 and ws = s1 2^32 + s0, a ws / 2^64 equals
+// a1 s1 + floor(a1 s0 / 2^32) + floor(a0 s1 / 2^32) plus a fraction below
+// 3 (the two dropped low halves and a0 s0 / 2^64), so the estimate is h,
+// h - 1 or h - 2 and a w - estimate q lies in [0, 4q).  Two 32-bit high
+// products and one multiply-add instead of the exact high product's three
+// multiply-adds.
+__device__ __forceinline__ uint64_t shoup_lazy4(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), s0 = (uint32_t)ws, s1 = (uint32_t)(ws >> 32);
+  const uint64_t h = (uint64_t)a1 * s1 + __umulhi(a1, s0) + __umulhi(a0, s1);
+  return a * w - h * q;
+}
 // A 128-bit value, (hi, lo).
 struct Acc128 {
   uint64_t lo = 0, hi = 0;
@@ -160,25 +173,28 @@ __device__ __forceinline__ void tw_of(const uint4 v, uint64_t *w, uint64_t *ws) 
   *w = ((uint64_t)v.y << 32) | v.x;
   *ws = ((uint64_t)v.w << 32) | v.z;
 }
-// Harvey's lazy butterflies (q < 2^60, so 4q fits a word).  Cooley-Tukey
-// (a, b) -> (a + b w, a - b w) on inputs in [0, 4q), outputs in [0, 4q):
-// one conditional subtraction of 2q per butterfly.
+// Harvey's lazy butterflies, widened for twiddle products in [0, 4q)
+// (q < 2^60, so 8q < 2^63 fits a word).  Cooley-Tukey (a, b) ->
+// (a + b w, a - b w) on inputs in [0, 8q), outputs in [0, 8q): one
+// conditional subtraction of 4q per butterfly.
 __device__ __forceinline__ void ct(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
-  const uint64_t q2 = 2 * q, x = csub(a, q2), v = shoup_lazy(b, w, ws, q);
+  const uint64_t q4 = 4 * q, x = csub(a, q4), v = shoup_lazy4(b, w, ws, q);
   a = x + v;
-  b = x - v + q2;
+  b = x - v + q4;
 }
-// Gentleman-Sande (a, b) -> (a + b, (a - b) w) on inputs in [0, 2q),
-// outputs in [0, 2q).
+// Gentleman-Sande (a, b) -> (a + b, (a - b) w) on inputs in [0, 4q),
+// outputs in [0, 4q).
 __device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
-  const uint64_t q2 = 2 * q, d = a - b + q2;
-  a = csub(a + b, q2);
-  b = shoup_lazy(d, w, ws, q);
+  const uint64_t q4 = 4 * q, d = a - b + q4;
+  a = csub(a + b, q4);
+  b = shoup_lazy4(d, w, ws, q);
 }
+// A forward transform's word in [0, 8q) made canonical.
+__device__ __forceinline__ uint64_t fwd_canon(uint64_t x, uint64_t q) { return csub(csub(csub(x, 4 * q), 2 * q), q); }
 
 // One step over `nseq` sequences of M words in LDS (word p of sequence c
 // at s[p * ps + c * cs]) with twiddles at tw + c * ts.  Forward: the
@@ -288,10 +304,10 @@ __global__ __launch_bounds__(256) void k_row(Dev64 P, List64 L, const uint64_t *
   stage_row_tw(tws, tab, N, row0);
   __syncthreads();
   npass<INV, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, ~0u, m.q);
-  // forward: the transform's last pass, words [0, 4q) -> canonical; inverse:
-  // the first pass, words left in [0, 2q) for the column pass
+  // forward: the transform's last pass, words [0, 8q) -> canonical; inverse:
+  // the first pass, words left in [0, 4q) for the column pass
   for (uint32_t i = threadIdx.x; i < kRowsPerTile * kRowWords; i += 256)
-    out[i] = INV ? s[i] : csub(csub(s[i], 2 * m.q), m.q);
+    out[i] = INV ? s[i] : fwd_canon(s[i], m.q);
 }
 
 // Column pass: tiles of kColsPerTile columns of R = N / 256 rows.  Forward:
@@ -442,7 +458,7 @@ __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const 
       __syncthreads();
       npass<false, true>(s, tws, 8, kRowsPerTile, 1, kRowWords, kRowWords, ~0u, m.q);
 #pragma unroll
-      for (uint32_t i = 0; i < kPerThread; i++) y[i] = csub(csub(s[threadIdx.x + 256 * i], 2 * m.q), m.q);
+      for (uint32_t i = 0; i < kPerThread; i++) y[i] = fwd_canon(s[threadIdx.x + 256 * i], m.q);
     }
     const size_t row = (size_t)j * (SEEDED ? 1 : 2) * P.ntot + g;  // b half of digit j, key row g
     const uint64_t *e0 = evk + row * N + base;
@@ -483,7 +499,7 @@ __global__ __launch_bounds__(256) void k_row_mac(Dev64 P, uint32_t level, const 
   const uint32_t k = t - l1, K = P.num_p;
   for (uint32_t e = threadIdx.x; e < 2 * kTileWords; e += 256) {
     const uint32_t h = e / kTileWords;
-    XP[((size_t)h * K + k) * N + base + (e - h * kTileWords)] = s[e];  // [0, 2q): the column pass finishes
+    XP[((size_t)h * K + k) * N + base + (e - h * kTileWords)] = s[e];  // [0, 4q): the column pass finishes
   }
 }
 
@@ -539,7 +555,7 @@ __global__ __launch_bounds__(256) void k_row_moddown(Dev64 P, uint32_t level, co
   for (uint32_t e = threadIdx.x; e < 2 * kTileWords; e += 256) {
     const uint32_t h = e / kTileWords;
     const size_t o = base + (e - h * kTileWords);
-    const uint64_t w = csub(csub(s[e], 2 * m.q), m.q);
+    const uint64_t w = fwd_canon(s[e], m.q);
     out[((size_t)h * l1 + i) * N + o] = shoup(sub_mod(acc[((size_t)h * T + i) * N + o], w, m.q), pi, pis, m.q);
   }
 }
@@ -732,8 +748,8 @@ void free_plan(ks64_plan *pl) {
 
 // One transform direction over a list of towers, split into launches of
 // kList.  col_only: the column pass alone (forward: its first pass, words
-// left in [0, 4q) for a fused row pass; inverse: its second pass, reading
-// words in [0, 2q) that a fused row pass wrote).
+// left in [0, 8q) for a fused row pass; inverse: its second pass, reading
+// words in [0, 4q) that a fused row pass wrote).
 hipError_t transform(const ks64_plan *pl, bool inverse, const uint64_t *src, uint64_t *dst,
                      const std::vector<uint32_t> &so, const std::vector<uint32_t> &dof,
                      const std::vector<uint32_t> &g, hipStream_t st, bool col_only = false) {
