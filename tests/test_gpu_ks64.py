@@ -8,7 +8,9 @@ with every word at m - 1; Table III's BTS1/BTS2/BTS3 at N = 2^17 and
 ARK/DPRIVE at N = 2^16, full size, and BTS3 below its top level (a partial digit at N = 2^17); compressed
 keys (the a halves regenerated from a seed) with real seeded keys at every
 level (decrypted), against the expanded key for several shapes and BTS3 at
-full size; error paths.
+full size; a seeded random sweep of 16 parameter sets (log N 12..14, 1..40
+q towers, dnum up to 16, K = alpha or 1..32, random levels), full and
+compressed keys; error paths.
 """
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -264,4 +266,46 @@ def test_seeded_error_paths(ks):
         with pytest.raises(ks.KsError) as e:
             ks.ks64_keyswitch_seeded(plan.handle, *args)
         assert e.value.status == ks.KS_ERR_INVALID_ARG
+    plan.close()
+
+
+# ---- seeded random sweep ----------------------------------------------------
+def _sweep_cases(count=16, seed=6401):
+    """Parameter sets drawn (seeded) from what a 64-bit plan accepts: log N
+    12..14, 1..40 q towers, dnum 1..min(16, towers), K = alpha or 1..32, at
+    a random level."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        log_n = int(rng.integers(12, 15))
+        num_q = int(rng.integers(1, 41))
+        dnum = int(rng.integers(1, min(16, num_q) + 1))
+        alpha = -(-num_q // dnum)
+        num_p = 0 if rng.random() < 0.4 else int(rng.integers(1, 33))
+        if alpha > 32 or (num_p or alpha) > 32:
+            continue
+        out.append((log_n, num_q, dnum, num_p, int(rng.integers(0, num_q))))
+    return out
+
+
+@pytest.mark.parametrize("log_n,num_q,dnum,num_p,level", _sweep_cases())
+def test_sweep(ks, log_n, num_q, dnum, num_p, level):
+    """Every word of a full-key and a compressed-key key switch against the
+    64-bit oracle (the compressed key's a halves from the oracle's seeded
+    words, its b halves uniform)."""
+    p = oracle.Params(log_n, num_q, dnum, num_p)
+    mods = o64.moduli(p)
+    seed = 7000 + 97 * num_q + log_n + level
+    a_seed = 0x5eed_0000 + seed
+    evk = o64.seeded_a(p, mods, a_seed)
+    evk[:, 0] = uniform_evk64(mods, dnum, p.n, seed)[:, 0]
+    d = uniform64(mods[:level + 1], p.n, seed + 1)
+    say(f"[ks64 sweep] {log_n} {num_q} {dnum} {num_p} level={level}")
+    want = o64.keyswitch(p, mods, level, evk, d)
+    plan = ks.Plan64(log_n, num_q, dnum, num_p)
+    got = host(plan.keyswitch(dev(evk), level, dev(d)))
+    got_s = host(plan.keyswitch_seeded(dev(np.ascontiguousarray(evk[:, 0])), a_seed, level, dev(d)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+    assert np.array_equal(got_s, want), np.argwhere(got_s != want)[:5]
     plan.close()
