@@ -20,7 +20,9 @@
 //    each below 2^60: four 64-bit sums (one multiply-add per partial
 //    product) hold 16 products without overflow, and are combined into
 //    the 128-bit sum once per chunk.
-//  - every stage leaves canonical residues.
+//  - every stage leaves canonical residues, except inside a transform: a
+//    pass hands its next pass words in [0, 8q) (forward) or [0, 4q)
+//    (inverse), and the last pass makes them canonical.
 // The forward transform is the Cooley-Tukey network that lists a(psi^(2
 // brv(j)+1)) at position j; the inverse is the Gentleman-Sande network and
 // N^-1.  A transform of N = R x 256 words is a column pass (stages with
