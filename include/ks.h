@@ -492,7 +492,7 @@ ks_status_t ks64_keyswitch_seeded(ks64_plan_t plan, const uint64_t *evk_b, uint6
                                   void *stream);
 /* In-place forward (inverse = 0) or inverse NTT of `count` limbs of data
  * [count][N]; limb c uses modulus number g[c] (host array, order q_0..q_L,
- * p_0..p_{K-1}). */
+ * p_0..p_{K-1}).  Words canonical on entry and on return. */
 ks_status_t ks64_ntt(ks64_plan_t plan, uint32_t count, const uint32_t *g, int inverse, uint64_t *data,
                      void *stream);
 
