@@ -414,6 +414,23 @@ ks_status_t ks_trace_read(ks_plan_t plan, uint32_t max, const char **names, uint
  * doubles.  Allocates and frees 2 GiB of device memory; synchronous. */
 ks_status_t ks_device_rates(double *out, void *stream);
 
+/* Range checks for tools (not part of the method).  The library is also
+ * built as libks_check.so with every lazy-range and accumulator bound the
+ * exact arithmetic relies on tested where it is used: butterfly inputs
+ * ([0, 4q) / [0, 2q) for 30-bit words, [0, 8q) / [0, 4q) for 64-bit ones),
+ * Shoup products, multiply-accumulate operands below 2^30 and sums that do
+ * not wrap, REDC inputs and outputs.  A violation is counted on the device
+ * and the computation goes on.  ks_range_violations returns, for the
+ * current device, the number of violations since the last reset and the
+ * code of one of them (0 if none; the codes are listed in
+ * csrc/range_check.h), clearing the counters when `reset` is nonzero; it
+ * synchronises with the device's work.  ks_range_set_strict(1) makes the
+ * REDC check demand results below q/2, which ordinary inputs violate, so a
+ * caller can see that the counters are live.  libks.so compiles the checks
+ * out and returns KS_ERR_UNSUPPORTED from both. */
+ks_status_t ks_range_violations(uint32_t *count, uint32_t *code, int reset);
+ks_status_t ks_range_set_strict(int on);
+
 /* Cost model of the autotuner (not part of the key switch): an fp32 MLP
  * with F inputs, two hidden layers of H units with ReLU, and one linear
  * output.  Parameters are one device float array of ks_mlp_param_count(F,H)

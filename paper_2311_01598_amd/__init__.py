@@ -4,7 +4,9 @@ Argument marshalling only: every step of the key switch runs in the HIP
 kernels behind the C ABI declared in ``include/ks.h``.  PyTorch supplies
 device memory and streams; uint32 residues travel in ``torch.int32``
 tensors (same bits).  Importing this module loads ``libks.so`` and raises if
-it is missing -- there is no fallback path.
+it is missing -- there is no fallback path.  With ``KS_LIBRARY=libks_check.so``
+in the environment it loads the range-check build instead (the same kernels
+with every lazy-range bound tested; ``range_violations`` reads the counts).
 
 The functions keep the C names (``ks_plan_create``, ``ks_keyswitch``, ...);
 ``Plan`` is a small convenience wrapper around them.
@@ -13,7 +15,11 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libks.so")
+LIBRARIES = ("libks.so", "libks_check.so")
+_LIB_NAME = os.environ.get("KS_LIBRARY", "libks.so")
+if _LIB_NAME not in LIBRARIES:
+    raise ImportError(f"KS_LIBRARY={_LIB_NAME!r}: expected one of {LIBRARIES}")
+LIB_PATH = os.path.join(HERE, _LIB_NAME)
 
 KS_OK, KS_ERR_INVALID_ARG, KS_ERR_UNSUPPORTED, KS_ERR_NOMEM, KS_ERR_BUDGET, KS_ERR_DEVICE = range(6)
 KS_SCHED_AUTO, KS_SCHED_MP, KS_SCHED_DC, KS_SCHED_OC = range(4)
@@ -114,6 +120,8 @@ _SIGS = {
     "ks_trace_read": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_char_p), _U32P,
                                      ctypes.POINTER(ctypes.c_double), _U32P]),
     "ks_device_rates": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _VP]),
+    "ks_range_violations": (ctypes.c_int, [_U32P, _U32P, ctypes.c_int]),
+    "ks_range_set_strict": (ctypes.c_int, [ctypes.c_int]),
     "ks_mlp_param_count": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32]),
     "ks_mlp_forward": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
     "ks_mlp_mse_grad": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
@@ -424,6 +432,20 @@ def ks_device_rates(stream=None):
     out = (ctypes.c_double * 7)()
     _check(_lib.ks_device_rates(out, _stream(stream)), "ks_device_rates")
     return dict(zip(RATE_NAMES, list(out)))
+
+
+def ks_range_violations(reset=False):
+    """(count, code): range-check violations on the current device since the
+    last reset (range-check build only; the normal build raises KsError with
+    KS_ERR_UNSUPPORTED)."""
+    count, code = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    _check(_lib.ks_range_violations(ctypes.byref(count), ctypes.byref(code), 1 if reset else 0),
+           "ks_range_violations")
+    return int(count.value), int(code.value)
+
+
+def ks_range_set_strict(on):
+    _check(_lib.ks_range_set_strict(1 if on else 0), "ks_range_set_strict")
 
 
 def ks_mlp_param_count(F, H):

@@ -483,7 +483,63 @@ ks_status_t validate_params(const ks_params_t *p) {
 
 }  // namespace
 
+#ifdef KS_CHECK_RANGES
+// The range-check build's registry: one reader per HIP compile unit, filled
+// while the library loads.
+namespace ks_range {
+namespace {
+struct Unit {
+  reader_t read;
+  strict_t strict;
+};
+std::mutex &registry_mu() {
+  static std::mutex m;
+  return m;
+}
+std::vector<Unit> &registry() {
+  static std::vector<Unit> r;
+  return r;
+}
+}  // namespace
+void register_unit(reader_t read, strict_t strict) {
+  std::lock_guard<std::mutex> g(registry_mu());
+  registry().push_back({read, strict});
+}
+}  // namespace ks_range
+#endif
+
 extern "C" {
+
+ks_status_t ks_range_violations(uint32_t *count, uint32_t *code, int reset) {
+#ifdef KS_CHECK_RANGES
+  if (!count || !code) return KS_ERR_INVALID_ARG;
+  *count = 0;
+  *code = 0;
+  if (hipDeviceSynchronize() != hipSuccess) return KS_ERR_DEVICE;
+  std::lock_guard<std::mutex> g(ks_range::registry_mu());
+  for (const auto &u : ks_range::registry())
+    if (u.read(count, code, reset) != 0) return KS_ERR_DEVICE;
+  return KS_OK;
+#else
+  (void)count;
+  (void)code;
+  (void)reset;
+  return KS_ERR_UNSUPPORTED;
+#endif
+}
+
+ks_status_t ks_range_set_strict(int on) {
+#ifdef KS_CHECK_RANGES
+  if (hipDeviceSynchronize() != hipSuccess) return KS_ERR_DEVICE;
+  std::lock_guard<std::mutex> g(ks_range::registry_mu());
+  for (const auto &u : ks_range::registry())
+    if (u.strict(on) != 0) return KS_ERR_DEVICE;
+  return KS_OK;
+#else
+  (void)on;
+  return KS_ERR_UNSUPPORTED;
+#endif
+}
 
 const char *ks_status_string(ks_status_t s) {
   switch (s) {

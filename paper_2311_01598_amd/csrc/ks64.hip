@@ -42,6 +42,7 @@
 
 #include "ks.h"
 #include "numtheory.h"
+#include "range_check.h"
 
 namespace ks64 {
 
@@ -86,7 +87,9 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) 
 // a < 2^64, w < q < 2^62, ws = floor(w 2^64 / q): a w mod q in [0, 2q)
 __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
   const uint64_t h = __umul64hi(a, ws);
-  return a * w - h * q;
+  const uint64_t r = a * w - h * q;
+  KS_RANGE(r < 2 * q, KS_RC64_SHOUP);
+  return r;
 }
 // the same, canonical
 __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
@@ -102,7 +105,9 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t ws, u
 __device__ __forceinline__ uint64_t shoup_lazy4(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), s0 = (uint32_t)ws, s1 = (uint32_t)(ws >> 32);
   const uint64_t h = (uint64_t)a1 * s1 + __umulhi(a1, s0) + __umulhi(a0, s1);
-  return a * w - h * q;
+  const uint64_t r = a * w - h * q;
+  KS_RANGE(r < 4 * q, KS_RC64_SHOUP4);
+  return r;
 }
 // A 128-bit value, (hi, lo).
 struct Acc128 {
@@ -113,10 +118,15 @@ constexpr uint64_t kLo30 = (1ull << 30) - 1;
 struct Acc4 {
   uint64_t s0 = 0, s1a = 0, s1b = 0, s2 = 0;
   __device__ __forceinline__ void mac(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
+    KS_RANGE((a0 | a1 | b0 | b1) < (1u << 30), KS_RC64_MAC_OPND);
+#ifdef KS_CHECK_RANGES
+    const uint64_t p0 = s0, p1 = s1a, p2 = s1b, p3 = s2;
+#endif
     s0 += (uint64_t)a0 * b0;
     s1a += (uint64_t)a1 * b0;
     s1b += (uint64_t)a0 * b1;
     s2 += (uint64_t)a1 * b1;
+    KS_RANGE(s0 >= p0 && s1a >= p1 && s1b >= p2 && s2 >= p3, KS_RC64_MAC_WRAP);
   }
   __device__ __forceinline__ void mac(uint32_t a0, uint32_t a1, uint64_t b) {
     mac(a0, a1, (uint32_t)(b & kLo30), (uint32_t)(b >> 30));
@@ -131,6 +141,7 @@ struct Acc4 {
 };
 // T < q 2^64: (T + m q) / 2^64 with m = T_lo (-q^-1) mod 2^64, canonical
 __device__ __forceinline__ uint64_t redc(const Acc128 &t, const Mod64 &m) {
+  KS_RANGE(t.hi < m.q, KS_RC64_REDC_IN);
   const uint64_t u = t.lo * m.qneg;
   const uint64_t lo = t.lo + u * m.q;  // 0 mod 2^64 by the choice of u
   return csub(t.hi + __umul64hi(u, m.q) + (lo < t.lo ? 1u : 0u), m.q);
@@ -180,6 +191,7 @@ __device__ __forceinline__ void tw_of(const uint4 v, uint64_t *w, uint64_t *ws) 
 // (a + b w, a - b w) on inputs in [0, 8q), outputs in [0, 8q): one
 // conditional subtraction of 4q per butterfly.
 __device__ __forceinline__ void ct(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
+  KS_RANGE(a < 8 * q && b < 8 * q, KS_RC64_CT_IN);
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
   const uint64_t q4 = 4 * q, x = csub(a, q4), v = shoup_lazy4(b, w, ws, q);
@@ -189,6 +201,7 @@ __device__ __forceinline__ void ct(uint64_t &a, uint64_t &b, const uint4 tv, uin
 // Gentleman-Sande (a, b) -> (a + b, (a - b) w) on inputs in [0, 4q),
 // outputs in [0, 4q).
 __device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uint64_t q) {
+  KS_RANGE(a < 4 * q && b < 4 * q, KS_RC64_GS_IN);
   uint64_t w, ws;
   tw_of(tv, &w, &ws);
   const uint64_t q4 = 4 * q, d = a - b + q4;
@@ -196,7 +209,10 @@ __device__ __forceinline__ void gs(uint64_t &a, uint64_t &b, const uint4 tv, uin
   b = shoup_lazy4(d, w, ws, q);
 }
 // A forward transform's word in [0, 8q) made canonical.
-__device__ __forceinline__ uint64_t fwd_canon(uint64_t x, uint64_t q) { return csub(csub(csub(x, 4 * q), 2 * q), q); }
+__device__ __forceinline__ uint64_t fwd_canon(uint64_t x, uint64_t q) {
+  KS_RANGE(x < 8 * q, KS_RC64_FWD_IN);
+  return csub(csub(csub(x, 4 * q), 2 * q), q);
+}
 
 // One step over `nseq` sequences of M words in LDS (word p of sequence c
 // at s[p * ps + c * cs]) with twiddles at tw + c * ts.  Forward: the

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "range_check.h"
+
 namespace ks {
 
 // Global-memory views of generic pointers.  Buffers reached through a job
@@ -140,11 +142,17 @@ __device__ __forceinline__ uint32_t neg_mod(uint32_t q) {
 // a * w mod q in [0, 2q), any a < 2^32.
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
   const uint32_t h = __umulhi(a, wp);
-  return a * w + h * neg_mod(q);
+  const uint32_t r = a * w + h * neg_mod(q);
+  KS_RANGE(r < 2 * q, KS_RC_SHOUP_OUT);
+  return r;
 }
 
+// One term of a sum of at most 16 products of values below 2^30.
 __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
-  return (uint64_t)a * (uint64_t)b + c;
+  KS_RANGE((a | b) < (1u << 30), KS_RC_MAC_OPND);
+  const uint64_t r = (uint64_t)a * (uint64_t)b + c;
+  KS_RANGE(r >= c, KS_RC_MAC_WRAP);
+  return r;
 }
 
 // T * 2^-32 mod q, canonical, for any T < 2^64.
@@ -155,7 +163,9 @@ __device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
   uint64_t s = (uint64_t)u * m.q + (((uint64_t)hi << 32) | lo);
   uint32_t r = (uint32_t)(s >> 32);      // [0, 3q)
   r = csub(r, m.q);
-  return csub(r, m.q);
+  r = csub(r, m.q);
+  KS_RANGE(r < (KS_RANGE_STRICT() ? m.q / 2 : m.q), KS_RC_REDC_OUT);
+  return r;
 }
 
 // Compressed keys (Sec. IV-D): the a half of a key pair is regenerated where
@@ -196,6 +206,7 @@ __device__ __forceinline__ uint32_t galois_perm(uint32_t j, uint32_t k, uint32_t
 // with t in [0, 2q); then x' = a + t = a - nt and y' = a + 2q - t =
 // a + 2q + nt, a single three-input add.
 __device__ __forceinline__ void bfly_ct(uint32_t &x, uint32_t &y, uint32_t wneg, uint32_t wp, uint32_t q) {
+  KS_RANGE(x < 4 * q && y < 4 * q, KS_RC_CT_IN);
   const uint32_t two_q = q << 1;
   const uint32_t a = csub(x, two_q);
   const uint32_t h = __umulhi(y, wp);
@@ -207,6 +218,7 @@ __device__ __forceinline__ void bfly_ct(uint32_t &x, uint32_t &y, uint32_t wneg,
 // Harvey inverse (Gentleman-Sande) butterfly, inputs and outputs in [0, 2q);
 // inverse tables hold (w, w').
 __device__ __forceinline__ void bfly_gs(uint32_t &x, uint32_t &y, uint32_t w, uint32_t wp, uint32_t q) {
+  KS_RANGE(x < 2 * q && y < 2 * q, KS_RC_GS_IN);
   const uint32_t two_q = q << 1;
   const uint32_t a = x, b = y;
   x = csub(a + b, two_q);
@@ -214,6 +226,9 @@ __device__ __forceinline__ void bfly_gs(uint32_t &x, uint32_t &y, uint32_t w, ui
 }
 
 // [0, 4q) -> [0, q)
-__device__ __forceinline__ uint32_t canon4(uint32_t a, uint32_t q) { return csub(csub(a, q << 1), q); }
+__device__ __forceinline__ uint32_t canon4(uint32_t a, uint32_t q) {
+  KS_RANGE(a < 4 * q, KS_RC_CANON4_IN);
+  return csub(csub(a, q << 1), q);
+}
 
 }  // namespace ks

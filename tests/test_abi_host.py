@@ -5,6 +5,7 @@ its own derivation of moduli and roots of unity agrees with the oracle's
 independent one (trial division / brute-force root search).  Argument errors
 that are decided before any device work return the documented status.
 """
+import ctypes
 import os
 import re
 
@@ -23,6 +24,21 @@ def test_exports_every_declared_symbol():
     assert declared == set(ks.EXPORTS)
     for name in declared:
         assert hasattr(ks.lib(), name), name
+    # the range-check build exports the same entry points
+    check = ctypes.CDLL(os.path.join(os.path.dirname(ks.LIB_PATH), "libks_check.so"))
+    for name in declared:
+        assert hasattr(check, name), name
+
+
+def test_range_checks_are_compiled_out_of_the_normal_build():
+    if os.path.basename(ks.LIB_PATH) != "libks.so":
+        pytest.skip("the range-check build is loaded")
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_range_violations()
+    assert e.value.status == ks.KS_ERR_UNSUPPORTED
+    with pytest.raises(ks.KsError) as e:
+        ks.ks_range_set_strict(True)
+    assert e.value.status == ks.KS_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("shape", [(12, 4, 2, 2), (16, 24, 3, 8), (14, 10, 3, 0), (17, 48, 3, 16), (15, 26, 3, 7)])
