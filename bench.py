@@ -153,8 +153,8 @@ def stage_bytes(log_n, l1, k, alpha):
 
 # Compile units of the library that hold none of the 32-bit key switch's
 # kernels or their launches: the 64-bit-word path, the cost-model MLP, the
-# rate probes and the no-allocation scratch array.
-DIGEST_EXCLUDE = ("ks64.hip", "mlp.hip", "rates.hip", "noalloc.hip")
+# rate probes, the no-allocation scratch array and the arithmetic probe.
+DIGEST_EXCLUDE = ("ks64.hip", "mlp.hip", "rates.hip", "noalloc.hip", "probe.hip")
 
 
 def kernel_source_digest(csrc=None):

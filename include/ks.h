@@ -431,6 +431,39 @@ ks_status_t ks_device_rates(double *out, void *stream);
 ks_status_t ks_range_violations(uint32_t *count, uint32_t *code, int reset);
 ks_status_t ks_range_set_strict(int on);
 
+/* Arithmetic probes for tests (not part of the method): the kernels'
+ * modular primitives applied element-wise, so that each can be compared
+ * with a b mod q directly.  a, b: n device words each (any values); each
+ * primitive gets them reduced into the range it is specified for; out:
+ * device, n x 8 (30-bit) or n x 9 (64-bit) words, element-major.
+ * Asynchronous on `stream`.  Errors: null pointers, n = 0, or q outside
+ * the word size's modulus range (odd, 2^29 < q < 2^30, resp. 2^59 < q <
+ * 2^60; and w < q for the 64-bit probe) give KS_ERR_INVALID_ARG.
+ * 30-bit (w: n device words, reduced mod q; its Shoup companion derived on
+ * the device as the transform tiles derive it):
+ *   0: a w mod q (Shoup, any a < 2^32), canonical;
+ *   1: (a mod q)(b mod q) 2^-32 mod q (one product, REDC), canonical;
+ *   2: sum over k < 16 of (a_j mod q)(b_j mod q), j = (i + k) mod n, times
+ *      2^-32 mod q (a full chunk of products, one REDC), canonical;
+ *   3, 4: the forward butterfly of (x, y) = (a mod 4q, b mod 4q):
+ *      x + w y and x - w y mod q, each in [0, 4q);
+ *   5, 6: the inverse butterfly of (u, v) = (a mod 2q, b mod 2q):
+ *      u + v and (u - v) w mod q, each in [0, 2q);
+ *   7: (a mod 4q) mod q through the [0, 4q) -> [0, q) reduction.
+ * 64-bit (one twiddle w < q for all elements; its companion computed on the
+ * host as the plan computes it):
+ *   0: a w mod q (Shoup), canonical;  1: a w mod q with the estimated
+ *      quotient, in [0, 4q);
+ *   2: (a mod q)(b mod q) 2^-64 mod q (30-bit-half products, REDC);
+ *   3: the same for the 16 products from element i on (cyclically);
+ *   4, 5: the forward butterfly of (a mod 8q, b mod 8q), each in [0, 8q);
+ *   6, 7: the inverse butterfly of (a mod 4q, b mod 4q), each in [0, 4q);
+ *   8: (a mod 8q) mod q through the forward transform's last reduction. */
+ks_status_t ks_arith_probe(uint32_t q, uint32_t n, const uint32_t *a, const uint32_t *b, const uint32_t *w,
+                           uint32_t *out, void *stream);
+ks_status_t ks64_arith_probe(uint64_t q, uint64_t w, uint32_t n, const uint64_t *a, const uint64_t *b,
+                             uint64_t *out, void *stream);
+
 /* Cost model of the autotuner (not part of the key switch): an fp32 MLP
  * with F inputs, two hidden layers of H units with ReLU, and one linear
  * output.  Parameters are one device float array of ks_mlp_param_count(F,H)

@@ -122,6 +122,7 @@ _SIGS = {
     "ks_device_rates": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), _VP]),
     "ks_range_violations": (ctypes.c_int, [_U32P, _U32P, ctypes.c_int]),
     "ks_range_set_strict": (ctypes.c_int, [ctypes.c_int]),
+    "ks_arith_probe": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
     "ks_mlp_param_count": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32]),
     "ks_mlp_forward": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
     "ks_mlp_mse_grad": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP]),
@@ -448,6 +449,17 @@ def ks_range_set_strict(on):
     _check(_lib.ks_range_set_strict(1 if on else 0), "ks_range_set_strict")
 
 
+def ks_arith_probe(q, a, b, w, out=None, stream=None):
+    """The 30-bit primitives on int32 device tensors a, b, w of n words;
+    returns out [n][8] (see include/ks.h)."""
+    import torch
+    n = a.numel()
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.int32, device=a.device)
+    _check(_lib.ks_arith_probe(int(q), n, _ptr(a), _ptr(b), _ptr(w), _ptr(out), _stream(stream)), "ks_arith_probe")
+    return out
+
+
 def ks_mlp_param_count(F, H):
     return int(_lib.ks_mlp_param_count(F, H))
 
@@ -641,6 +653,7 @@ _SIGS64 = {
     "ks64_workspace_size": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "ks64_keyswitch": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "ks64_ntt": (ctypes.c_int, [_VP, ctypes.c_uint32, _U32P, ctypes.c_int, _VP, _VP]),
+    "ks64_arith_probe": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
     "ks64_keyswitch_seeded": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP,
                                              ctypes.c_size_t, _VP]),
 }
@@ -703,6 +716,18 @@ def ks64_keyswitch_seeded(plan, evk_b, a_seed, level, inp, out, workspace, works
     st = _lib.ks64_keyswitch_seeded(plan, _ptr(evk_b), int(a_seed) & 0xFFFFFFFFFFFFFFFF, int(level), _ptr(inp),
                                     _ptr(out), _ptr(workspace), int(workspace_bytes), _stream(stream))
     _check(st, "ks64_keyswitch_seeded")
+
+
+def ks64_arith_probe(q, w, a, b, out=None, stream=None):
+    """The 64-bit primitives on int64 device tensors a, b of n words with
+    the twiddle w; returns out [n][9] (see include/ks.h)."""
+    import torch
+    n = a.numel()
+    if out is None:
+        out = torch.empty((n, 9), dtype=torch.int64, device=a.device)
+    _check(_lib.ks64_arith_probe(int(q), int(w), n, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
+           "ks64_arith_probe")
+    return out
 
 
 def ks64_ntt(plan, g, inverse, data, stream=None):

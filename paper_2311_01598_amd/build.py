@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libks.so")
 OUT_CHECK = os.path.join(HERE, "libks_check.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["numtheory.cpp", "plan.cpp", "api.cpp", "kernels.hip", "rates.hip", "mlp.hip", "noalloc.hip", "ks64.hip"] + ["oc_a%d.hip" % a for a in range(4, 10)]
+SOURCES = ["numtheory.cpp", "plan.cpp", "api.cpp", "kernels.hip", "rates.hip", "mlp.hip", "noalloc.hip", "ks64.hip",
+           "probe.hip"] + ["oc_a%d.hip" % a for a in range(4, 10)]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]

@@ -578,6 +578,44 @@ __global__ __launch_bounds__(256) void k_row_moddown(Dev64 P, uint32_t level, co
   }
 }
 
+// ------------------------------------------------------------ arithmetic probe
+// The primitives above applied element-wise to caller arrays, for a test
+// that compares each with a b mod q directly (not part of the method).
+// Element i: a = a[i], b = b[i] (any words), the twiddle (w, ws); each
+// primitive gets its operands reduced into the range it is specified for.
+constexpr uint32_t kProbe64Out = 9;
+__global__ __launch_bounds__(256) void k_arith_probe64(Mod64 m, uint4 tv, uint32_t n, const uint64_t *a,
+                                                       const uint64_t *b, uint64_t *out) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t q = m.q, ai = a[i], bi = b[i];
+  uint64_t w, ws;
+  tw_of(tv, &w, &ws);
+  uint64_t *o = out + (size_t)i * kProbe64Out;
+  o[0] = shoup(ai, w, ws, q);        // a w mod q
+  o[1] = shoup_lazy4(ai, w, ws, q);  // a w mod q, in [0, 4q)
+  const uint64_t ac = ai % q, bc = bi % q;
+  Acc4 one;
+  one.mac((uint32_t)(ac & kLo30), (uint32_t)(ac >> 30), bc);
+  o[2] = redc(one.sum(), m);  // a b 2^-64 mod q
+  Acc4 sum;  // the 16 products from element i on (cyclically), 2^-64
+  for (uint32_t k = 0; k < 16; k++) {
+    const uint32_t j = (i + k) % n;
+    const uint64_t x = a[j] % q;
+    sum.mac((uint32_t)(x & kLo30), (uint32_t)(x >> 30), b[j] % q);
+  }
+  o[3] = redc(sum.sum(), m);
+  uint64_t x = ai % (8 * q), y = bi % (8 * q);
+  ct(x, y, tv, q);  // (x + w y, x - w y), [0, 8q)
+  o[4] = x;
+  o[5] = y;
+  uint64_t u = ai % (4 * q), v = bi % (4 * q);
+  gs(u, v, tv, q);  // (u + v, (u - v) w), [0, 4q)
+  o[6] = u;
+  o[7] = v;
+  o[8] = fwd_canon(ai % (8 * q), q);
+}
+
 // ------------------------------------------------------------ host side
 namespace {
 
@@ -979,6 +1017,21 @@ ks_status_t ks64_keyswitch_seeded(ks64_plan_t plan, const uint64_t *evk_b, uint6
                                   const uint64_t *in, uint64_t *out, void *workspace, size_t workspace_bytes,
                                   void *stream) {
   return keyswitch64(plan, evk_b, true, a_seed, level, in, out, workspace, workspace_bytes, stream);
+}
+
+ks_status_t ks64_arith_probe(uint64_t q, uint64_t w, uint32_t n, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                             void *stream) {
+  if (!a || !b || !out || n == 0) return KS_ERR_INVALID_ARG;
+  if (!(q & 1u) || q <= (1ull << 59) || q >= (1ull << 60) || w >= q) return KS_ERR_INVALID_ARG;
+  uint64_t inv = 1;  // q^-1 mod 2^64 by Newton's iteration
+  for (int i = 0; i < 7; i++) inv *= 2 - q * inv;
+  Mod64 m{};
+  m.q = q;
+  m.qneg = (uint64_t)0 - inv;
+  const uint64_t ws = shoup_of(w, q);
+  const uint4 tv = make_uint4((uint32_t)w, (uint32_t)(w >> 32), (uint32_t)ws, (uint32_t)(ws >> 32));
+  hipLaunchKernelGGL(k_arith_probe64, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, m, tv, n, a, b, out);
+  return hipGetLastError() == hipSuccess ? KS_OK : KS_ERR_DEVICE;
 }
 
 }  // extern "C"
