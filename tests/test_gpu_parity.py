@@ -344,6 +344,33 @@ def test_oc_batch_modes_and_graph_replays(ks, small_batch, mode, graph, tile):
     plan.close()
 
 
+def test_graph_capture_follows_the_batch(ks, small_batch):
+    """With graph capture on, a batch that differs from a captured one in
+    job count, workspace, tile width or batch mode is captured anew, and a
+    batch with the same key but other jobs in another order replays the
+    capture with its own job table: batches alternating between those kinds
+    on one plan must each equal the oracle for every job."""
+    p, mods, evks, levels, ins, want = small_batch
+    plan = ks.Plan(13, 8, 3, 3, schedule="oc", batch_mode=1, graph=1, tile_towers=1)
+    evk_d = [dev(e) for e in evks]
+    ins_d = [dev(x) for x in ins]
+    ws = [plan.workspace(levels), plan.workspace(levels)]
+    every = list(range(len(levels)))
+    variants = {"all": (every, 0, 1, 1), "first3": (every[:3], 0, 1, 1), "reversed": (every[::-1], 0, 1, 1),
+                "other_ws": (every, 1, 1, 1), "tile2": (every, 0, 2, 1), "mode3": (every, 0, 1, 3)}
+    for name in ("all", "first3", "all", "reversed", "all", "other_ws", "all", "tile2", "all", "mode3", "all",
+                 "reversed"):
+        idx, w, tt, mode = variants[name]
+        say(f"[graph key] {name}")
+        plan.configure("oc", tile_towers=tt, batch_mode=mode, graph=1)
+        outs = [torch.full((2, levels[i] + 1, p.n), -1, dtype=torch.int32, device="cuda") for i in idx]
+        plan.keyswitch_batch([(evk_d[i % 2], levels[i], ins_d[i], o) for i, o in zip(idx, outs)], workspace=ws[w])
+        torch.cuda.synchronize()
+        for i, o in zip(idx, outs):
+            assert np.array_equal(host(o), want[i]), (name, i)
+    plan.close()
+
+
 @pytest.mark.skip(reason=SWITCHED_OFF)
 def test_persistent_spin_limit_flags_error_and_recovers(ks, small_batch):
     """A tiny spin limit (forced from the host) makes dependency waits give
