@@ -371,6 +371,31 @@ def test_graph_capture_follows_the_batch(ks, small_batch):
     plan.close()
 
 
+def test_batch_results_do_not_depend_on_the_job_order(ks, small_batch):
+    """Race check by remapping work: the order of a batch's jobs decides
+    which workgroups, XCDs and interleave slots take each job's tiles, so
+    random permutations of the same jobs (both batch modes, tile widths 1
+    and 2, direct launches and graph replays) must give every job the same
+    words, equal to the oracle."""
+    p, mods, evks, levels, ins, want = small_batch
+    plan = ks.Plan(13, 8, 3, 3, schedule="oc")
+    evk_d = [dev(e) for e in evks]
+    ins_d = [dev(x) for x in ins]
+    ws = plan.workspace(levels)
+    rng = np.random.default_rng(2024)
+    for mode, tt, graph in ((1, 1, 2), (1, 2, 1), (3, 2, 2), (3, 1, 1)):
+        plan.configure("oc", tile_towers=tt, batch_mode=mode, graph=graph)
+        for rep in range(3):
+            order = [int(i) for i in rng.permutation(len(levels))]
+            say(f"[job order] mode={mode} tile={tt} graph={graph} order={order}")
+            outs = [torch.full((2, levels[i] + 1, p.n), -1, dtype=torch.int32, device="cuda") for i in order]
+            plan.keyswitch_batch([(evk_d[i % 2], levels[i], ins_d[i], o) for i, o in zip(order, outs)], workspace=ws)
+            torch.cuda.synchronize()
+            for i, o in zip(order, outs):
+                assert np.array_equal(host(o), want[i]), (mode, tt, graph, order, i)
+    plan.close()
+
+
 @pytest.mark.skip(reason=SWITCHED_OFF)
 def test_persistent_spin_limit_flags_error_and_recovers(ks, small_batch):
     """A tiny spin limit (forced from the host) makes dependency waits give
