@@ -208,7 +208,8 @@ ks_status_t ks_keyswitch_noalloc(ks_plan_t plan, const uint32_t *evk, uint32_t l
  * streams (3); with graph = 1 those launches are captured once per (count,
  * workspace, configuration, tile counts) in a hipGraph that later calls
  * replay.  The job table travels in the workspace (uploaded before every
- * launch or replay), so concurrent batches need distinct workspaces.  For tests of
+ * launch or replay), so concurrent batches need distinct workspaces.  A count
+ * of 0 returns KS_OK and enqueues nothing.  For tests of
  * failure handling, the environment variable KS_FAULT_INJECT=<n> makes the
  * n-th call after the variable took its current value return KS_ERR_DEVICE
  * without enqueuing work. */

@@ -229,3 +229,50 @@ def test_n17_hoisted_rotations_across_the_two_target_switch(ks, level):
     for o, w in zip(outs, want):
         assert np.array_equal(host(o), w), level
     plan.close()
+
+
+def test_calls_with_nothing_to_do(ks):
+    """Degenerate sizes: a batch of no jobs (full and compressed keys), a
+    rotation batch of no jobs, hoisted rotations with no rotation, a
+    double-hoisted sum of no terms and an automorphism of no limbs return
+    KS_OK and write nothing."""
+    plan = ks.Plan(12, 4, 2, 2)
+    n = plan.n
+    ws = plan.workspace([3])
+    c = torch.zeros((4, n), dtype=torch.int32, device="cuda")
+    out = torch.full((2, 4, n), -1, dtype=torch.int32, device="cuda")
+    ks.ks_keyswitch_batch(plan.handle, [], ws)
+    ks.ks_keyswitch_batch_seeded(plan.handle, [], ws)
+    ks.ks_rotate_batch(plan.handle, [], ws)
+    ks.ks_rotate_hoisted(plan.handle, 3, c, c, [], ws)
+    ks.ks_rotate_sum_hoisted(plan.handle, 3, c, c, [], out, ws)
+    ks.ks_automorphism(plan.handle, 5, 0, c, out)
+    torch.cuda.synchronize()
+    assert bool((out == -1).all())
+    plan.close()
+
+
+def test_largest_plan(ks):
+    """The largest plan the library accepts in towers: 96 + 32 = 128 towers,
+    alpha = K = 32 (two chunks of 16 products in every conversion), at
+    N = 2^16, at the top level under every schedule and at l+1 = 51 (a
+    partial last digit of 19 towers), every word against the oracle."""
+    p = oracle.Params(16, 96, 3, 32)
+    mods = oracle.moduli(p)
+    evk = synth.uniform_evk(mods, 3, p.n, synth.seed_for(44, 0))
+    plan = ks.Plan(16, 96, 3, 32)
+    assert plan.moduli == [int(m) for m in mods] and len(mods) == 128
+    evk_d = dev(evk)
+    for level, runs in ((95, (("oc", 1), ("oc", 2), ("mp", 1), ("dc", 1))), (50, (("oc", 2), ("mp", 1)))):
+        d = synth.uniform_limbs(mods[:level + 1], p.n, synth.seed_for(44, 1 + level))
+        say(f"[largest] level={level}: oracle")
+        want = oracle.keyswitch(p, mods, level, evk, d)
+        d_d = dev(d)
+        for sched, tt in runs:
+            say(f"[largest] level={level} {sched} tile={tt}")
+            plan.configure(sched, tile_towers=tt)
+            got = host(plan.keyswitch(evk_d, level, d_d))
+            torch.cuda.synchronize()
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, (level, sched, tt, bad[:5], len(bad))
+    plan.close()
