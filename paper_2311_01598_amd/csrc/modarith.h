@@ -155,6 +155,19 @@ __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
   return r;
 }
 
+// T * 2^-32 mod q in [0, 3q), for any T < 2^64: REDC without its final
+// conditional subtractions, for consumers that take lazy words (a forward
+// transform, a Shoup product).
+__device__ __forceinline__ uint32_t redc64_lazy(uint64_t T, const ModQ &m) {
+  uint32_t hi = (uint32_t)(T >> 32), lo = (uint32_t)T;
+  hi += __umulhi(hi, m.mu) * neg_mod(m.q);  // hi - floor(hi mu / 2^32) q, in [0, 2q)
+  uint32_t u = lo * m.qinv;
+  uint64_t s = (uint64_t)u * m.q + (((uint64_t)hi << 32) | lo);
+  const uint32_t r = (uint32_t)(s >> 32);
+  KS_RANGE(r < 3 * m.q, KS_RC_REDC_OUT);
+  return r;
+}
+
 // T * 2^-32 mod q, canonical, for any T < 2^64.
 __device__ __forceinline__ uint32_t redc64(uint64_t T, const ModQ &m) {
   uint32_t hi = (uint32_t)(T >> 32), lo = (uint32_t)T;

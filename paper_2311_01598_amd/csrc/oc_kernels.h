@@ -356,7 +356,8 @@ __device__ __forceinline__ void tile_bconv_col(const DevPlan &P, const uint32_t 
 #pragma unroll
     for (int e = 0; e < TT; e++)
 #pragma unroll
-      for (int u = 0; u < E; u++) y[e][u] = ONEC ? redc64(acc[e][u], mq[e]) : csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
+      for (int u = 0; u < E; u++)  // one chunk: [0, 3q) feeds the forward column pass ([0, 4q) accepted)
+        y[e][u] = ONEC ? redc64_lazy(acc[e][u], mq[e]) : csub(y[e][u] + redc64(acc[e][u], mq[e]), mq[e].q);
   }
 #pragma unroll
   for (int e = 0; e < TT; e++) ct[e].store(twl + e * (1 << A), mq[e].q, qr[e], true);
@@ -773,11 +774,13 @@ __device__ __forceinline__ void tile_row(const DevPlan &P, const OcJob &J, uint3
       acc1[i] = mad64(yo[i], eo1[i], acc1[i]);
     }
   }
+  // P: canonical for the inverse row pass; Q: [0, 3q) into (r + q - w) P^-1,
+  // a Shoup product that takes any 32-bit word
   uint32_t r0[4], r1[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    r0[i] = redc64(acc0[i], m);
-    r1[i] = redc64(acc1[i], m);
+    r0[i] = IS_P ? redc64(acc0[i], m) : redc64_lazy(acc0[i], m);
+    r1[i] = IS_P ? redc64(acc1[i], m) : redc64_lazy(acc1[i], m);
   }
   if (IS_P) {
     // ModDown P1 for this special tower: inverse row transforms of both
