@@ -177,6 +177,8 @@ def kernel_source_digest(csrc=None):
 
 
 DEFAULT_CFG = {"schedule": "oc", "tile_towers": 2, "col_width": 16, "row_block": 8, "batch_mode": 1, "batch_order": 1}
+# interleaved timing rounds of the sections that compare configurations
+ROUNDS = 3
 
 
 def timed_calls(fn, reps, torch, warmup=1):
@@ -215,14 +217,24 @@ def batched_rate(ks, tune, tuner, plan, evks, mods, count, reps, np, torch, synt
         # untimed call (clocks and caches settling): five untimed calls each
         s = timed_calls(lambda r=0: plan.keyswitch_batch(jobs(r), workspace=ws), reps, torch, warmup=5)
         del ws
-        return round(count / s, 1)
+        return count / s
     picked = tuner.tune(plan, LEVEL, count)
-    res = {"ciphertexts_per_call": count, "calls": reps, "ks_per_s": rate(None),
+    # the tuned run, the fixed default and every OC configuration are timed in
+    # ROUNDS interleaved rounds and each reports its median, so that a drift
+    # of the device's speed over the section does not favour whichever runs
+    # first (single rounds differed by up to 4 % for the same configuration)
+    cands = [None, DEFAULT_CFG] + [c for c in tune.config_space() if c["schedule"] == "oc"
+                                   and c.get("batch_order", 1) == 1]
+    runs = [[] for _ in cands]
+    for _ in range(ROUNDS):
+        for i, c in enumerate(cands):
+            runs[i].append(rate(c))
+    med = [round(float(np.median(r)), 1) for r in runs]
+    res = {"ciphertexts_per_call": count, "calls": reps, "rounds": ROUNDS, "ks_per_s": med[0],
            "schedule": "auto", "tuned_config": tune.config_key(picked)}
     res["ms_per_call"] = round(1e3 * count / res["ks_per_s"], 4)
-    res["fixed_default"] = {"config": tune.config_key(DEFAULT_CFG), "ks_per_s": rate(DEFAULT_CFG)}
-    res["configs"] = {tune.config_key(c): rate(c) for c in tune.config_space() if c["schedule"] == "oc"
-                      and c.get("batch_order", 1) == 1}
+    res["fixed_default"] = {"config": tune.config_key(DEFAULT_CFG), "ks_per_s": med[1]}
+    res["configs"] = {tune.config_key(c): m for c, m in zip(cands[2:], med[2:])}
     plan.configure("auto")
     return res
 
@@ -504,23 +516,28 @@ def mixed_rate(ks, tune, tuner, dnum, reps, np, torch, synth):
     outs = [torch.empty((2, l + 1, n), dtype=torch.int32, device="cuda") for l in levels]
     jobs = [(evk, l, x, o) for l, x, o in zip(levels, ins, outs)]
     picked = tuner.tune(plan, None, levels=levels, seed=3000 + dnum)
-    res = {"tuned_config": tune.config_key(picked)}
-    for name, cfg, batched in (("oc_batched_tuned", None, True), ("oc_batched_fixed_default", DEFAULT_CFG, True),
-                               ("mp_one_at_a_time", {**DEFAULT_CFG, "schedule": "mp"}, False)):
-        if cfg is None:
-            plan.configure("auto")
-        else:
-            tune.apply_config(plan, cfg)
-        ws = plan.workspace(levels if batched else [max(levels)])
-
-        def once(r=0):
-            if batched:
-                plan.keyswitch_batch(jobs, workspace=ws)
+    res = {"tuned_config": tune.config_key(picked), "rounds": ROUNDS}
+    runs = {}
+    for _ in range(ROUNDS):  # interleaved rounds, median per entry (see batched_rate)
+        for name, cfg, batched in (("oc_batched_tuned", None, True),
+                                   ("oc_batched_fixed_default", DEFAULT_CFG, True),
+                                   ("mp_one_at_a_time", {**DEFAULT_CFG, "schedule": "mp"}, False)):
+            if cfg is None:
+                plan.configure("auto")
             else:
-                for e, l, x, o in jobs:
-                    plan.keyswitch(e, l, x, out=o, workspace=ws)
-        res[name] = round(64 / timed_calls(once, reps, torch, warmup=3), 1)
-        del ws
+                tune.apply_config(plan, cfg)
+            ws = plan.workspace(levels if batched else [max(levels)])
+
+            def once(r=0):
+                if batched:
+                    plan.keyswitch_batch(jobs, workspace=ws)
+                else:
+                    for e, l, x, o in jobs:
+                        plan.keyswitch(e, l, x, out=o, workspace=ws)
+            runs.setdefault(name, []).append(64 / timed_calls(once, reps, torch, warmup=3))
+            del ws
+    for name, r in runs.items():
+        res[name] = round(float(np.median(r)), 1)
     res["tuned_over_mp"] = round(res["oc_batched_tuned"] / res["mp_one_at_a_time"], 3)
     plan.close()
     return res

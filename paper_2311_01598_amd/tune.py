@@ -90,22 +90,30 @@ class Workload:
                                       workspace=ws)
 
 
-def time_config(work, cfg, reps=5):
-    """Median milliseconds per key switch of `work` under configuration `cfg`."""
+def time_config(work, cfg, reps=5, span_ms=1.0):
+    """Median milliseconds per key switch of `work` under configuration `cfg`.
+
+    Each of the `reps` timings covers enough back-to-back calls to span about
+    `span_ms` (at most 32 calls), so that a single key switch of ~0.1 ms is
+    not timed against the resolution and jitter of one event pair."""
     import torch
     plan = work.plan
     apply_config(plan, cfg)
     ws = plan.workspace(work.levels)
     work.run(ws)
     torch.cuda.synchronize()
-    ts = []
-    for _ in range(reps):
+
+    def timed(calls):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        work.run(ws)
+        for _ in range(calls):
+            work.run(ws)
         b.record()
         b.synchronize()
-        ts.append(a.elapsed_time(b) / work.count)
+        return a.elapsed_time(b) / calls
+
+    inner = int(min(32, max(1, np.ceil(span_ms / max(timed(1), 1e-3)))))
+    ts = [timed(inner) / work.count for _ in range(reps)]
     del ws
     return float(np.median(ts))
 
